@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Throughput of the cascaded-biquad filter on one MI355X.
+
+One step = one call of sos_filt over the whole signal: a K = 8 cascade over
+2^28 float32 samples (x ~ N(0, 1), pole radius U[0.8, 0.98], seed 0), FP64
+arithmetic inside the kernel, input already resident in HBM.  Prints one JSON
+line; extra detail (per-solver/N sweep, copy ceiling) goes to stderr and, with
+--out, to a JSON file.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_filter(S, torch, plan, x, y, steps, warmup):
+    """Median-free total over `steps` back-to-back launches, HIP events on the
+    launch stream; returns seconds per step."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        S.filt(plan, x, y, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        S.filt(plan, x, y, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def copy_ceiling(torch, x, y, steps=10):
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / steps
+    return 2 * x.numel() * x.element_size() / t / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--solver", default="auto")
+    ap.add_argument("--N", type=int, default=0)
+    ap.add_argument("--sweep", action="store_true", help="also time PH and CR at every N")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the cascade is filtered on a single "
+              "MI355X; multi-GPU sharding is not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_14054_amd import sosfilt as S
+    from paper_2607_14054_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    n = 1 << args.log2n
+    K = 8
+    sos = W.make_sos(K, 0.8, 0.98, 0)
+    t = time.time()
+    x_np = W.make_signal(n, 0, np.float32)
+    log("generated %d samples in %.1f s" % (n, time.time() - t))
+    x = torch.from_numpy(x_np).to(dev)
+    y = torch.empty_like(x)
+
+    N = args.N or 32
+    plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=args.solver, N=N)
+    info = plan.info()
+    sec = timed_filter(S, torch, plan, x, y, args.steps, args.warmup)
+    gsps = n / sec / 1e9
+    achieved = 8.0 * n / sec / 1e9
+    log("main: N=%d solvers=%s warm=%d  %.3f ms/step  %.1f GS/s  %.0f GB/s"
+        % (N, info.solver, info.warm_samples, sec * 1e3, gsps, achieved))
+    y_np = y.cpu().numpy()
+
+    extra = {"plan": {"N": info.N, "solver": info.solver, "warm_samples": info.warm_samples,
+                      "b0_factored": info.b0_factored}}
+    copy_gbs = copy_ceiling(torch, x, torch.empty_like(x))
+    extra["copy_GBps"] = copy_gbs
+    log("copy ceiling: %.0f GB/s" % copy_gbs)
+
+    if args.sweep:
+        rows = []
+        for solver in ("ph", "cr"):
+            for NN in (8, 16, 32, 64):
+                for cd in ("f64", "f32"):
+                    p2 = S.Plan(sos, io_dtype="f32", compute_dtype=cd, solver=solver, N=NN)
+                    s2 = timed_filter(S, torch, p2, x, y, max(3, args.steps // 2), 2)
+                    rows.append({"solver": solver, "N": NN, "compute": cd,
+                                 "ms": s2 * 1e3, "GSps": n / s2 / 1e9,
+                                 "frac_hbm": 8.0 * n / s2 / 1e9 / HBM_PEAK_GBS})
+                    log("sweep %s N=%2d %s: %.3f ms %.1f GS/s" % (solver, NN, cd, s2 * 1e3, n / s2 / 1e9))
+        extra["sweep"] = rows
+
+    cpu = None
+    accuracy = {}
+    if not args.no_cpu:
+        import oracle
+        threads = 1
+        t = time.time()
+        ref = oracle.sosfilt(x_np, sos)
+        tc = time.time() - t
+        cpu = {"value": n / tc / 1e9, "unit": "GS/s", "cores": threads, "kind": "oracle",
+               "sample": "the full 2^28-sample signal, FP64 direct form I, one thread"}
+        accuracy["rel_rms"] = oracle.rel_rms(y_np, ref)
+        accuracy["max_rel"] = oracle.max_rel(y_np, ref)
+        log("oracle: %.2f s (%.1f MS/s); rel_rms=%.3e max_rel=%.3e"
+            % (tc, n / tc / 1e6, accuracy["rel_rms"], accuracy["max_rel"]))
+        del ref
+
+    line = {
+        "metric": "GS/s filtered (K=8, FP32) + % HBM roofline; forms vs plain at <=1e-4 rel RMS",
+        "value": gsps,
+        "unit": "GS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain cascade, 1 channel x 2^%d float32 samples, K=8, "
+                               "pole radius U[0.8,0.98], seed 0" % args.log2n,
+                   "io_dtype": "f32", "N": info.N, "L": 64, "solver": args.solver},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+        "accuracy": accuracy,
+    }
+    print(json.dumps(line), flush=True)
+    if args.out:
+        extra["line"] = line
+        with open(args.out, "w") as f:
+            json.dump(extra, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+/*
+ * sosfilt.h -- C ABI of the MI355X (gfx950) cascaded-biquad filter library.
+ *
+ * The library filters long signals through a cascade of K second-order
+ * sections (Section II, eq. general_cascaded_equation and eq.
+ * complex_second_order):
+ *
+ *   y_k[n] = b0 x_k[n] + b1 x_k[n-1] + b2 x_k[n-2] - a1 y_k[n-1] - a2 y_k[n-2],
+ *   x_1 = x,  x_k = y_{k-1},  y = y_K,  zero initial state.
+ *
+ * Each group of N*L samples is taken in the stride-N layout of Section V
+ * (lane l of a 64-wide wavefront holds x[m + l N] for block m), which turns
+ * the group into the block-tridiagonal system of eq. multi_block_A.  That
+ * system is solved per section by the PH factorisation (Section VI-B) or by
+ * cyclic reduction (Section VI-C); the permuted layout is kept across all K
+ * sections (Section VII-B), so one permutation and one de-permutation serve
+ * the whole cascade.  Groups inside a tile are chained by the per-section
+ * boundary values (x[-2], x[-1], y[-2], y[-1]) as in Section V; tiles are
+ * chained by the cascade's 2K-dimensional state (see sos_plan_info).
+ *
+ * Conventions for every entry point:
+ *  - "host" pointers are CPU memory; "device" pointers are GPU memory on the
+ *    device current when the call is made.  All arrays are contiguous.
+ *  - Calls never throw; they return a sos_status.  Arguments are checked
+ *    before anything is enqueued: on any error nothing is launched and no
+ *    output is written.
+ *  - Filtering calls are asynchronous on the given HIP stream (NULL = the
+ *    legacy default stream), do not allocate and do not synchronise.
+ *  - A plan is immutable once created and may be used from several threads
+ *    and streams at once; it must outlive all work enqueued with it.
+ */
+#ifndef SOSFILT_H
+#define SOSFILT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sos_plan_s *sos_plan_t;      /* opaque, owned by the caller */
+typedef struct ihipStream_t *sos_stream_t;  /* a hipStream_t */
+
+typedef enum {
+    SOS_OK = 0,
+    SOS_E_ARG = 1,          /* null/invalid pointer, size, aliasing, bad enum */
+    SOS_E_COEF = 2,         /* a0 == 0 or a non-finite coefficient */
+    SOS_E_UNSTABLE = 3,     /* a section with |a2| >= 1 or |a1| >= 1 + a2 (after a0 division) */
+    SOS_E_UNSUPPORTED = 4,  /* N, L, dtype combination or K not built */
+    SOS_E_DEVICE = 5,       /* a HIP call failed (no device, launch error) */
+    SOS_E_NOMEM = 6         /* host or device allocation failed (plan creation only) */
+} sos_status;
+
+typedef enum { SOS_F32 = 0, SOS_F64 = 1 } sos_dtype;
+
+typedef enum {
+    SOS_AUTO = 0,   /* cyclic reduction, with PH for sections the CR guard rejects */
+    SOS_PH = 1,     /* PH factorisation (Section VI-B) for every section */
+    SOS_CR = 2      /* cyclic reduction (Section VI-C), guard still applies */
+} sos_solver;
+
+/* Plan flags. */
+#define SOS_FLAG_HOST_ONLY 0x1u   /* build the FP64 host tables only; the plan
+                                     can be queried but not used to filter */
+
+typedef struct {
+    int32_t io_dtype;       /* sos_dtype of x and y (default SOS_F32) */
+    int32_t compute_dtype;  /* sos_dtype of the in-kernel arithmetic (default SOS_F64) */
+    int32_t solver;         /* sos_solver (default SOS_AUTO) */
+    int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32) */
+    int32_t L;              /* samples per block = lanes: 64 (0 = 64) */
+    int32_t tile_groups;    /* groups per tile (0 = chosen per call from n) */
+    uint32_t flags;         /* SOS_FLAG_* */
+} sos_opts;
+
+/* Limits. */
+#define SOS_MAX_SECTIONS 64
+
+/*
+ * sos_plan -- validate coefficients and build the per-section tables.
+ *
+ * sos   host, [K][6] row-major float64, rows (b0, b1, b2, a0, a1, a2) as in
+ *       eq. complex_second_order with the denominator a0 + a1 z^-1 + a2 z^-2.
+ *       Each row is divided by its a0 (a0 = 0 -> SOS_E_COEF).  If every b0 is
+ *       nonzero and the running products of 1/b0 stay within range, b0 is
+ *       factored out as in eq. simple_second_order and the product of the b0
+ *       is applied once at the store.  Copied; the caller may free it.
+ * K     1..SOS_MAX_SECTIONS.
+ * opts  host, may be NULL for the defaults.
+ * out   host, receives the plan handle (unchanged on error).
+ *
+ * Tables (FP64 on the host, converted to the compute dtype on the device):
+ * u_{1,m}, u_{2,m} (Section VI-A), the matrix C of eq. C and the powers of
+ * -C used by the terminal-block scan (Section VI-B), the cyclic-reduction
+ * coefficients of eq. cr_coeff_update per level (f/e, e, c, d) and the
+ * terminal-block coefficients of eq. cr_terminal_block, and the cascade's
+ * one-step state transition (2K x 2K).  The cyclic-reduction guard runs
+ * here: a level whose r^(2^i) < 2^-60 is flushed to zero coupling; a section
+ * with any |f/e|, |c| or |d| above 64 at a remaining level is solved with PH
+ * (reported by sos_plan_query).  No division happens on the device.
+ */
+sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan_t *out);
+
+/* Release the plan and its device tables.  NULL is accepted. */
+sos_status sos_plan_destroy(sos_plan_t plan);
+
+typedef struct {
+    int32_t K, N, L;
+    int32_t io_dtype, compute_dtype;
+    int32_t b0_factored;        /* 1 if the b0 of every section was factored out */
+    int64_t warm_samples;       /* W: samples of run-in that make a tile's carry-in
+                                   state exact to the working precision (a multiple of N*L) */
+    double gain;                /* product of the b0 applied at the store (1 if not factored) */
+    double transition_norm_W;   /* infinity norm of the cascade state transition over W samples */
+} sos_plan_info;
+
+/* info        host, filled in.
+ * solver      host [K] or NULL: per section SOS_PH or SOS_CR as run. */
+sos_status sos_plan_query(sos_plan_t plan, sos_plan_info *info, int32_t *solver);
+
+/* Host FP64 tables, for inspection and tests.  Copies min(count, size) values
+ * into out (host) and returns the table's size in *size (host, may be NULL).
+ * section is ignored for SOS_TABLE_TRANSITION. */
+typedef enum {
+    SOS_TABLE_ROWS = 0,        /* 5: b0 b1 b2 a1 a2 as the kernel uses them */
+    SOS_TABLE_U1 = 1,          /* N: u_{1,m} */
+    SOS_TABLE_U2 = 2,          /* N: u_{2,m} */
+    SOS_TABLE_C = 3,           /* 4: e g f d (eq. C), row-major */
+    SOS_TABLE_PH_POWERS = 4,   /* 4 log2 L: (-C)^(2^j), row-major, j = 0.. */
+    SOS_TABLE_CR_LEVELS = 5,   /* 4 log2 N: per level f/e, e, c, d */
+    SOS_TABLE_CR_TERMINAL = 6, /* 2: e, f of eq. cr_terminal_block */
+    SOS_TABLE_CR_POWERS = 7,   /* 4 log2 L: T^(2^j), T = [[0, 1], [-f, -e]] */
+    SOS_TABLE_TRANSITION = 8   /* (2K)^2: one-step cascade state transition, row-major */
+} sos_table;
+
+sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
+                          double *out, int32_t count, int32_t *size);
+
+/* Device workspace bytes sos_filt needs for n samples (0 at present). */
+size_t sos_workspace_size(sos_plan_t plan, int64_t n);
+
+/*
+ * sos_filt -- y = cascade(x), zero initial state.
+ *
+ * x, y       device, n samples of the plan's io_dtype; must not overlap
+ *            (SOS_E_ARG): tiles re-read input that precedes them.
+ * n          >= 0; n == 0 is a no-op.  Any n is accepted: the last group is
+ *            zero-padded and only n outputs are written.
+ * workspace  device, sos_workspace_size bytes (may be NULL when that is 0).
+ * stream     HIP stream the kernels are enqueued on.
+ */
+sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
+                    void *workspace, sos_stream_t stream);
+
+const char *sos_status_string(sos_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOSFILT_H */

@@ -1,0 +1,53 @@
+// Internal plan structure and the per-section coefficient table layout that
+// the host plan writes and the kernels read.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/sosfilt.h"
+
+namespace sosf {
+
+constexpr int kLanes = 64;       // wavefront width = block size L
+constexpr int kLogLanes = 6;
+constexpr int kMaxLevels = 10;   // log2 of the largest N the tables hold
+
+// Offsets (in elements of the compute dtype) inside one section's row of the
+// device table.  Row length = tab_stride(N).
+enum : int {
+  OFF_B0 = 0, OFF_B1 = 1, OFF_B2 = 2, OFF_A1 = 3, OFF_A2 = 4,
+  OFF_PH_POW = 8,                              // 6 x 4: (-C)^(2^j)
+  OFF_CR_POW = OFF_PH_POW + 4 * kLogLanes,     // 6 x 4: T^(2^j)
+  OFF_CR_LVL = OFF_CR_POW + 4 * kLogLanes,     // 10 x 4: f/e, e, c, d
+  OFF_U1 = OFF_CR_LVL + 4 * kMaxLevels,        // N
+};
+inline int off_u2(int N) { return OFF_U1 + N; }
+inline int tab_stride(int N) { return (OFF_U1 + 2 * N + 7) & ~7; }
+
+}  // namespace sosf
+
+struct sos_plan_s {
+  int K = 0, N = 0, L = 0, lgN = 0;
+  int io_dtype = SOS_F32, compute_dtype = SOS_F64, solver_opt = SOS_AUTO;
+  int tile_groups = 0;
+  uint32_t flags = 0;
+  bool b0_factored = false;
+  double gain = 1.0;
+  std::vector<double> rows;        // K x 5: b0 b1 b2 a1 a2 as the kernel uses them
+  std::vector<int32_t> solver;     // K: SOS_PH or SOS_CR
+  std::vector<double> C;           // K x 4
+  std::vector<double> cr_term;     // K x 2: e, f at the terminal level
+  std::vector<double> table;       // K x stride, FP64 master copy of the device table
+  int stride = 0;
+  std::vector<double> phi;         // (2K)^2 one-step cascade state transition
+  int64_t warm = 0;                // run-in samples, multiple of N*L
+  double warm_norm = 0.0;
+  int device = -1;
+  void *d_table = nullptr;         // device copy in the compute dtype
+  void *d_solver = nullptr;        // device int8 per section: 1 = PH, 2 = CR
+};
+
+namespace sosf {
+sos_status build_plan_tables(sos_plan_s &p, const double *sos);
+}

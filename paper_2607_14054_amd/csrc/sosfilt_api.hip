@@ -1,0 +1,230 @@
+// C ABI entry points (include/sosfilt.h): plan creation and upload, queries,
+// and the launch of the tile kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace sosf;
+
+namespace {
+
+bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+sos_status upload(sos_plan_s &p) {
+  if (hipGetDevice(&p.device) != hipSuccess) return SOS_E_DEVICE;
+  const size_t count = (size_t)p.K * p.stride;
+  const size_t esz = p.compute_dtype == SOS_F64 ? 8 : 4;
+  if (hipMalloc(&p.d_table, count * esz) != hipSuccess) { p.d_table = nullptr; return SOS_E_NOMEM; }
+  if (hipMalloc(&p.d_solver, (size_t)p.K * sizeof(int32_t)) != hipSuccess) {
+    hipFree(p.d_table);
+    p.d_table = nullptr;
+    p.d_solver = nullptr;
+    return SOS_E_NOMEM;
+  }
+  hipError_t e1, e2;
+  if (esz == 8) {
+    e1 = hipMemcpy(p.d_table, p.table.data(), count * 8, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> f(count);
+    for (size_t i = 0; i < count; ++i) f[i] = (float)p.table[i];
+    e1 = hipMemcpy(p.d_table, f.data(), count * 4, hipMemcpyHostToDevice);
+  }
+  e2 = hipMemcpy(p.d_solver, p.solver.data(), (size_t)p.K * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (e1 != hipSuccess || e2 != hipSuccess) return SOS_E_DEVICE;
+  return SOS_OK;
+}
+
+struct Ptrs {
+  const void *x;
+  void *y;
+  const void *tab;
+  const int32_t *solver;
+};
+
+template <int N, typename TI, typename T>
+sos_status launch_n(const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s) {
+  const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const TI *x = static_cast<const TI *>(q.x);
+  TI *y = static_cast<TI *>(q.y);
+  const T *tab = static_cast<const T *>(q.tab);
+  if (b0one)
+    hipLaunchKernelGGL((sos_tiles_kernel<N, TI, T, true>), dim3((unsigned)blocks),
+                       dim3(kWavesPerBlock * 64), 0, s, x, y, tab, q.solver, a);
+  else
+    hipLaunchKernelGGL((sos_tiles_kernel<N, TI, T, false>), dim3((unsigned)blocks),
+                       dim3(kWavesPerBlock * 64), 0, s, x, y, tab, q.solver, a);
+  return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+}
+
+template <typename TI, typename T>
+sos_status launch_t(int N, const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s) {
+  switch (N) {
+    case 8: return launch_n<8, TI, T>(q, a, b0one, s);
+    case 16: return launch_n<16, TI, T>(q, a, b0one, s);
+    case 32: return launch_n<32, TI, T>(q, a, b0one, s);
+    case 64: return launch_n<64, TI, T>(q, a, b0one, s);
+    default: return SOS_E_UNSUPPORTED;
+  }
+}
+
+// Tile length for n samples: long enough that the run-in costs at most
+// about 1/16 of the tile, short enough to give the chip enough wavefronts.
+int64_t choose_tile(const sos_plan_s &p, int64_t n) {
+  const int64_t NL = (int64_t)p.N * kLanes;
+  const int64_t groups = (n + NL - 1) / NL;
+  if (p.tile_groups > 0) return (int64_t)p.tile_groups * NL;
+  const int64_t gw = p.warm / NL;
+  int64_t tg = std::max<int64_t>(16 * gw, 8);
+  const int64_t want_tiles = 4096;
+  const int64_t tg_par = std::max<int64_t>(groups / want_tiles, 1);
+  if (tg_par < tg) tg = std::max<int64_t>(tg_par, std::max<int64_t>(4 * gw, 4));
+  return tg * NL;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sos_status_string(sos_status s) {
+  switch (s) {
+    case SOS_OK: return "ok";
+    case SOS_E_ARG: return "invalid argument";
+    case SOS_E_COEF: return "invalid coefficients (a0 == 0 or non-finite)";
+    case SOS_E_UNSTABLE: return "unstable section (a pole on or outside the unit circle)";
+    case SOS_E_UNSUPPORTED: return "unsupported configuration";
+    case SOS_E_DEVICE: return "HIP device error";
+    case SOS_E_NOMEM: return "out of memory";
+  }
+  return "unknown status";
+}
+
+sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan_t *out) {
+  if (!sos || !out || K < 1 || K > SOS_MAX_SECTIONS) return SOS_E_ARG;
+  sos_opts o{SOS_F32, SOS_F64, SOS_AUTO, 0, 0, 0, 0};
+  if (opts) o = *opts;
+  if (o.N == 0) o.N = 32;
+  if (o.L == 0) o.L = 64;
+  if (o.io_dtype != SOS_F32 && o.io_dtype != SOS_F64) return SOS_E_ARG;
+  if (o.compute_dtype != SOS_F32 && o.compute_dtype != SOS_F64) return SOS_E_ARG;
+  if (o.solver < SOS_AUTO || o.solver > SOS_CR) return SOS_E_ARG;
+  if (o.tile_groups < 0) return SOS_E_ARG;
+  if (!pow2_in(o.N, 8, 64) || o.L != 64) return SOS_E_UNSUPPORTED;
+  if (o.io_dtype == SOS_F64 && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
+  sos_plan_s *p = new (std::nothrow) sos_plan_s;
+  if (!p) return SOS_E_NOMEM;
+  p->K = K;
+  p->N = o.N;
+  p->L = o.L;
+  p->lgN = __builtin_ctz((unsigned)o.N);
+  p->io_dtype = o.io_dtype;
+  p->compute_dtype = o.compute_dtype;
+  p->solver_opt = o.solver;
+  p->tile_groups = o.tile_groups;
+  p->flags = o.flags;
+  sos_status st = build_plan_tables(*p, sos);
+  if (st == SOS_OK && !(o.flags & SOS_FLAG_HOST_ONLY)) st = upload(*p);
+  if (st != SOS_OK) {
+    sos_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return SOS_OK;
+}
+
+sos_status sos_plan_destroy(sos_plan_t p) {
+  if (!p) return SOS_OK;
+  if (p->d_table || p->d_solver) {
+    int cur = -1;
+    hipGetDevice(&cur);
+    if (p->device >= 0 && cur != p->device) hipSetDevice(p->device);
+    if (p->d_table) hipFree(p->d_table);
+    if (p->d_solver) hipFree(p->d_solver);
+    if (p->device >= 0 && cur >= 0 && cur != p->device) hipSetDevice(cur);
+  }
+  delete p;
+  return SOS_OK;
+}
+
+sos_status sos_plan_query(sos_plan_t p, sos_plan_info *info, int32_t *solver) {
+  if (!p) return SOS_E_ARG;
+  if (info) {
+    info->K = p->K;
+    info->N = p->N;
+    info->L = p->L;
+    info->io_dtype = p->io_dtype;
+    info->compute_dtype = p->compute_dtype;
+    info->b0_factored = p->b0_factored ? 1 : 0;
+    info->warm_samples = p->warm;
+    info->gain = p->gain;
+    info->transition_norm_W = p->warm_norm;
+  }
+  if (solver)
+    for (int k = 0; k < p->K; ++k) solver[k] = p->solver[k];
+  return SOS_OK;
+}
+
+sos_status sos_plan_table(sos_plan_t p, int32_t table, int32_t section, double *out,
+                          int32_t count, int32_t *size) {
+  if (!p || count < 0 || (count > 0 && !out)) return SOS_E_ARG;
+  if (table != SOS_TABLE_TRANSITION && (section < 0 || section >= p->K)) return SOS_E_ARG;
+  const double *t = p->table.data() + (size_t)(section < 0 ? 0 : section) * p->stride;
+  std::vector<double> buf;
+  switch (table) {
+    case SOS_TABLE_ROWS: buf.assign(p->rows.begin() + 5 * section, p->rows.begin() + 5 * section + 5); break;
+    case SOS_TABLE_U1: buf.assign(t + OFF_U1, t + OFF_U1 + p->N); break;
+    case SOS_TABLE_U2: buf.assign(t + off_u2(p->N), t + off_u2(p->N) + p->N); break;
+    case SOS_TABLE_C: buf.assign(p->C.begin() + 4 * section, p->C.begin() + 4 * section + 4); break;
+    case SOS_TABLE_PH_POWERS: buf.assign(t + OFF_PH_POW, t + OFF_PH_POW + 4 * kLogLanes); break;
+    case SOS_TABLE_CR_LEVELS: buf.assign(t + OFF_CR_LVL, t + OFF_CR_LVL + 4 * p->lgN); break;
+    case SOS_TABLE_CR_TERMINAL: buf.assign(p->cr_term.begin() + 2 * section, p->cr_term.begin() + 2 * section + 2); break;
+    case SOS_TABLE_CR_POWERS: buf.assign(t + OFF_CR_POW, t + OFF_CR_POW + 4 * kLogLanes); break;
+    case SOS_TABLE_TRANSITION: buf = p->phi; break;
+    default: return SOS_E_ARG;
+  }
+  if (size) *size = (int32_t)buf.size();
+  const size_t c = std::min<size_t>((size_t)count, buf.size());
+  if (c) std::memcpy(out, buf.data(), c * sizeof(double));
+  return SOS_OK;
+}
+
+size_t sos_workspace_size(sos_plan_t p, int64_t n) {
+  (void)p;
+  (void)n;
+  return 0;
+}
+
+sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *workspace,
+                    sos_stream_t stream) {
+  (void)workspace;
+  if (!p || n < 0) return SOS_E_ARG;
+  if (n == 0) return SOS_OK;
+  if (!x || !y) return SOS_E_ARG;
+  if (!p->d_table) return SOS_E_ARG;   // a host-only plan cannot filter
+  const size_t esz = p->io_dtype == SOS_F64 ? 8 : 4;
+  const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y;
+  if (xb < yb + (uintptr_t)n * esz && yb < xb + (uintptr_t)n * esz) return SOS_E_ARG;   // overlap
+  if ((xb | yb) & 15) return SOS_E_ARG;   // 16-byte vector access
+  Ptrs q{x, y, p->d_table, static_cast<const int32_t *>(p->d_solver)};
+  FiltArgs a;
+  a.n = n;
+  a.K = p->K;
+  a.stride = p->stride;
+  a.tile = choose_tile(*p, n);
+  a.warm = p->warm;
+  a.ntiles = (n + a.tile - 1) / a.tile;
+  a.gain = p->gain;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const bool b0one = p->b0_factored;
+  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F32) return launch_t<float, float>(p->N, q, a, b0one, s);
+  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F64) return launch_t<float, double>(p->N, q, a, b0one, s);
+  if (p->io_dtype == SOS_F64 && p->compute_dtype == SOS_F64) return launch_t<double, double>(p->N, q, a, b0one, s);
+  return SOS_E_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+"""Python binding of libsosfilt.so (include/sosfilt.h), argument marshalling only.
+
+Every step of the filter runs in the HIP kernels behind the C ABI; this module
+only turns numpy arrays and torch tensors into pointers, sizes and a stream.
+There is no fallback: if the library is missing, importing the binding's
+entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsosfilt.so")
+
+SOS_OK, SOS_E_ARG, SOS_E_COEF, SOS_E_UNSTABLE, SOS_E_UNSUPPORTED, SOS_E_DEVICE, SOS_E_NOMEM = range(7)
+SOS_F32, SOS_F64 = 0, 1
+SOS_AUTO, SOS_PH, SOS_CR = 0, 1, 2
+SOS_FLAG_HOST_ONLY = 0x1
+(SOS_TABLE_ROWS, SOS_TABLE_U1, SOS_TABLE_U2, SOS_TABLE_C, SOS_TABLE_PH_POWERS,
+ SOS_TABLE_CR_LEVELS, SOS_TABLE_CR_TERMINAL, SOS_TABLE_CR_POWERS, SOS_TABLE_TRANSITION) = range(9)
+
+EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table",
+            "sos_workspace_size", "sos_filt", "sos_status_string"]
+
+_DTYPES = {"f32": SOS_F32, "f64": SOS_F64, np.float32: SOS_F32, np.float64: SOS_F64}
+_SOLVERS = {"auto": SOS_AUTO, "ph": SOS_PH, "cr": SOS_CR}
+
+
+class SosError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        super().__init__("%s: %s (status %d)" % (what, status_string(code), code))
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("io_dtype", ctypes.c_int32), ("compute_dtype", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("N", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("tile_groups", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("N", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("io_dtype", ctypes.c_int32), ("compute_dtype", ctypes.c_int32),
+                ("b0_factored", ctypes.c_int32), ("warm_samples", ctypes.c_int64),
+                ("gain", ctypes.c_double), ("transition_norm_W", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsosfilt.so is not built (python -m paper_2607_14054_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.sos_plan.argtypes = [ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(_Opts), ctypes.POINTER(vp)]
+        L.sos_plan_destroy.argtypes = [vp]
+        L.sos_plan_query.argtypes = [vp, ctypes.POINTER(_Info), ctypes.POINTER(ctypes.c_int32)]
+        L.sos_plan_table.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(ctypes.c_int32)]
+        L.sos_workspace_size.argtypes = [vp, i64]
+        L.sos_workspace_size.restype = ctypes.c_size_t
+        L.sos_filt.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.sos_status_string.argtypes = [ctypes.c_int]
+        L.sos_status_string.restype = ctypes.c_char_p
+        for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().sos_status_string(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != SOS_OK:
+        raise SosError(code, what)
+
+
+@dataclass
+class PlanInfo:
+    K: int
+    N: int
+    L: int
+    io_dtype: str
+    compute_dtype: str
+    b0_factored: bool
+    warm_samples: int
+    gain: float
+    transition_norm_W: float
+    solver: list
+
+
+class Plan:
+    """Owns a sos_plan_t.  sos: [K, 6] rows (b0, b1, b2, a0, a1, a2)."""
+
+    def __init__(self, sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=0,
+                 tile_groups=0, host_only=False):
+        s = np.ascontiguousarray(np.asarray(sos, dtype=np.float64))
+        if s.ndim != 2 or s.shape[1] != 6:
+            raise ValueError("sos must be [K, 6]")
+        o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), 64,
+                  int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0)
+        h = ctypes.c_void_p()
+        _check(lib().sos_plan(s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), s.shape[0],
+                              ctypes.byref(o), ctypes.byref(h)), "sos_plan")
+        self._h = h
+        self.K = s.shape[0]
+        self.io_dtype = io_dtype if isinstance(io_dtype, str) else ("f32" if io_dtype == np.float32 else "f64")
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sos_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> PlanInfo:
+        inf = _Info()
+        sol = (ctypes.c_int32 * self.K)()
+        _check(lib().sos_plan_query(self._h, ctypes.byref(inf), sol), "sos_plan_query")
+        names = {SOS_PH: "ph", SOS_CR: "cr"}
+        return PlanInfo(inf.K, inf.N, inf.L, "f32" if inf.io_dtype == SOS_F32 else "f64",
+                        "f32" if inf.compute_dtype == SOS_F32 else "f64", bool(inf.b0_factored),
+                        int(inf.warm_samples), float(inf.gain), float(inf.transition_norm_W),
+                        [names[int(v)] for v in sol])
+
+    def table(self, which: int, section: int = 0) -> np.ndarray:
+        size = ctypes.c_int32()
+        _check(lib().sos_plan_table(self._h, which, section, None, 0, ctypes.byref(size)), "sos_plan_table")
+        out = np.zeros(size.value, dtype=np.float64)
+        _check(lib().sos_plan_table(self._h, which, section,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    size.value, None), "sos_plan_table")
+        return out
+
+    def workspace_size(self, n: int) -> int:
+        return int(lib().sos_workspace_size(self._h, int(n)))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def filt(plan: Plan, x, y=None, stream=None):
+    """y = cascade(x) for a 1-D CUDA (HIP) tensor x of the plan's io dtype."""
+    import torch
+    want = torch.float32 if plan.io_dtype == "f32" else torch.float64
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == want and x.dim() == 1):
+        raise ValueError("x must be a 1-D device tensor of dtype %s" % want)
+    x = x.contiguous()
+    if y is None:
+        y = torch.empty_like(x)
+    if not (y.is_cuda and y.dtype == want and y.shape == x.shape and y.is_contiguous()):
+        raise ValueError("y must be a contiguous device tensor like x")
+    n = x.numel()
+    ws = plan.workspace_size(n)
+    wsb = torch.empty(ws, dtype=torch.uint8, device=x.device) if ws else None
+    _check(lib().sos_filt(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                          n, ctypes.c_void_p(wsb.data_ptr()) if wsb is not None else None,
+                          _stream_ptr(stream)), "sos_filt")
+    return y

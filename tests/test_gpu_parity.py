@@ -1,0 +1,164 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances (relative RMS against the FP64 oracle, per channel):
+* FP64 in/out, FP64 arithmetic: 1e-12 on the r <= 0.95 draws (the oracle's
+  own error against extended precision is ~5e-13 there).
+* FP32 in/out, FP64 arithmetic: 1e-6 (output rounding to FP32 is ~6e-8
+  relative; the run-in truncation is below 2^-50).
+* FP32 in/out, FP32 arithmetic: reported against the plain FP32 sequential
+  cascade on the same draw (the FP32 floor), within a factor of 8 of it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_14054_amd import sosfilt as S
+from paper_2607_14054_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def run(sos, x_np, **kw):
+    io = "f64" if x_np.dtype == np.float64 else "f32"
+    p = S.Plan(sos, io_dtype=io, **kw)
+    x = torch.from_numpy(x_np).to(dev())
+    y = S.filt(p, x)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), p
+
+
+@pytest.mark.parametrize("solver", ["ph", "cr"])
+@pytest.mark.parametrize("N", [8, 16, 32, 64])
+def test_tiny_config_f64(solver, N):
+    c = W.CONFIGS["tiny"]
+    sos = W.make_sos(c.K, c.r_lo, c.r_hi, c.seed)
+    x = W.make_signal(c.n, c.seed, np.float64)
+    y, p = run(sos, x, compute_dtype="f64", solver=solver, N=N)
+    ref = oracle.sosfilt(x, sos)
+    err = oracle.rel_rms(y, ref)
+    print("tiny f64 %s N=%d rel_rms=%.3e solvers=%s" % (solver, N, err, p.info().solver))
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("solver", ["ph", "cr"])
+@pytest.mark.parametrize("N", [8, 32])
+def test_f32_io_f64_compute(solver, N):
+    sos = W.make_sos(8, 0.8, 0.98, 0)
+    x = W.make_signal(2 ** 20 + 12345, 0, np.float32)       # ragged tail, many tiles
+    y, p = run(sos, x, compute_dtype="f64", solver=solver, N=N, tile_groups=8)
+    err = oracle.rel_rms(y, oracle.sosfilt(x, sos))
+    print("f32io/f64 %s N=%d rel_rms=%.3e warm=%d" % (solver, N, err, p.info().warm_samples))
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("solver", ["ph", "cr"])
+def test_f32_arithmetic_near_fp32_floor(solver):
+    sos = W.make_sos(8, 0.5, 0.95, 0)
+    x = W.make_signal(2 ** 18, 0, np.float32)
+    y, _ = run(sos, x, compute_dtype="f32", solver=solver, N=16)
+    ref = oracle.sosfilt(x, sos)
+    err = oracle.rel_rms(y, ref)
+    floor = oracle.rel_rms(oracle.sosfilt_f32arith(x, sos), ref)
+    print("f32 arithmetic %s rel_rms=%.3e floor=%.3e" % (solver, err, floor))
+    assert err < 8 * floor + 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 511, 512, 513, 2047, 2049, 100003])
+def test_ragged_lengths(n):
+    sos = W.make_sos(4, 0.5, 0.95, 9)
+    x = W.make_signal(n, 3, np.float64)
+    for solver in ("ph", "cr"):
+        y, _ = run(sos, x, compute_dtype="f64", solver=solver, N=8, tile_groups=2)
+        assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12, (n, solver)
+
+
+def test_zero_length_is_noop():
+    p = S.Plan(W.make_sos(2, 0.5, 0.9, 1), io_dtype="f32")
+    x = torch.zeros(0, dtype=torch.float32, device=dev())
+    y = S.filt(p, x)
+    assert y.numel() == 0
+
+
+@pytest.mark.parametrize("K", [1, 2, 16])
+def test_section_counts(K):
+    sos = W.make_sos(K, 0.5, 0.95, 11)
+    x = W.make_signal(50000, 4, np.float64)
+    y, _ = run(sos, x, compute_dtype="f64", N=16, tile_groups=4)
+    assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12
+
+
+@pytest.mark.parametrize("offset", [-2, -1, 0, 1])
+def test_impulse_across_tile_boundary(offset):
+    """An impulse just before/after a tile boundary reproduces the oracle's
+    impulse response across the boundary (run-in carry)."""
+    sos = W.make_sos(8, 0.5, 0.95, 13)
+    N, tg = 8, 4
+    tile = N * 64 * tg
+    n = 6 * tile
+    x = np.zeros(n)
+    x[3 * tile + offset] = 1.0
+    y, _ = run(sos, x, compute_dtype="f64", solver="cr", N=N, tile_groups=tg)
+    ref = oracle.sosfilt(x, sos)
+    assert np.max(np.abs(y - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("theta", [math.pi / 2, math.pi / 4, math.pi / 8, math.pi / 2 + 1e-4])
+def test_cr_hazard_angles(theta):
+    """Angles where e^(i) of cyclic reduction vanishes or nearly does: the
+    plan's guard must route these sections to PH and the result stay exact."""
+    r = 0.95
+    sec = np.array([[1.0, 0.3, 0.2, 1.0, -2 * r * math.cos(theta), r * r]])
+    sos = np.vstack([sec, W.make_sos(2, 0.5, 0.9, 17)])
+    x = W.make_signal(40000, 5, np.float64)
+    y, p = run(sos, x, compute_dtype="f64", solver="cr", N=64)
+    assert p.info().solver[0] == "ph"
+    assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12
+
+
+def test_unfactored_b0():
+    sos = W.make_sos(4, 0.5, 0.95, 19)
+    sos[2, 0:3] = [0.0, 0.7, -0.2]
+    x = W.make_signal(30000, 6, np.float64)
+    y, p = run(sos, x, compute_dtype="f64", N=32)
+    assert not p.info().b0_factored
+    assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12
+
+
+def test_slow_pole_long_run_in():
+    """r = 0.9995: the run-in spans many tiles."""
+    r, th = 0.9995, 0.01
+    sec = np.array([[1.0, 0.0, 0.0, 1.0, -2 * r * math.cos(th), r * r]])
+    x = W.make_signal(2 ** 19, 7, np.float64)
+    y, p = run(sec, x, compute_dtype="f64", N=8, tile_groups=4)
+    assert p.info().warm_samples > 4 * 8 * 64
+    assert oracle.rel_rms(y, oracle.sosfilt(x, sec)) < 1e-11
+
+
+def test_bad_arguments_rejected():
+    p = S.Plan(W.make_sos(2, 0.5, 0.9, 1), io_dtype="f32")
+    x = torch.zeros(4096, dtype=torch.float32, device=dev())
+    import ctypes
+    lib = S.lib()
+    # overlapping input and output
+    rc = lib.sos_filt(p.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr() + 64),
+                      4096, None, None)
+    assert rc == S.SOS_E_ARG
+    rc = lib.sos_filt(p.handle, None, ctypes.c_void_p(x.data_ptr()), 16, None, None)
+    assert rc == S.SOS_E_ARG
+    rc = lib.sos_filt(p.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(x.data_ptr()), -1, None, None)
+    assert rc == S.SOS_E_ARG
+    host = S.Plan(W.make_sos(2, 0.5, 0.9, 1), host_only=True)
+    y = torch.zeros(4096, dtype=torch.float32, device=dev())
+    rc = lib.sos_filt(host.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), 16, None, None)
+    assert rc == S.SOS_E_ARG
