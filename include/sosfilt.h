@@ -8,9 +8,11 @@
  *   y_k[n] = b0 x_k[n] + b1 x_k[n-1] + b2 x_k[n-2] - a1 y_k[n-1] - a2 y_k[n-2],
  *   x_1 = x,  x_k = y_{k-1},  y = y_K,  zero initial state.
  *
- * Each group of N*L samples is taken in the stride-N layout of Section V
- * (lane l of a 64-wide wavefront holds x[m + l N] for block m), which turns
- * the group into the block-tridiagonal system of eq. multi_block_A.  That
+ * Each group of N*L samples (L = 16) is taken in the stride-N layout of
+ * Section V: lane l of a 16-lane DPP row holds x[m + l N] for block m, and a
+ * 64-wide wavefront carries four such groups from four different tiles.
+ * This turns each group into the block-tridiagonal system of eq.
+ * multi_block_A.  That
  * system is solved per section by the PH factorisation (Section VI-B) or by
  * cyclic reduction (Section VI-C); the permuted layout is kept across all K
  * sections (Section VII-B), so one permutation and one de-permutation serve
@@ -69,7 +71,7 @@ typedef struct {
     int32_t compute_dtype;  /* sos_dtype of the in-kernel arithmetic (default SOS_F64) */
     int32_t solver;         /* sos_solver (default SOS_AUTO) */
     int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32) */
-    int32_t L;              /* samples per block = lanes: 64 (0 = 64) */
+    int32_t L;              /* samples per block = lanes of a DPP row: 16 (0 = 16) */
     int32_t tile_groups;    /* groups per tile (0 = chosen per call from n) */
     uint32_t flags;         /* SOS_FLAG_* */
 } sos_opts;
@@ -127,10 +129,10 @@ typedef enum {
     SOS_TABLE_U1 = 1,          /* N: u_{1,m} */
     SOS_TABLE_U2 = 2,          /* N: u_{2,m} */
     SOS_TABLE_C = 3,           /* 4: e g f d (eq. C), row-major */
-    SOS_TABLE_PH_POWERS = 4,   /* 4 log2 L: (-C)^(2^j), row-major, j = 0.. */
+    SOS_TABLE_PH_POWERS = 4,   /* 4 log2 L = 16: (-C)^(2^j), row-major, j = 0..3 */
     SOS_TABLE_CR_LEVELS = 5,   /* 4 log2 N: per level f/e, e, c, d */
     SOS_TABLE_CR_TERMINAL = 6, /* 2: e, f of eq. cr_terminal_block */
-    SOS_TABLE_CR_POWERS = 7,   /* 4 log2 L: T^(2^j), T = [[0, 1], [-f, -e]] */
+    SOS_TABLE_CR_POWERS = 7,   /* 4 log2 L = 16: T^(2^j), T = [[0, 1], [-f, -e]] */
     SOS_TABLE_TRANSITION = 8   /* (2K)^2: one-step cascade state transition, row-major */
 } sos_table;
 

@@ -1,12 +1,18 @@
-// Device code: one 64-wide wavefront filters one tile of the signal through
-// all K sections, one signal block group of N*64 samples at a time.
+// Device code: the multi-block filter on 16-lane DPP rows.
 //
-// Layout (Section V): lane l holds the l-th run of N consecutive samples of
-// the group in registers X[0..N-1], i.e. X[m] on lane l is x[m + l N], the
-// l-th element of the stride-N block xbar_m.  A lane shift by one (lane l
-// receives lane l-1, lane 0 receives a fill value) is the shift matrix R.
-// The layout is kept across all K sections (Section VII-B): one
-// permutation on load, one de-permutation on store.
+// Layout (Section V, with block size L = 16): a 64-wide wavefront holds four
+// independent signal block groups, one per DPP row of 16 lanes.  In row r,
+// lane l (0..15) holds the l-th run of N consecutive samples of that row's
+// group in registers X[0..N-1]; X[m] on lane l is x[m + l N], the l-th
+// element of the stride-N block xbar_m.  Moving a register one lane down
+// inside the row (lane l receives lane l-1, lane 0 a fill value) is the
+// shift matrix R.  Every cross-lane step is a DPP row operation.  The layout
+// is kept across all K sections (Section VII-B): one permutation when a
+// group is loaded, one de-permutation when it is stored.
+//
+// The four rows of a wavefront work on four different tiles of the signal,
+// so nothing couples them; groups inside a tile are chained through each
+// section's boundary values (x[-2], x[-1], y[-2], y[-1]), kept per row in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,153 +20,186 @@
 
 #include "plan.hpp"
 
+#ifndef SOSF_SCHED_CHUNK
+#define SOSF_SCHED_CHUNK 4
+#endif
+
 namespace sosf {
 
 // ------------------------------------------------------------ lane moves
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
+__device__ __forceinline__ int row_lane() { return (int)(threadIdx.x & 15); }
 
-// R applied to a register: out[l] = v[l-1], out[0] = fill.  DPP wave_shr:1
-// with bound_ctrl writes 0 into lane 0; the fill is merged afterwards.
-__device__ __forceinline__ float shift_r(float v, float fill) {
-  int r = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true);
-  return lane_id() == 0 ? fill : __int_as_float(r);
+// DPP controls (GFX9 encoding): row_shr:d = 0x110 + d, row_newbcast:15 = 0x15f.
+template <int CTRL, bool ZERO>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, ZERO));
 }
-__device__ __forceinline__ double shift_r(double v, double fill) {
-  uint64_t b = (uint64_t)__double_as_longlong(v);
-  int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x138, 0xf, 0xf, true);
-  int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x138, 0xf, 0xf, true);
-  double r = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-  return lane_id() == 0 ? fill : r;
-}
-
-// Lane shift by d >= 2 with zeros entering lanes 0..d-1 (ds_bpermute).
-__device__ __forceinline__ float shift_d(float v, int d) {
-  int l = lane_id();
-  int r = __builtin_amdgcn_ds_bpermute(((l - d) & 63) << 2, __float_as_int(v));
-  return l >= d ? __int_as_float(r) : 0.0f;
-}
-__device__ __forceinline__ double shift_d(double v, int d) {
-  int l = lane_id();
-  int addr = ((l - d) & 63) << 2;
-  uint64_t b = (uint64_t)__double_as_longlong(v);
-  int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)b);
-  int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(b >> 32));
-  double r = __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-  return l >= d ? r : 0.0;
-}
-template <typename T>
-__device__ __forceinline__ T shift_any(T v, int d) {
-  return d == 1 ? shift_r(v, T(0)) : shift_d(v, d);
-}
-
-// Value of lane 63 in every lane.
-__device__ __forceinline__ float lane63(float v) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-__device__ __forceinline__ double lane63(double v) {
-  uint64_t b = (uint64_t)__double_as_longlong(v);
-  uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
-  uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+template <int CTRL, bool ZERO>
+__device__ __forceinline__ double dpp(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf, 0xf, ZERO);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, ZERO);
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Log-depth solve across the 64 lanes of z_l = A z_{l-1} + z_l (z_{-1} = 0)
-// for 2-vectors z = (p, q): Kogge-Stone doubling, round j adds A^(2^j) times
-// the value 2^j lanes below.  pw holds A^(2^j) row-major for j = 0..5.
+// Row shift by d with zeros entering the first d lanes of the row.
+template <int D, typename T>
+__device__ __forceinline__ T shr(T v) { return dpp<0x110 + D, true>(v); }
+
+// R with a fill value for lane 0 of the row.
 template <typename T>
-__device__ __forceinline__ void lane_scan_2x2(T &p, T &q, const T *__restrict__ pw) {
-#pragma unroll
-  for (int j = 0; j < kLogLanes; ++j) {
-    const int d = 1 << j;
-    const T m00 = pw[4 * j], m01 = pw[4 * j + 1], m10 = pw[4 * j + 2], m11 = pw[4 * j + 3];
-    T ps = shift_any(p, d);
-    T qs = shift_any(q, d);
-    T np = __builtin_fma(m00, ps, __builtin_fma(m01, qs, p));
-    T nq = __builtin_fma(m10, ps, __builtin_fma(m11, qs, q));
-    p = np;
-    q = nq;
+__device__ __forceinline__ T shift_r(T v, T fill) {
+  const T s = shr<1>(v);
+  return row_lane() == 0 ? fill : s;
+}
+
+// Lane 15 of the row in every lane of the row.
+template <typename T>
+__device__ __forceinline__ T last_of_row(T v) { return dpp<0x15f, false>(v); }
+
+// Log-depth solve along the row of z_l = A z_{l-1} + z_l (z_{-1} = 0) for
+// 2-vectors z = (p, q): round j adds A^(2^j) times the value 2^j lanes below
+// (Kogge-Stone doubling).  pw holds A^(2^j) row-major for j = 0..3.
+template <typename T>
+__device__ __forceinline__ void row_scan_2x2(T &p, T &q, const T *__restrict__ pw) {
+#define SOSF_ROUND(J, D)                                                          \
+  {                                                                               \
+    const T m00 = pw[4 * J], m01 = pw[4 * J + 1], m10 = pw[4 * J + 2], m11 = pw[4 * J + 3]; \
+    const T ps = shr<D>(p), qs = shr<D>(q);                                       \
+    const T np = __builtin_fma(m00, ps, __builtin_fma(m01, qs, p));               \
+    q = __builtin_fma(m10, ps, __builtin_fma(m11, qs, q));                        \
+    p = np;                                                                       \
   }
+  SOSF_ROUND(0, 1) SOSF_ROUND(1, 2) SOSF_ROUND(2, 4) SOSF_ROUND(3, 8)
+#undef SOSF_ROUND
 }
 
 // ------------------------------------------------------------ one section
 
 // Per-section boundary values carried from group to group (Section V):
-// st[0] = x[-2], st[1] = x[-1], st[2] = y[-2], st[3] = y[-1].
+// st[0] = x[-2], st[1] = x[-1], st[2] = y[-2], st[3] = y[-1], one set per row.
 
-// Non-recursive stage, eq. feedforward_block_uniform: v_m = b0 x_m +
-// b1 x_{m-1} + b2 x_{m-2} with the extended blocks x_{-1} = R x_{N-1} +
-// e0 x[-1], x_{-2} = R x_{N-2} + e0 x[-2]; then the previous group's outputs
-// enter the first element of blocks 0 and 1.
+// The block loops below are fully unrolled; left alone, the scheduler hoists
+// the FIR of every block ahead of the recursion, which keeps inputs and FIR
+// outputs live together.  A scheduling barrier every kSchedChunk blocks
+// bounds that lookahead (and the register pressure it costs).
+constexpr int kSchedChunk = SOSF_SCHED_CHUNK;
+
+// Non-recursive stage (eq. feedforward_block_uniform), computed block by
+// block in ascending m together with the first recursive pass, so that the
+// tile is updated in place with a few rolling registers:
+//   v_m = b0 x_m + b1 x_{m-1} + b2 x_{m-2},
+// with the extended blocks x_{-1} = R x_{N-1} + e0 x[-1] and
+// x_{-2} = R x_{N-2} + e0 x[-2]; the previous group's outputs enter the
+// first element of blocks 0 and 1: v_0[0] -= a1 y[-1] + a2 y[-2],
+// v_1[0] -= a2 y[-1].
+template <typename T, bool B0ONE>
+struct Fir {
+  T b0, b1, b2;
+  T p1, p2;   // x_{m-1}, x_{m-2} (original inputs)
+  __device__ __forceinline__ T next(T xm) {
+    T v = B0ONE ? xm : b0 * xm;
+    v = __builtin_fma(b1, p1, v);
+    v = __builtin_fma(b2, p2, v);
+    p2 = p1;
+    p1 = xm;
+    return v;
+  }
+};
+
+// PH factorisation (Section VI-B) of one section on one group per row.
 template <int N, typename T, bool B0ONE>
-__device__ __forceinline__ void nonrecursive(T (&X)[N], const T *__restrict__ c, T *st) {
-  const T b0 = c[OFF_B0], b1 = c[OFF_B1], b2 = c[OFF_B2];
+__device__ __forceinline__ void ph_section(T (&X)[N], const T *__restrict__ c, T *st) {
   const T a1 = c[OFF_A1], a2 = c[OFF_A2];
   const T xs2 = st[0], xs1 = st[1], ys2 = st[2], ys1 = st[3];
-  const T nx2 = lane63(X[N - 2]), nx1 = lane63(X[N - 1]);
-  const T xm1 = shift_r(X[N - 1], xs1);
-  const T xm2 = shift_r(X[N - 2], xs2);
+  const T nx2 = last_of_row(X[N - 2]), nx1 = last_of_row(X[N - 1]);
+  Fir<T, B0ONE> fir{c[OFF_B0], c[OFF_B1], c[OFF_B2], shift_r(X[N - 1], xs1),
+                    shift_r(X[N - 2], xs2)};
+  // step 1, eq. particular_recurrence: w_m = v_m - a1 w_{m-1} - a2 w_{m-2},
+  // every lane a zero-state recurrence over its own N samples.  On lane 0
+  // of the row the recurrence starts from the previous group's outputs,
+  // which is the same arithmetic as the state correction of v_0[0], v_1[0].
+  const bool l0 = row_lane() == 0;
+  T w1 = l0 ? ys1 : T(0), w2 = l0 ? ys2 : T(0);
 #pragma unroll
-  for (int m = N - 1; m >= 2; --m) {
-    T acc = B0ONE ? X[m] : b0 * X[m];
-    acc = __builtin_fma(b1, X[m - 1], acc);
-    X[m] = __builtin_fma(b2, X[m - 2], acc);
+  for (int m = 0; m < N; ++m) {
+    T w = fir.next(X[m]);
+    w = __builtin_fma(-a1, w1, w);
+    w = __builtin_fma(-a2, w2, w);
+    X[m] = w;
+    w2 = w1;
+    w1 = w;
+    if ((m & (kSchedChunk - 1)) == kSchedChunk - 1) __builtin_amdgcn_sched_barrier(0);
   }
-  {
-    T acc = B0ONE ? X[1] : b0 * X[1];
-    acc = __builtin_fma(b1, X[0], acc);
-    X[1] = __builtin_fma(b2, xm1, acc);
-    acc = B0ONE ? X[0] : b0 * X[0];
-    acc = __builtin_fma(b1, xm1, acc);
-    X[0] = __builtin_fma(b2, xm2, acc);
-  }
-  const bool l0 = lane_id() == 0;
-  const T c0 = __builtin_fma(a1, ys1, a2 * ys2);
-  const T c1 = a2 * ys1;
-  X[0] -= l0 ? c0 : T(0);
-  X[1] -= l0 ? c1 : T(0);
-  st[0] = nx2;
-  st[1] = nx1;
-}
-
-// PH factorisation (Section VI-B).
-template <int N, typename T>
-__device__ __forceinline__ void ph_solve(T (&X)[N], const T *__restrict__ c, T *st) {
-  const T a1 = c[OFF_A1], a2 = c[OFF_A2];
-  // step 1, eq. particular_recurrence: every lane runs the zero-state
-  // recurrence over its own N samples
-  X[1] = __builtin_fma(-a1, X[0], X[1]);
-#pragma unroll
-  for (int m = 2; m < N; ++m) X[m] = __builtin_fma(-a2, X[m - 2], __builtin_fma(-a1, X[m - 1], X[m]));
   // step 2, eq. recursive_doubling_equation: y_e[l] = w_e[l] - C y_e[l-1]
-  // over the lanes, with y_e[l] = (y[(l+1)N-2], y[(l+1)N-1])
+  // along the row, with y_e[l] = (y[(l+1)N-2], y[(l+1)N-1])
   T p = X[N - 2], q = X[N - 1];
-  lane_scan_2x2(p, q, c + OFF_PH_POW);
+  row_scan_2x2(p, q, c + OFF_PH_POW);
   X[N - 2] = p;
   X[N - 1] = q;
   // step 3, eq. PH_forward: the homogeneous correction from the true
   // terminal values of the preceding lane (R y_{N-2}, R y_{N-1})
-  const T pr = shift_r(p, T(0)), qr = shift_r(q, T(0));
+  const T pr = shr<1>(p), qr = shr<1>(q);
   const T *__restrict__ u1 = c + OFF_U1;
   const T *__restrict__ u2 = c + OFF_U1 + N;
 #pragma unroll
   for (int m = 0; m < N - 2; ++m) X[m] = __builtin_fma(-u2[m], pr, __builtin_fma(-u1[m], qr, X[m]));
-  st[2] = lane63(p);
-  st[3] = lane63(q);
+  st[0] = nx2;
+  st[1] = nx1;
+  st[2] = last_of_row(p);
+  st[3] = last_of_row(q);
 }
 
-// Cyclic reduction (Section VI-C).  Level i works on the blocks m = s(j+1)-1
-// (s = 2^i, j = 0..N/s-1); even j are eliminated, odd j retained.  A
-// reference below j = 0 wraps to the last blocks through R.
-template <int N, typename T>
-__device__ __forceinline__ void cr_solve(T (&X)[N], const T *__restrict__ c, T *st) {
+// Cyclic reduction (Section VI-C) of one section on one group per row.
+// Level i works on the blocks m = s(j+1)-1 (s = 2^i, j = 0..N/s-1); even j
+// are eliminated, odd j retained.  A reference below j = 0 wraps to the last
+// blocks through R.
+template <int N, typename T, bool B0ONE>
+__device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T *st) {
   constexpr int LG = __builtin_ctz(N);
-  // reduction, eq. cr_coeff_update coefficients per level
+  const T a1 = c[OFF_A1], a2 = c[OFF_A2];
+  const T xs2 = st[0], xs1 = st[1], ys2 = st[2], ys1 = st[3];
+  const T nx2 = last_of_row(X[N - 2]), nx1 = last_of_row(X[N - 1]);
+  const bool l0 = row_lane() == 0;
+  Fir<T, B0ONE> fir{c[OFF_B0], c[OFF_B1], c[OFF_B2], shift_r(X[N - 1], xs1),
+                    shift_r(X[N - 2], xs2)};
+  // v_{N-1} first: level 0 needs R v_{N-1} for its first row
+  T vlast;
+  {
+    T v = B0ONE ? X[N - 1] : fir.b0 * X[N - 1];
+    v = __builtin_fma(fir.b1, X[N - 2], v);
+    vlast = __builtin_fma(fir.b2, X[N - 3], v);
+  }
+  // non-recursive stage fused with reduction level 0 (s = 1): even rows
+  // v'_m = v_m - (f/e) v_{m-1} (row 0 takes R v_{N-1}), odd rows
+  // v'_m = v_m - e v'_{m-1}
+  {
+    const T fe = c[OFF_CR_LVL], e = c[OFF_CR_LVL + 1];
+    T prev_odd = shr<1>(vlast);
 #pragma unroll
-  for (int i = 0; i < LG; ++i) {
+    for (int m = 0; m < N; m += 2) {
+      T ve = fir.next(X[m]);
+      T vo = (m + 1 == N - 1) ? vlast : fir.next(X[m + 1]);
+      if (m + 1 == N - 1) fir.next(X[m + 1]);
+      if (m == 0) {
+        ve -= l0 ? __builtin_fma(a1, ys1, a2 * ys2) : T(0);
+        vo -= l0 ? a2 * ys1 : T(0);
+      }
+      ve = __builtin_fma(-fe, prev_odd, ve);
+      prev_odd = vo;
+      X[m] = ve;
+      X[m + 1] = __builtin_fma(-e, ve, vo);
+      if ((m & (kSchedChunk - 1)) == kSchedChunk - 2) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // reduction levels 1 .. log2 N - 1, eq. cr_coeff_update coefficients
+#pragma unroll
+  for (int i = 1; i < LG; ++i) {
     const int s = 1 << i, ni = N >> i;
     const T fe = c[OFF_CR_LVL + 4 * i], e = c[OFF_CR_LVL + 4 * i + 1];
-    const T wrap = shift_r(X[N - 1], T(0));
+    const T wrap = shr<1>(X[N - 1]);
 #pragma unroll
     for (int j = 0; j < ni; j += 2) {
       const int m = s * (j + 1) - 1;
@@ -173,22 +212,22 @@ __device__ __forceinline__ void cr_solve(T (&X)[N], const T *__restrict__ c, T *
     }
   }
   // terminal block, eq. cr_terminal_block: (I + e R + f R^2) y = v' on block
-  // N-1, a second-order recurrence over the lanes; solved by the log-depth
+  // N-1, a second-order recurrence along the row; solved by the log-depth
   // scan of z_l = (y_{l-1}, y_l) = T z_{l-1} + (0, v'_l)
   {
     T p = T(0), q = X[N - 1];
-    lane_scan_2x2(p, q, c + OFF_CR_POW);
+    row_scan_2x2(p, q, c + OFF_CR_POW);
     X[N - 1] = q;
   }
   // back substitution, eqs. cr_companion_block .. cr_backsub_final
-  const T r1 = shift_r(X[N - 1], T(0));   // R y_{N-1}, reused at every level
+  const T r1 = shr<1>(X[N - 1]);   // R y_{N-1}, reused at every level
 #pragma unroll
   for (int i = LG - 1; i >= 0; --i) {
     const int s = 1 << i, ni = N >> i;
     const T cc = c[OFF_CR_LVL + 4 * i + 2], dd = c[OFF_CR_LVL + 4 * i + 3];
     T w3;   // the once-wrapped block for j = 0
-    if (ni == 2) w3 = shift_r(r1, T(0));                 // R^2 y_{N-1}
-    else w3 = shift_r(X[N - 2 * s - 1], T(0));           // R y at position ni-3
+    if (ni == 2) w3 = shr<1>(r1);                 // R^2 y_{N-1}
+    else w3 = shr<1>(X[N - 2 * s - 1]);           // R y at position ni-3
 #pragma unroll
     for (int j = 0; j < ni; j += 2) {
       const int m = s * (j + 1) - 1;
@@ -197,8 +236,10 @@ __device__ __forceinline__ void cr_solve(T (&X)[N], const T *__restrict__ c, T *
       X[m] = __builtin_fma(-cc, y1, __builtin_fma(-dd, y3, X[m]));
     }
   }
-  st[2] = lane63(X[N - 2]);
-  st[3] = lane63(X[N - 1]);
+  st[0] = nx2;
+  st[1] = nx1;
+  st[2] = last_of_row(X[N - 2]);
+  st[3] = last_of_row(X[N - 1]);
 }
 
 // ------------------------------------------------------------ memory
@@ -206,65 +247,93 @@ __device__ __forceinline__ void cr_solve(T (&X)[N], const T *__restrict__ c, T *
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef double vd2 __attribute__((ext_vector_type(2)));
 
+template <typename TI>
+struct Vec16;
+template <>
+struct Vec16<float> { typedef vf4 type; static constexpr int n = 4; };
+template <>
+struct Vec16<double> { typedef vd2 type; static constexpr int n = 2; };
+
+// A group (16 N samples per row) is moved between HBM and registers through
+// a per-wave LDS buffer.  Global accesses are 16-byte vectors, 16 lanes of a
+// row covering 256 consecutive bytes of that row's group per instruction;
+// the stride-N permutation happens in LDS, where lane l reads or writes its
+// own run of N samples.  Each run is padded by 16 bytes so that the 16-byte
+// LDS accesses of a row fall on distinct banks.
+template <int N, typename TI>
+struct Stage {
+  static constexpr int V = Vec16<TI>::n;        // elements per 16-byte vector
+  static constexpr int RUN = N + V;             // padded run length (elements)
+  static constexpr int ROWBUF = kL * RUN;       // per row
+  static constexpr int ELEMS = kRows * ROWBUF;  // per wave
+};
+
+// g: this row's group start (may be negative or run past n in the run-in
+// and at the end; those samples read as zero).  full: every row of the wave
+// has a whole group inside [0, n).
 template <int N, typename TI, typename T>
 __device__ __forceinline__ void load_group(T (&X)[N], const TI *__restrict__ x, int64_t g,
-                                           int64_t n) {
-  const int64_t base = g + (int64_t)lane_id() * N;
-  if (g + (int64_t)N * kLanes <= n) {
-    if constexpr (sizeof(TI) == 4) {
-      const vf4 *p = reinterpret_cast<const vf4 *>(x + base);
+                                           int64_t n, bool full, TI *__restrict__ buf) {
+  typedef typename Vec16<TI>::type VT;
+  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
+  const int rl = row_lane();
+  if (full) {
+    const VT *src = reinterpret_cast<const VT *>(x + g);
 #pragma unroll
-      for (int j = 0; j < N / 4; ++j) {
-        vf4 v = __builtin_nontemporal_load(p + j);
-        X[4 * j] = T(v.x); X[4 * j + 1] = T(v.y); X[4 * j + 2] = T(v.z); X[4 * j + 3] = T(v.w);
-      }
-    } else {
-      const vd2 *p = reinterpret_cast<const vd2 *>(x + base);
-#pragma unroll
-      for (int j = 0; j < N / 2; ++j) {
-        vd2 v = __builtin_nontemporal_load(p + j);
-        X[2 * j] = T(v.x); X[2 * j + 1] = T(v.y);
-      }
+    for (int j = 0; j < N / V; ++j) {
+      const int e = (j * kL + rl) * V;            // element of the row's group
+      VT v = __builtin_nontemporal_load(src + j * kL + rl);
+      *reinterpret_cast<VT *>(buf + (e / N) * RUN + (e % N)) = v;
     }
   } else {
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-      const int64_t i = base + m;
-      X[m] = (i < n) ? T(x[i]) : T(0);
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+      const int e = j * kL + rl;
+      const int64_t i = g + e;
+      buf[(e / N) * RUN + (e % N)] = (i >= 0 && i < n) ? x[i] : TI(0);
     }
   }
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < N / V; ++j) {
+    VT v = *reinterpret_cast<const VT *>(buf + rl * RUN + j * V);
+#pragma unroll
+    for (int i = 0; i < V; ++i) X[j * V + i] = T(v[i]);
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
 template <int N, typename TI, typename T>
 __device__ __forceinline__ void store_group(const T (&X)[N], TI *__restrict__ y, int64_t g,
-                                            int64_t n, T gain) {
-  const int64_t base = g + (int64_t)lane_id() * N;
-  if (g + (int64_t)N * kLanes <= n) {
-    if constexpr (sizeof(TI) == 4) {
-      vf4 *p = reinterpret_cast<vf4 *>(y + base);
+                                            int64_t n, bool full, T gain, TI *__restrict__ buf) {
+  typedef typename Vec16<TI>::type VT;
+  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
+  const int rl = row_lane();
 #pragma unroll
-      for (int j = 0; j < N / 4; ++j) {
-        vf4 v;
-        v.x = (float)(X[4 * j] * gain); v.y = (float)(X[4 * j + 1] * gain);
-        v.z = (float)(X[4 * j + 2] * gain); v.w = (float)(X[4 * j + 3] * gain);
-        __builtin_nontemporal_store(v, p + j);
-      }
-    } else {
-      vd2 *p = reinterpret_cast<vd2 *>(y + base);
+  for (int j = 0; j < N / V; ++j) {
+    VT v;
 #pragma unroll
-      for (int j = 0; j < N / 2; ++j) {
-        vd2 v;
-        v.x = (double)(X[2 * j] * gain); v.y = (double)(X[2 * j + 1] * gain);
-        __builtin_nontemporal_store(v, p + j);
-      }
+    for (int i = 0; i < V; ++i) v[i] = (TI)(X[j * V + i] * gain);
+    *reinterpret_cast<VT *>(buf + rl * RUN + j * V) = v;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (full) {
+    VT *dst = reinterpret_cast<VT *>(y + g);
+#pragma unroll
+    for (int j = 0; j < N / V; ++j) {
+      const int e = (j * kL + rl) * V;
+      VT v = *reinterpret_cast<const VT *>(buf + (e / N) * RUN + (e % N));
+      __builtin_nontemporal_store(v, dst + j * kL + rl);
     }
   } else {
-#pragma unroll
-    for (int m = 0; m < N; ++m) {
-      const int64_t i = base + m;
-      if (i < n) y[i] = (TI)(X[m] * gain);
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+      const int e = j * kL + rl;
+      const int64_t i = g + e;
+      if (i >= 0 && i < n) y[i] = buf[(e / N) * RUN + (e % N)];
     }
   }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // ------------------------------------------------------------ kernel
@@ -273,49 +342,67 @@ struct FiltArgs {
   int64_t n;
   int32_t K;
   int32_t stride;
-  int64_t tile;             // samples per tile, multiple of N*64
-  int64_t warm;             // run-in samples before each tile, multiple of N*64
+  int64_t tile;             // samples per tile, a multiple of the group (16 N)
+  int64_t warm;             // run-in samples before each tile, a multiple of the group
   int64_t ntiles;
   double gain;
 };
 
 constexpr int kWavesPerBlock = 4;
 
-// One wavefront per tile [t*tile, (t+1)*tile).  The wave first runs the
-// cascade from zero state over the `warm` samples that precede the tile
-// (its carry-in: the cascade state after `warm` samples no longer depends,
-// to the working precision, on anything earlier), then filters the tile,
-// chaining groups by each section's boundary values.
+template <int N, typename TI>
+__host__ __device__ constexpr int stage_bytes() {
+  return kWavesPerBlock * Stage<N, TI>::ELEMS * (int)sizeof(TI);
+}
+template <int N, typename TI, typename T>
+__host__ __device__ constexpr int lds_bytes(int K) {
+  return stage_bytes<N, TI>() + kWavesPerBlock * kRows * K * 4 * (int)sizeof(T);
+}
+
+// Tile t = [t*tile, (t+1)*tile) is filtered by row (t mod 4) of wavefront
+// t / 4.  The row first runs the cascade from zero state over the `warm`
+// samples that precede its tile (its carry-in: after `warm` samples the
+// cascade state no longer depends, to the working precision, on anything
+// earlier), then filters the tile, chaining groups through each section's
+// boundary values.  All four rows run the same number of groups; samples
+// outside [0, n) are zeros and are not stored.
 //
 // The pointers are separate restrict-qualified arguments so that the
 // compiler may read the coefficient table (uniform addresses, never
 // written here) through the scalar cache.
 template <int N, typename TI, typename T, bool B0ONE>
-__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_tiles_kernel(
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const T *__restrict__ tab,
     const int32_t *__restrict__ solver, FiltArgs a) {
-  __shared__ T state[kWavesPerBlock][SOS_MAX_SECTIONS][4];
+  // dynamic LDS: the staging buffers, then the boundary values of every
+  // section of every row (sized for the plan's K at launch)
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  TI *stage = reinterpret_cast<TI *>(smem);
+  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, TI>());
   // the wave index is uniform across the wave; say so, so that everything
-  // derived from it (tile bounds, table addresses) stays in scalar registers
+  // derived from it stays in scalar registers
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t tile = (int64_t)blockIdx.x * kWavesPerBlock + w;
-  if (tile >= a.ntiles) return;   // uniform per wave
-  T(*st)[4] = state[w];
-  for (int i = 0; i < a.K * 4; ++i) st[i >> 2][i & 3] = T(0);   // every lane writes the same value
-  const int64_t t0 = tile * a.tile;
-  const int64_t t1 = (t0 + a.tile < a.n) ? t0 + a.tile : a.n;
-  const int64_t NL = (int64_t)N * kLanes;
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (wave * kRows >= a.ntiles) return;   // uniform per wave
+  const int row = lane_id() >> 4;
+  const int64_t t0 = (wave * kRows + row) * a.tile;   // this row's tile
+  T(*st)[4] = reinterpret_cast<T(*)[4]>(state + (int64_t)(w * kRows + row) * a.K * 4);
+  for (int i = 0; i < a.K * 4; ++i) st[i >> 2][i & 3] = T(0);   // the row's lanes write the same value
+  TI *buf = stage + (w * kRows + row) * Stage<N, TI>::ROWBUF;
+  const int64_t G = (int64_t)N * kL;
+  const int64_t warm_groups = a.warm / G, steps = warm_groups + a.tile / G;
   const T gain = (T)a.gain;
   T X[N];
-  for (int64_t g = (t0 > a.warm ? t0 - a.warm : 0); g < t1; g += NL) {
-    load_group<N, TI, T>(X, x, g, a.n);
+  for (int64_t it = 0; it < steps; ++it) {
+    const int64_t g = t0 - a.warm + it * G;
+    const bool full = __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= a.n)) == 0;
+    load_group<N, TI, T>(X, x, g, a.n, full, buf);
     for (int k = 0; k < a.K; ++k) {
       const T *__restrict__ c = tab + (int64_t)k * a.stride;
-      nonrecursive<N, T, B0ONE>(X, c, st[k]);
-      if (solver[k] == SOS_CR) cr_solve<N, T>(X, c, st[k]);
-      else ph_solve<N, T>(X, c, st[k]);
+      if (solver[k] == SOS_CR) cr_section<N, T, B0ONE>(X, c, st[k]);
+      else ph_section<N, T, B0ONE>(X, c, st[k]);
     }
-    if (g >= t0) store_group<N, TI, T>(X, y, g, a.n, gain);
+    if (it >= warm_groups) store_group<N, TI, T>(X, y, g, a.n, full, gain, buf);
   }
 }
 

@@ -9,17 +9,18 @@
 
 namespace sosf {
 
-constexpr int kLanes = 64;       // wavefront width = block size L
-constexpr int kLogLanes = 6;
+constexpr int kL = 16;           // block size L = lanes of one DPP row
+constexpr int kLogL = 4;
+constexpr int kRows = 4;         // independent blocks (rows) per 64-wide wavefront
 constexpr int kMaxLevels = 10;   // log2 of the largest N the tables hold
 
 // Offsets (in elements of the compute dtype) inside one section's row of the
 // device table.  Row length = tab_stride(N).
 enum : int {
   OFF_B0 = 0, OFF_B1 = 1, OFF_B2 = 2, OFF_A1 = 3, OFF_A2 = 4,
-  OFF_PH_POW = 8,                              // 6 x 4: (-C)^(2^j)
-  OFF_CR_POW = OFF_PH_POW + 4 * kLogLanes,     // 6 x 4: T^(2^j)
-  OFF_CR_LVL = OFF_CR_POW + 4 * kLogLanes,     // 10 x 4: f/e, e, c, d
+  OFF_PH_POW = 8,                              // 4 x 4: (-C)^(2^j)
+  OFF_CR_POW = OFF_PH_POW + 4 * kLogL,         // 4 x 4: T^(2^j)
+  OFF_CR_LVL = OFF_CR_POW + 4 * kLogL,         // 10 x 4: f/e, e, c, d
   OFF_U1 = OFF_CR_LVL + 4 * kMaxLevels,        // N
 };
 inline int off_u2(int N) { return OFF_U1 + N; }

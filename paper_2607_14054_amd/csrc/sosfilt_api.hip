@@ -49,16 +49,18 @@ struct Ptrs {
 
 template <int N, typename TI, typename T>
 sos_status launch_n(const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s) {
-  const int64_t blocks = (a.ntiles + kWavesPerBlock - 1) / kWavesPerBlock;
+  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
+  const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
   const TI *x = static_cast<const TI *>(q.x);
   TI *y = static_cast<TI *>(q.y);
   const T *tab = static_cast<const T *>(q.tab);
+  const unsigned lds = (unsigned)lds_bytes<N, TI, T>(a.K);
   if (b0one)
-    hipLaunchKernelGGL((sos_tiles_kernel<N, TI, T, true>), dim3((unsigned)blocks),
-                       dim3(kWavesPerBlock * 64), 0, s, x, y, tab, q.solver, a);
+    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, true>), dim3((unsigned)blocks),
+                       dim3(kWavesPerBlock * 64), lds, s, x, y, tab, q.solver, a);
   else
-    hipLaunchKernelGGL((sos_tiles_kernel<N, TI, T, false>), dim3((unsigned)blocks),
-                       dim3(kWavesPerBlock * 64), 0, s, x, y, tab, q.solver, a);
+    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, false>), dim3((unsigned)blocks),
+                       dim3(kWavesPerBlock * 64), lds, s, x, y, tab, q.solver, a);
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }
 
@@ -74,17 +76,18 @@ sos_status launch_t(int N, const Ptrs &q, const FiltArgs &a, bool b0one, hipStre
 }
 
 // Tile length for n samples: long enough that the run-in costs at most
-// about 1/16 of the tile, short enough to give the chip enough wavefronts.
+// about 1/16 of the tile, short enough to give the chip enough rows (four
+// per wavefront) in flight.
 int64_t choose_tile(const sos_plan_s &p, int64_t n) {
-  const int64_t NL = (int64_t)p.N * kLanes;
-  const int64_t groups = (n + NL - 1) / NL;
-  if (p.tile_groups > 0) return (int64_t)p.tile_groups * NL;
-  const int64_t gw = p.warm / NL;
+  const int64_t G = (int64_t)p.N * kL;
+  const int64_t groups = (n + G - 1) / G;
+  if (p.tile_groups > 0) return (int64_t)p.tile_groups * G;
+  const int64_t gw = p.warm / G;
   int64_t tg = std::max<int64_t>(16 * gw, 8);
-  const int64_t want_tiles = 4096;
+  const int64_t want_tiles = 16384;
   const int64_t tg_par = std::max<int64_t>(groups / want_tiles, 1);
   if (tg_par < tg) tg = std::max<int64_t>(tg_par, std::max<int64_t>(4 * gw, 4));
-  return tg * NL;
+  return tg * G;
 }
 
 }  // namespace
@@ -109,12 +112,12 @@ sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan
   sos_opts o{SOS_F32, SOS_F64, SOS_AUTO, 0, 0, 0, 0};
   if (opts) o = *opts;
   if (o.N == 0) o.N = 32;
-  if (o.L == 0) o.L = 64;
+  if (o.L == 0) o.L = 16;
   if (o.io_dtype != SOS_F32 && o.io_dtype != SOS_F64) return SOS_E_ARG;
   if (o.compute_dtype != SOS_F32 && o.compute_dtype != SOS_F64) return SOS_E_ARG;
   if (o.solver < SOS_AUTO || o.solver > SOS_CR) return SOS_E_ARG;
   if (o.tile_groups < 0) return SOS_E_ARG;
-  if (!pow2_in(o.N, 8, 64) || o.L != 64) return SOS_E_UNSUPPORTED;
+  if (!pow2_in(o.N, 8, 64) || o.L != kL) return SOS_E_UNSUPPORTED;
   if (o.io_dtype == SOS_F64 && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
   sos_plan_s *p = new (std::nothrow) sos_plan_s;
   if (!p) return SOS_E_NOMEM;
@@ -180,10 +183,10 @@ sos_status sos_plan_table(sos_plan_t p, int32_t table, int32_t section, double *
     case SOS_TABLE_U1: buf.assign(t + OFF_U1, t + OFF_U1 + p->N); break;
     case SOS_TABLE_U2: buf.assign(t + off_u2(p->N), t + off_u2(p->N) + p->N); break;
     case SOS_TABLE_C: buf.assign(p->C.begin() + 4 * section, p->C.begin() + 4 * section + 4); break;
-    case SOS_TABLE_PH_POWERS: buf.assign(t + OFF_PH_POW, t + OFF_PH_POW + 4 * kLogLanes); break;
+    case SOS_TABLE_PH_POWERS: buf.assign(t + OFF_PH_POW, t + OFF_PH_POW + 4 * kLogL); break;
     case SOS_TABLE_CR_LEVELS: buf.assign(t + OFF_CR_LVL, t + OFF_CR_LVL + 4 * p->lgN); break;
     case SOS_TABLE_CR_TERMINAL: buf.assign(p->cr_term.begin() + 2 * section, p->cr_term.begin() + 2 * section + 2); break;
-    case SOS_TABLE_CR_POWERS: buf.assign(t + OFF_CR_POW, t + OFF_CR_POW + 4 * kLogLanes); break;
+    case SOS_TABLE_CR_POWERS: buf.assign(t + OFF_CR_POW, t + OFF_CR_POW + 4 * kLogL); break;
     case SOS_TABLE_TRANSITION: buf = p->phi; break;
     default: return SOS_E_ARG;
   }

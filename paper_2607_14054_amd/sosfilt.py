@@ -106,7 +106,7 @@ class Plan:
         s = np.ascontiguousarray(np.asarray(sos, dtype=np.float64))
         if s.ndim != 2 or s.shape[1] != 6:
             raise ValueError("sos must be [K, 6]")
-        o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), 64,
+        o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), 16,
                   int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0)
         h = ctypes.c_void_p()
         _check(lib().sos_plan(s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), s.shape[0],

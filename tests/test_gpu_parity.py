@@ -104,7 +104,7 @@ def test_impulse_across_tile_boundary(offset):
     impulse response across the boundary (run-in carry)."""
     sos = W.make_sos(8, 0.5, 0.95, 13)
     N, tg = 8, 4
-    tile = N * 64 * tg
+    tile = N * 16 * tg          # group = N L samples, L = 16
     n = 6 * tile
     x = np.zeros(n)
     x[3 * tile + offset] = 1.0

@@ -110,8 +110,8 @@ def test_ph_tables_match_model(N):
         assert np.allclose(p.table(S.SOS_TABLE_U2, k), u2, rtol=1e-13, atol=1e-300)
         C = M.ph_C(a1, a2, N)
         assert np.allclose(p.table(S.SOS_TABLE_C, k).reshape(2, 2), C, rtol=1e-13, atol=1e-300)
-        pw = p.table(S.SOS_TABLE_PH_POWERS, k).reshape(6, 2, 2)
-        for j in range(6):
+        pw = p.table(S.SOS_TABLE_PH_POWERS, k).reshape(4, 2, 2)    # L = 16: log2 L rounds
+        for j in range(4):
             assert np.allclose(pw[j], np.linalg.matrix_power(-C, 2 ** j), rtol=1e-10, atol=1e-300)
     assert p.info().solver == ["ph"] * 3
 
@@ -135,8 +135,8 @@ def test_cr_tables_match_closed_form(N):
     assert math.isclose(eT, -2 * r ** N * math.cos(N * theta), rel_tol=1e-8, abs_tol=1e-15)
     assert math.isclose(fT, r ** (2 * N), rel_tol=1e-8)
     T = np.array([[0.0, 1.0], [-fT, -eT]])
-    pw = p.table(S.SOS_TABLE_CR_POWERS, 0).reshape(6, 2, 2)
-    for j in range(6):
+    pw = p.table(S.SOS_TABLE_CR_POWERS, 0).reshape(4, 2, 2)
+    for j in range(4):
         assert np.allclose(pw[j], np.linalg.matrix_power(T, 2 ** j), rtol=1e-10, atol=1e-300)
     assert p.info().solver == ["cr"]
 
@@ -189,7 +189,7 @@ def test_run_in_length_bounds_transition():
     Phi = p.table(S.SOS_TABLE_TRANSITION).reshape(2 * K, 2 * K)
     P = np.linalg.matrix_power(Phi, info.warm_samples)
     assert np.max(np.sum(np.abs(P), axis=1)) < 2.0 ** -50
-    assert info.warm_samples % (32 * 64) == 0
+    assert info.warm_samples % (32 * 16) == 0
     assert math.isclose(info.transition_norm_W, np.max(np.sum(np.abs(P), axis=1)), rel_tol=1e-6)
     # the run-in is not absurdly long: the slowest pole is 0.98
     assert info.warm_samples <= 16 * 2048
