@@ -26,6 +26,11 @@
 
 namespace sosf {
 
+// Fused multiply-add in the compute type (the generic builtin would promote
+// float operands to double).
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // ------------------------------------------------------------ lane moves
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -68,8 +73,8 @@ __device__ __forceinline__ void row_scan_2x2(T &p, T &q, const T *__restrict__ p
   {                                                                               \
     const T m00 = pw[4 * J], m01 = pw[4 * J + 1], m10 = pw[4 * J + 2], m11 = pw[4 * J + 3]; \
     const T ps = shr<D>(p), qs = shr<D>(q);                                       \
-    const T np = __builtin_fma(m00, ps, __builtin_fma(m01, qs, p));               \
-    q = __builtin_fma(m10, ps, __builtin_fma(m11, qs, q));                        \
+    const T np = fma_(m00, ps, fma_(m01, qs, p));               \
+    q = fma_(m10, ps, fma_(m11, qs, q));                        \
     p = np;                                                                       \
   }
   SOSF_ROUND(0, 1) SOSF_ROUND(1, 2) SOSF_ROUND(2, 4) SOSF_ROUND(3, 8)
@@ -101,8 +106,8 @@ struct Fir {
   T p1, p2;   // x_{m-1}, x_{m-2} (original inputs)
   __device__ __forceinline__ T next(T xm) {
     T v = B0ONE ? xm : b0 * xm;
-    v = __builtin_fma(b1, p1, v);
-    v = __builtin_fma(b2, p2, v);
+    v = fma_(b1, p1, v);
+    v = fma_(b2, p2, v);
     p2 = p1;
     p1 = xm;
     return v;
@@ -126,8 +131,8 @@ __device__ __forceinline__ void ph_section(T (&X)[N], const T *__restrict__ c, T
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     T w = fir.next(X[m]);
-    w = __builtin_fma(-a1, w1, w);
-    w = __builtin_fma(-a2, w2, w);
+    w = fma_(-a1, w1, w);
+    w = fma_(-a2, w2, w);
     X[m] = w;
     w2 = w1;
     w1 = w;
@@ -145,7 +150,7 @@ __device__ __forceinline__ void ph_section(T (&X)[N], const T *__restrict__ c, T
   const T *__restrict__ u1 = c + OFF_U1;
   const T *__restrict__ u2 = c + OFF_U1 + N;
 #pragma unroll
-  for (int m = 0; m < N - 2; ++m) X[m] = __builtin_fma(-u2[m], pr, __builtin_fma(-u1[m], qr, X[m]));
+  for (int m = 0; m < N - 2; ++m) X[m] = fma_(-u2[m], pr, fma_(-u1[m], qr, X[m]));
   st[0] = nx2;
   st[1] = nx1;
   st[2] = last_of_row(p);
@@ -169,8 +174,8 @@ __device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T
   T vlast;
   {
     T v = B0ONE ? X[N - 1] : fir.b0 * X[N - 1];
-    v = __builtin_fma(fir.b1, X[N - 2], v);
-    vlast = __builtin_fma(fir.b2, X[N - 3], v);
+    v = fma_(fir.b1, X[N - 2], v);
+    vlast = fma_(fir.b2, X[N - 3], v);
   }
   // non-recursive stage fused with reduction level 0 (s = 1): even rows
   // v'_m = v_m - (f/e) v_{m-1} (row 0 takes R v_{N-1}), odd rows
@@ -184,13 +189,13 @@ __device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T
       T vo = (m + 1 == N - 1) ? vlast : fir.next(X[m + 1]);
       if (m + 1 == N - 1) fir.next(X[m + 1]);
       if (m == 0) {
-        ve -= l0 ? __builtin_fma(a1, ys1, a2 * ys2) : T(0);
+        ve -= l0 ? fma_(a1, ys1, a2 * ys2) : T(0);
         vo -= l0 ? a2 * ys1 : T(0);
       }
-      ve = __builtin_fma(-fe, prev_odd, ve);
+      ve = fma_(-fe, prev_odd, ve);
       prev_odd = vo;
       X[m] = ve;
-      X[m + 1] = __builtin_fma(-e, ve, vo);
+      X[m + 1] = fma_(-e, ve, vo);
       if ((m & (kSchedChunk - 1)) == kSchedChunk - 2) __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -203,12 +208,12 @@ __device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T
 #pragma unroll
     for (int j = 0; j < ni; j += 2) {
       const int m = s * (j + 1) - 1;
-      X[m] = __builtin_fma(-fe, j == 0 ? wrap : X[m - s], X[m]);
+      X[m] = fma_(-fe, j == 0 ? wrap : X[m - s], X[m]);
     }
 #pragma unroll
     for (int j = 1; j < ni; j += 2) {
       const int m = s * (j + 1) - 1;
-      X[m] = __builtin_fma(-e, X[m - s], X[m]);
+      X[m] = fma_(-e, X[m - s], X[m]);
     }
   }
   // terminal block, eq. cr_terminal_block: (I + e R + f R^2) y = v' on block
@@ -233,7 +238,7 @@ __device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T
       const int m = s * (j + 1) - 1;
       const T y1 = (j >= 1) ? X[m - s] : r1;
       const T y3 = (j >= 3) ? X[m - 3 * s] : (j == 0 ? w3 : r1);
-      X[m] = __builtin_fma(-cc, y1, __builtin_fma(-dd, y3, X[m]));
+      X[m] = fma_(-cc, y1, fma_(-dd, y3, X[m]));
     }
   }
   st[0] = nx2;
@@ -370,7 +375,9 @@ __host__ __device__ constexpr int lds_bytes(int K) {
 // The pointers are separate restrict-qualified arguments so that the
 // compiler may read the coefficient table (uniform addresses, never
 // written here) through the scalar cache.
-template <int N, typename TI, typename T, bool B0ONE>
+// SOLVER: SOS_PH or SOS_CR when every section uses that solver (no branch
+// in the section loop), SOS_AUTO for a per-section choice.
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const T *__restrict__ tab,
     const int32_t *__restrict__ solver, FiltArgs a) {
@@ -399,8 +406,10 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_kernel(
     load_group<N, TI, T>(X, x, g, a.n, full, buf);
     for (int k = 0; k < a.K; ++k) {
       const T *__restrict__ c = tab + (int64_t)k * a.stride;
-      if (solver[k] == SOS_CR) cr_section<N, T, B0ONE>(X, c, st[k]);
-      else ph_section<N, T, B0ONE>(X, c, st[k]);
+      if (SOLVER == SOS_CR || (SOLVER == SOS_AUTO && solver[k] == SOS_CR))
+        cr_section<N, T, B0ONE>(X, c, st[k]);
+      else
+        ph_section<N, T, B0ONE>(X, c, st[k]);
     }
     if (it >= warm_groups) store_group<N, TI, T>(X, y, g, a.n, full, gain, buf);
   }

@@ -47,8 +47,8 @@ struct Ptrs {
   const int32_t *solver;
 };
 
-template <int N, typename TI, typename T>
-sos_status launch_n(const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s) {
+template <int N, typename TI, typename T, int SOLVER>
+sos_status launch_s(const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s) {
   const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
   const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
   const TI *x = static_cast<const TI *>(q.x);
@@ -56,21 +56,28 @@ sos_status launch_n(const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s)
   const T *tab = static_cast<const T *>(q.tab);
   const unsigned lds = (unsigned)lds_bytes<N, TI, T>(a.K);
   if (b0one)
-    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, true>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, true, SOLVER>), dim3((unsigned)blocks),
                        dim3(kWavesPerBlock * 64), lds, s, x, y, tab, q.solver, a);
   else
-    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, false>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, false, SOLVER>), dim3((unsigned)blocks),
                        dim3(kWavesPerBlock * 64), lds, s, x, y, tab, q.solver, a);
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }
 
+template <int N, typename TI, typename T>
+sos_status launch_n(const Ptrs &q, const FiltArgs &a, bool b0one, int mix, hipStream_t s) {
+  if (mix == SOS_PH) return launch_s<N, TI, T, SOS_PH>(q, a, b0one, s);
+  if (mix == SOS_CR) return launch_s<N, TI, T, SOS_CR>(q, a, b0one, s);
+  return launch_s<N, TI, T, SOS_AUTO>(q, a, b0one, s);
+}
+
 template <typename TI, typename T>
-sos_status launch_t(int N, const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s) {
+sos_status launch_t(int N, const Ptrs &q, const FiltArgs &a, bool b0one, int mix, hipStream_t s) {
   switch (N) {
-    case 8: return launch_n<8, TI, T>(q, a, b0one, s);
-    case 16: return launch_n<16, TI, T>(q, a, b0one, s);
-    case 32: return launch_n<32, TI, T>(q, a, b0one, s);
-    case 64: return launch_n<64, TI, T>(q, a, b0one, s);
+    case 8: return launch_n<8, TI, T>(q, a, b0one, mix, s);
+    case 16: return launch_n<16, TI, T>(q, a, b0one, mix, s);
+    case 32: return launch_n<32, TI, T>(q, a, b0one, mix, s);
+    case 64: return launch_n<64, TI, T>(q, a, b0one, mix, s);
     default: return SOS_E_UNSUPPORTED;
   }
 }
@@ -224,9 +231,13 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
   a.gain = p->gain;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool b0one = p->b0_factored;
-  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F32) return launch_t<float, float>(p->N, q, a, b0one, s);
-  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F64) return launch_t<float, double>(p->N, q, a, b0one, s);
-  if (p->io_dtype == SOS_F64 && p->compute_dtype == SOS_F64) return launch_t<double, double>(p->N, q, a, b0one, s);
+  // one solver for every section lets the kernel drop the per-section branch
+  int mix = p->solver[0];
+  for (int k = 1; k < p->K; ++k)
+    if (p->solver[k] != mix) mix = SOS_AUTO;
+  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F32) return launch_t<float, float>(p->N, q, a, b0one, mix, s);
+  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F64) return launch_t<float, double>(p->N, q, a, b0one, mix, s);
+  if (p->io_dtype == SOS_F64 && p->compute_dtype == SOS_F64) return launch_t<double, double>(p->N, q, a, b0one, mix, s);
   return SOS_E_UNSUPPORTED;
 }
 
