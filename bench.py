@@ -70,8 +70,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--solver", default="auto")
+    ap.add_argument("--solver", default="ph")
     ap.add_argument("--N", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="groups per tile (0: the library's choice)")
+    ap.add_argument("--tile-sweep", action="store_true", help="time the main plan at several tile sizes")
     ap.add_argument("--sweep", action="store_true", help="also time PH and CR at every N")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--out", default="")
@@ -99,7 +101,8 @@ def main():
     y = torch.empty_like(x)
 
     N = args.N or 32
-    plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=args.solver, N=N)
+    plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=args.solver, N=N,
+                  tile_groups=args.tile)
     info = plan.info()
     sec = timed_filter(S, torch, plan, x, y, args.steps, args.warmup)
     gsps = n / sec / 1e9
@@ -114,11 +117,24 @@ def main():
     extra["copy_GBps"] = copy_gbs
     log("copy ceiling: %.0f GB/s" % copy_gbs)
 
+    if args.tile_sweep:
+        rows = []
+        for solver, NN in (("ph", 32), ("ph", 64), ("cr", 64), ("ph", 16)):
+            for tg in (16, 24, 32, 48, 64, 96, 128):
+                p2 = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=solver, N=NN, tile_groups=tg)
+                s2 = timed_filter(S, torch, p2, x, y, max(3, args.steps // 2), 2)
+                rows.append({"solver": solver, "N": NN, "tile_groups": tg, "ms": s2 * 1e3,
+                             "GSps": n / s2 / 1e9})
+                log("tile %s N=%2d tile_groups=%3d: %.3f ms %.1f GS/s" % (solver, NN, tg, s2 * 1e3, n / s2 / 1e9))
+        extra["tile_sweep"] = rows
+
     if args.sweep:
         rows = []
-        for solver in ("ph", "cr"):
+        for solver in ("ph", "cr", "phd"):
             for NN in (8, 16, 32, 64):
                 for cd in ("f64", "f32"):
+                    if solver == "phd" and (NN < 16 or cd == "f32"):
+                        continue      # the deferred form: FP64 arithmetic, N >= 16
                     p2 = S.Plan(sos, io_dtype="f32", compute_dtype=cd, solver=solver, N=NN)
                     s2 = timed_filter(S, torch, p2, x, y, max(3, args.steps // 2), 2)
                     rows.append({"solver": solver, "N": NN, "compute": cd,
@@ -158,7 +174,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain cascade, 1 channel x 2^%d float32 samples, K=8, "
                                "pole radius U[0.8,0.98], seed 0" % args.log2n,
-                   "io_dtype": "f32", "N": info.N, "L": 64, "solver": args.solver},
+                   "io_dtype": "f32", "N": info.N, "L": info.L, "solver": args.solver},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,

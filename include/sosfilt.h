@@ -57,9 +57,13 @@ typedef enum {
 typedef enum { SOS_F32 = 0, SOS_F64 = 1 } sos_dtype;
 
 typedef enum {
-    SOS_AUTO = 0,   /* cyclic reduction, with PH for sections the CR guard rejects */
-    SOS_PH = 1,     /* PH factorisation (Section VI-B) for every section */
-    SOS_CR = 2      /* cyclic reduction (Section VI-C), guard still applies */
+    SOS_AUTO = 0,        /* cyclic reduction, with PH for sections the CR guard rejects */
+    SOS_PH = 1,          /* PH factorisation (Section VI-B) for every section */
+    SOS_CR = 2,          /* cyclic reduction (Section VI-C), guard still applies */
+    SOS_PH_DEFERRED = 3  /* PH with the homogeneous correction (eq. PH_forward) of all
+                            sections deferred to the end of the cascade and applied as
+                            one FP64 matrix-core product; FP64 arithmetic, N >= 16,
+                            K <= 16 */
 } sos_solver;
 
 /* Plan flags. */
@@ -123,7 +127,8 @@ sos_status sos_plan_query(sos_plan_t plan, sos_plan_info *info, int32_t *solver)
 
 /* Host FP64 tables, for inspection and tests.  Copies min(count, size) values
  * into out (host) and returns the table's size in *size (host, may be NULL).
- * section is ignored for SOS_TABLE_TRANSITION. */
+ * section is ignored for SOS_TABLE_TRANSITION and SOS_TABLE_THETA; the
+ * SOS_PH_DEFERRED tables exist only for plans with that solver. */
 typedef enum {
     SOS_TABLE_ROWS = 0,        /* 5: b0 b1 b2 a1 a2 as the kernel uses them */
     SOS_TABLE_U1 = 1,          /* N: u_{1,m} */
@@ -133,7 +138,12 @@ typedef enum {
     SOS_TABLE_CR_LEVELS = 5,   /* 4 log2 N: per level f/e, e, c, d */
     SOS_TABLE_CR_TERMINAL = 6, /* 2: e, f of eq. cr_terminal_block */
     SOS_TABLE_CR_POWERS = 7,   /* 4 log2 L = 16: T^(2^j), T = [[0, 1], [-f, -e]] */
-    SOS_TABLE_TRANSITION = 8   /* (2K)^2: one-step cascade state transition, row-major */
+    SOS_TABLE_TRANSITION = 8,  /* (2K)^2: one-step cascade state transition, row-major */
+    SOS_TABLE_THETA = 9,       /* N x 2K: SOS_PH_DEFERRED correction matrix, row-major
+                                  (response of the last section at block m to a unit entry
+                                  state component (y_j[-2], y_j[-1])); section ignored */
+    SOS_TABLE_COUPLING = 10    /* 4k: for section k, the 2x2 blocks (j = 0..k-1) giving its
+                                  terminal values from section j's entry state */
 } sos_table;
 
 sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,

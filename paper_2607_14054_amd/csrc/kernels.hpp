@@ -92,27 +92,43 @@ __device__ __forceinline__ void row_scan_2x2(T &p, T &q, const T *__restrict__ p
 // bounds that lookahead (and the register pressure it costs).
 constexpr int kSchedChunk = SOSF_SCHED_CHUNK;
 
-// Non-recursive stage (eq. feedforward_block_uniform), computed block by
-// block in ascending m together with the first recursive pass, so that the
-// tile is updated in place with a few rolling registers:
+// Non-recursive stage (eq. feedforward_block_uniform) in place, in
+// descending m so that every input is read before it is overwritten:
 //   v_m = b0 x_m + b1 x_{m-1} + b2 x_{m-2},
 // with the extended blocks x_{-1} = R x_{N-1} + e0 x[-1] and
-// x_{-2} = R x_{N-2} + e0 x[-2]; the previous group's outputs enter the
-// first element of blocks 0 and 1: v_0[0] -= a1 y[-1] + a2 y[-2],
-// v_1[0] -= a2 y[-1].
-template <typename T, bool B0ONE>
-struct Fir {
-  T b0, b1, b2;
-  T p1, p2;   // x_{m-1}, x_{m-2} (original inputs)
-  __device__ __forceinline__ T next(T xm) {
-    T v = B0ONE ? xm : b0 * xm;
+// x_{-2} = R x_{N-2} + e0 x[-2] passed in.  The recursive pass that follows
+// then also runs in place, so no register is live twice and the section
+// loop needs no copies.
+template <int N, typename T, bool B0ONE>
+__device__ __forceinline__ void fir_pass(T (&X)[N], const T *__restrict__ c, T xm1, T xm2) {
+  const T b0 = c[OFF_B0], b1 = c[OFF_B1], b2 = c[OFF_B2];
+#pragma unroll
+  for (int m = N - 1; m >= 0; --m) {
+    const T p1 = m >= 1 ? X[m - 1] : xm1;
+    const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? xm1 : xm2);
+    T v = B0ONE ? X[m] : b0 * X[m];
     v = fma_(b1, p1, v);
-    v = fma_(b2, p2, v);
-    p2 = p1;
-    p1 = xm;
-    return v;
+    X[m] = fma_(b2, p2, v);
+    if ((m & (kSchedChunk - 1)) == 0) __builtin_amdgcn_sched_barrier(0);
   }
-};
+}
+
+// Particular solution, eq. particular_recurrence, in place:
+// w_m = v_m - a1 w_{m-1} - a2 w_{m-2} from (w_{-1}, w_{-2}) = (w1, w2).
+// The y[n-2] term is added first, so one FMA per step is on the
+// recurrence's critical path.
+template <int N, typename T>
+__device__ __forceinline__ void particular_pass(T (&X)[N], T a1, T a2, T w1, T w2) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    T v = fma_(-a2, w2, X[m]);
+    v = fma_(-a1, w1, v);
+    X[m] = v;
+    w2 = w1;
+    w1 = v;
+    if ((m & (kSchedChunk - 1)) == kSchedChunk - 1) __builtin_amdgcn_sched_barrier(0);
+  }
+}
 
 // PH factorisation (Section VI-B) of one section on one group per row.
 template <int N, typename T, bool B0ONE>
@@ -120,24 +136,14 @@ __device__ __forceinline__ void ph_section(T (&X)[N], const T *__restrict__ c, T
   const T a1 = c[OFF_A1], a2 = c[OFF_A2];
   const T xs2 = st[0], xs1 = st[1], ys2 = st[2], ys1 = st[3];
   const T nx2 = last_of_row(X[N - 2]), nx1 = last_of_row(X[N - 1]);
-  Fir<T, B0ONE> fir{c[OFF_B0], c[OFF_B1], c[OFF_B2], shift_r(X[N - 1], xs1),
-                    shift_r(X[N - 2], xs2)};
-  // step 1, eq. particular_recurrence: w_m = v_m - a1 w_{m-1} - a2 w_{m-2},
-  // every lane a zero-state recurrence over its own N samples.  On lane 0
-  // of the row the recurrence starts from the previous group's outputs,
-  // which is the same arithmetic as the state correction of v_0[0], v_1[0].
+  fir_pass<N, T, B0ONE>(X, c, shift_r(X[N - 1], xs1), shift_r(X[N - 2], xs2));
+  __builtin_amdgcn_sched_barrier(0);
+  // step 1, eq. particular_recurrence: every lane a zero-state recurrence
+  // over its own N samples.  On lane 0 of the row the recurrence starts from
+  // the previous group's outputs, which is the same arithmetic as the state
+  // correction of v_0[0] and v_1[0].
   const bool l0 = row_lane() == 0;
-  T w1 = l0 ? ys1 : T(0), w2 = l0 ? ys2 : T(0);
-#pragma unroll
-  for (int m = 0; m < N; ++m) {
-    T w = fir.next(X[m]);
-    w = fma_(-a1, w1, w);
-    w = fma_(-a2, w2, w);
-    X[m] = w;
-    w2 = w1;
-    w1 = w;
-    if ((m & (kSchedChunk - 1)) == kSchedChunk - 1) __builtin_amdgcn_sched_barrier(0);
-  }
+  particular_pass<N, T>(X, a1, a2, l0 ? ys1 : T(0), l0 ? ys2 : T(0));
   // step 2, eq. recursive_doubling_equation: y_e[l] = w_e[l] - C y_e[l-1]
   // along the row, with y_e[l] = (y[(l+1)N-2], y[(l+1)N-1])
   T p = X[N - 2], q = X[N - 1];
@@ -167,41 +173,15 @@ __device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T
   const T a1 = c[OFF_A1], a2 = c[OFF_A2];
   const T xs2 = st[0], xs1 = st[1], ys2 = st[2], ys1 = st[3];
   const T nx2 = last_of_row(X[N - 2]), nx1 = last_of_row(X[N - 1]);
+  fir_pass<N, T, B0ONE>(X, c, shift_r(X[N - 1], xs1), shift_r(X[N - 2], xs2));
+  __builtin_amdgcn_sched_barrier(0);
+  // the previous group's outputs enter the first element of blocks 0 and 1
   const bool l0 = row_lane() == 0;
-  Fir<T, B0ONE> fir{c[OFF_B0], c[OFF_B1], c[OFF_B2], shift_r(X[N - 1], xs1),
-                    shift_r(X[N - 2], xs2)};
-  // v_{N-1} first: level 0 needs R v_{N-1} for its first row
-  T vlast;
-  {
-    T v = B0ONE ? X[N - 1] : fir.b0 * X[N - 1];
-    v = fma_(fir.b1, X[N - 2], v);
-    vlast = fma_(fir.b2, X[N - 3], v);
-  }
-  // non-recursive stage fused with reduction level 0 (s = 1): even rows
-  // v'_m = v_m - (f/e) v_{m-1} (row 0 takes R v_{N-1}), odd rows
-  // v'_m = v_m - e v'_{m-1}
-  {
-    const T fe = c[OFF_CR_LVL], e = c[OFF_CR_LVL + 1];
-    T prev_odd = shr<1>(vlast);
+  X[0] -= l0 ? fma_(a1, ys1, a2 * ys2) : T(0);
+  X[1] -= l0 ? a2 * ys1 : T(0);
+  // reduction, eq. cr_coeff_update coefficients per level
 #pragma unroll
-    for (int m = 0; m < N; m += 2) {
-      T ve = fir.next(X[m]);
-      T vo = (m + 1 == N - 1) ? vlast : fir.next(X[m + 1]);
-      if (m + 1 == N - 1) fir.next(X[m + 1]);
-      if (m == 0) {
-        ve -= l0 ? fma_(a1, ys1, a2 * ys2) : T(0);
-        vo -= l0 ? a2 * ys1 : T(0);
-      }
-      ve = fma_(-fe, prev_odd, ve);
-      prev_odd = vo;
-      X[m] = ve;
-      X[m + 1] = fma_(-e, ve, vo);
-      if ((m & (kSchedChunk - 1)) == kSchedChunk - 2) __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-  // reduction levels 1 .. log2 N - 1, eq. cr_coeff_update coefficients
-#pragma unroll
-  for (int i = 1; i < LG; ++i) {
+  for (int i = 0; i < LG; ++i) {
     const int s = 1 << i, ni = N >> i;
     const T fe = c[OFF_CR_LVL + 4 * i], e = c[OFF_CR_LVL + 4 * i + 1];
     const T wrap = shr<1>(X[N - 1]);

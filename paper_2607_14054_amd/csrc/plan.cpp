@@ -217,4 +217,56 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
   return SOS_OK;
 }
 
+// Tables of the deferred homogeneous correction.  Inside a group each lane
+// runs the whole cascade from zero state over its N samples (raw input
+// history taken from the data); the true output is that zero-state output
+// plus the response to the segment's entry state, the 2K values
+// (y_j[-2], y_j[-1]) of every section j.  A unit entry component of section
+// j sets y_j's history and, because x_{j+1} = y_j, x_{j+1}'s history too.
+//   theta[m][2j+c]      response of the last section at block m (m < N)
+//   coupling(j, k)[t][c] response of section k at block N-2+t, for j < k
+// (the diagonal blocks j = k are -C of the PH factorisation).
+void build_deferred_tables(sos_plan_s &p) {
+  const int K = p.K, N = p.N, D = 2 * K;
+  p.kb = (D + 3) / 4;
+  p.theta.assign((size_t)N * D, 0.0);
+  p.coupling.assign((size_t)2 * K * (K - 1), 0.0);
+  std::vector<double> out((size_t)K * N);
+  for (int col = 0; col < D; ++col) {
+    const int j = col / 2, c = col % 2;
+    std::vector<double> xh(2 * K, 0.0), yh(2 * K, 0.0);   // (x[-2], x[-1]), (y[-2], y[-1])
+    yh[2 * j + c] = 1.0;
+    if (j + 1 < K) xh[2 * (j + 1) + c] = 1.0;
+    for (int k = 0; k < K; ++k) {
+      const double *o = &p.rows[5 * k];
+      double x2 = xh[2 * k], x1 = xh[2 * k + 1], y2 = yh[2 * k], y1 = yh[2 * k + 1];
+      for (int m = 0; m < N; ++m) {
+        const double in = (k == 0) ? 0.0 : out[(size_t)(k - 1) * N + m];
+        const double v = o[0] * in + o[1] * x1 + o[2] * x2 - o[3] * y1 - o[4] * y2;
+        x2 = x1; x1 = in; y2 = y1; y1 = v;
+        out[(size_t)k * N + m] = v;
+      }
+    }
+    for (int m = 0; m < N; ++m) p.theta[(size_t)m * D + col] = out[(size_t)(K - 1) * N + m];
+    for (int k = j + 1; k < K; ++k) {
+      double *blk = &p.coupling[4 * ((size_t)k * (k - 1) / 2 + j)];
+      blk[0 * 2 + c] = out[(size_t)k * N + N - 2];
+      blk[1 * 2 + c] = out[(size_t)k * N + N - 1];
+    }
+  }
+  // MFMA A operand (16 x 4 FP64 tile, lane l holds A[l % 16][l / 16]) for
+  // each 16-block of m and 4-block of state components, zero-padded to the
+  // kernel's compile-time block count (2, 4 or 8)
+  const int MB = N / 16;
+  const int kbm = K <= 4 ? 2 : (K <= 8 ? 4 : 8);
+  p.kb = kbm;
+  p.theta_mfma.assign((size_t)(MB > 0 ? MB : 0) * kbm * 64, 0.0);
+  for (int mb = 0; mb < MB; ++mb)
+    for (int b = 0; b < kbm; ++b)
+      for (int l = 0; l < 64; ++l) {
+        const int m = 16 * mb + l % 16, comp = 4 * b + l / 16;
+        p.theta_mfma[((size_t)mb * kbm + b) * 64 + l] = comp < D ? p.theta[(size_t)m * D + comp] : 0.0;
+      }
+}
+
 }  // namespace sosf

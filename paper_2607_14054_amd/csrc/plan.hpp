@@ -42,6 +42,13 @@ struct sos_plan_s {
   std::vector<double> table;       // K x stride, FP64 master copy of the device table
   int stride = 0;
   std::vector<double> phi;         // (2K)^2 one-step cascade state transition
+  // deferred homogeneous correction (solver SOS_PH_DEFERRED, N >= 16)
+  std::vector<double> theta;       // N x 2K: output at block m from a unit entry state
+  std::vector<double> theta_mfma;  // theta in MFMA A-operand order [mb][kb][lane]
+  std::vector<double> coupling;    // K(K-1)/2 blocks of 2x2: terminal of k from entry state j < k
+  int kb = 0;                      // 4-wide state blocks: ceil(2K / 4)
+  void *d_theta = nullptr;
+  void *d_coupling = nullptr;
   int64_t warm = 0;                // run-in samples, multiple of N*L
   double warm_norm = 0.0;
   int device = -1;
@@ -51,4 +58,5 @@ struct sos_plan_s {
 
 namespace sosf {
 sos_status build_plan_tables(sos_plan_s &p, const double *sos);
+void build_deferred_tables(sos_plan_s &p);
 }

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "kernels.hpp"
+#include "kernels_deferred.hpp"
 #include "plan.hpp"
 
 using namespace sosf;
@@ -37,6 +38,15 @@ sos_status upload(sos_plan_s &p) {
   }
   e2 = hipMemcpy(p.d_solver, p.solver.data(), (size_t)p.K * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e1 != hipSuccess || e2 != hipSuccess) return SOS_E_DEVICE;
+  if (p.solver_opt == SOS_PH_DEFERRED) {
+    const size_t nt = p.theta_mfma.size(), nc = p.coupling.size() ? p.coupling.size() : 1;
+    if (hipMalloc(&p.d_theta, nt * 8) != hipSuccess) { p.d_theta = nullptr; return SOS_E_NOMEM; }
+    if (hipMalloc(&p.d_coupling, nc * 8) != hipSuccess) { p.d_coupling = nullptr; return SOS_E_NOMEM; }
+    if (hipMemcpy(p.d_theta, p.theta_mfma.data(), nt * 8, hipMemcpyHostToDevice) != hipSuccess) return SOS_E_DEVICE;
+    if (p.coupling.size() &&
+        hipMemcpy(p.d_coupling, p.coupling.data(), p.coupling.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return SOS_E_DEVICE;
+  }
   return SOS_OK;
 }
 
@@ -69,6 +79,44 @@ sos_status launch_n(const Ptrs &q, const FiltArgs &a, bool b0one, int mix, hipSt
   if (mix == SOS_PH) return launch_s<N, TI, T, SOS_PH>(q, a, b0one, s);
   if (mix == SOS_CR) return launch_s<N, TI, T, SOS_CR>(q, a, b0one, s);
   return launch_s<N, TI, T, SOS_AUTO>(q, a, b0one, s);
+}
+
+template <int N, typename TI, int KBM>
+sos_status launch_deferred_k(const Ptrs &q, const void *coup, const void *theta, const FiltArgs &a,
+                             bool b0one, hipStream_t s) {
+  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
+  const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
+  const TI *x = static_cast<const TI *>(q.x);
+  TI *y = static_cast<TI *>(q.y);
+  const double *tab = static_cast<const double *>(q.tab);
+  const double *cp = static_cast<const double *>(coup), *th = static_cast<const double *>(theta);
+  const unsigned lds = (unsigned)deferred_lds_bytes<N, TI>(a.K, KBM);
+  if (b0one)
+    hipLaunchKernelGGL((sos_rows_deferred_kernel<N, TI, true, KBM>), dim3((unsigned)blocks),
+                       dim3(kWavesPerBlock * 64), lds, s, x, y, tab, cp, th, a);
+  else
+    hipLaunchKernelGGL((sos_rows_deferred_kernel<N, TI, false, KBM>), dim3((unsigned)blocks),
+                       dim3(kWavesPerBlock * 64), lds, s, x, y, tab, cp, th, a);
+  return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+}
+
+template <int N, typename TI>
+sos_status launch_deferred_n(const Ptrs &q, const void *coup, const void *theta, const FiltArgs &a,
+                             bool b0one, hipStream_t s) {
+  if (a.K <= 4) return launch_deferred_k<N, TI, 2>(q, coup, theta, a, b0one, s);
+  if (a.K <= 8) return launch_deferred_k<N, TI, 4>(q, coup, theta, a, b0one, s);
+  return launch_deferred_k<N, TI, 8>(q, coup, theta, a, b0one, s);
+}
+
+template <typename TI>
+sos_status launch_deferred(int N, const Ptrs &q, const void *coup, const void *theta,
+                           const FiltArgs &a, bool b0one, hipStream_t s) {
+  switch (N) {
+    case 16: return launch_deferred_n<16, TI>(q, coup, theta, a, b0one, s);
+    case 32: return launch_deferred_n<32, TI>(q, coup, theta, a, b0one, s);
+    case 64: return launch_deferred_n<64, TI>(q, coup, theta, a, b0one, s);
+    default: return SOS_E_UNSUPPORTED;
+  }
 }
 
 template <typename TI, typename T>
@@ -122,10 +170,12 @@ sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan
   if (o.L == 0) o.L = 16;
   if (o.io_dtype != SOS_F32 && o.io_dtype != SOS_F64) return SOS_E_ARG;
   if (o.compute_dtype != SOS_F32 && o.compute_dtype != SOS_F64) return SOS_E_ARG;
-  if (o.solver < SOS_AUTO || o.solver > SOS_CR) return SOS_E_ARG;
+  if (o.solver < SOS_AUTO || o.solver > SOS_PH_DEFERRED) return SOS_E_ARG;
   if (o.tile_groups < 0) return SOS_E_ARG;
   if (!pow2_in(o.N, 8, 64) || o.L != kL) return SOS_E_UNSUPPORTED;
   if (o.io_dtype == SOS_F64 && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
+  const bool deferred_ok = o.compute_dtype == SOS_F64 && o.N >= 16 && K <= 16;
+  if (o.solver == SOS_PH_DEFERRED && !deferred_ok) return SOS_E_UNSUPPORTED;
   sos_plan_s *p = new (std::nothrow) sos_plan_s;
   if (!p) return SOS_E_NOMEM;
   p->K = K;
@@ -138,6 +188,10 @@ sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan
   p->tile_groups = o.tile_groups;
   p->flags = o.flags;
   sos_status st = build_plan_tables(*p, sos);
+  if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED) {
+    build_deferred_tables(*p);
+    for (int k = 0; k < K; ++k) p->solver[k] = SOS_PH_DEFERRED;
+  }
   if (st == SOS_OK && !(o.flags & SOS_FLAG_HOST_ONLY)) st = upload(*p);
   if (st != SOS_OK) {
     sos_plan_destroy(p);
@@ -155,6 +209,8 @@ sos_status sos_plan_destroy(sos_plan_t p) {
     if (p->device >= 0 && cur != p->device) hipSetDevice(p->device);
     if (p->d_table) hipFree(p->d_table);
     if (p->d_solver) hipFree(p->d_solver);
+    if (p->d_theta) hipFree(p->d_theta);
+    if (p->d_coupling) hipFree(p->d_coupling);
     if (p->device >= 0 && cur >= 0 && cur != p->device) hipSetDevice(cur);
   }
   delete p;
@@ -182,7 +238,8 @@ sos_status sos_plan_query(sos_plan_t p, sos_plan_info *info, int32_t *solver) {
 sos_status sos_plan_table(sos_plan_t p, int32_t table, int32_t section, double *out,
                           int32_t count, int32_t *size) {
   if (!p || count < 0 || (count > 0 && !out)) return SOS_E_ARG;
-  if (table != SOS_TABLE_TRANSITION && (section < 0 || section >= p->K)) return SOS_E_ARG;
+  if (table != SOS_TABLE_TRANSITION && table != SOS_TABLE_THETA && (section < 0 || section >= p->K))
+    return SOS_E_ARG;
   const double *t = p->table.data() + (size_t)(section < 0 ? 0 : section) * p->stride;
   std::vector<double> buf;
   switch (table) {
@@ -195,6 +252,15 @@ sos_status sos_plan_table(sos_plan_t p, int32_t table, int32_t section, double *
     case SOS_TABLE_CR_TERMINAL: buf.assign(p->cr_term.begin() + 2 * section, p->cr_term.begin() + 2 * section + 2); break;
     case SOS_TABLE_CR_POWERS: buf.assign(t + OFF_CR_POW, t + OFF_CR_POW + 4 * kLogL); break;
     case SOS_TABLE_TRANSITION: buf = p->phi; break;
+    case SOS_TABLE_THETA:
+      if (p->theta.empty()) return SOS_E_ARG;
+      buf = p->theta;
+      break;
+    case SOS_TABLE_COUPLING:
+      if (p->theta.empty()) return SOS_E_ARG;
+      buf.assign(p->coupling.begin() + 2 * section * (section - 1),
+                 p->coupling.begin() + 2 * section * (section + 1));
+      break;
     default: return SOS_E_ARG;
   }
   if (size) *size = (int32_t)buf.size();
@@ -231,6 +297,10 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
   a.gain = p->gain;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool b0one = p->b0_factored;
+  if (p->solver_opt == SOS_PH_DEFERRED) {
+    if (p->io_dtype == SOS_F32) return launch_deferred<float>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);
+    return launch_deferred<double>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);
+  }
   // one solver for every section lets the kernel drop the per-section branch
   int mix = p->solver[0];
   for (int k = 1; k < p->K; ++k)

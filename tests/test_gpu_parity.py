@@ -38,9 +38,11 @@ def run(sos, x_np, **kw):
     return y.cpu().numpy(), p
 
 
-@pytest.mark.parametrize("solver", ["ph", "cr"])
+@pytest.mark.parametrize("solver", ["ph", "cr", "phd"])
 @pytest.mark.parametrize("N", [8, 16, 32, 64])
 def test_tiny_config_f64(solver, N):
+    if solver == "phd" and N < 16:
+        pytest.skip("the deferred correction works on 16-block tiles")
     c = W.CONFIGS["tiny"]
     sos = W.make_sos(c.K, c.r_lo, c.r_hi, c.seed)
     x = W.make_signal(c.n, c.seed, np.float64)
@@ -51,8 +53,8 @@ def test_tiny_config_f64(solver, N):
     assert err < 1e-12
 
 
-@pytest.mark.parametrize("solver", ["ph", "cr"])
-@pytest.mark.parametrize("N", [8, 32])
+@pytest.mark.parametrize("solver,N", [("ph", 8), ("ph", 32), ("cr", 8), ("cr", 32),
+                                      ("phd", 16), ("phd", 32), ("phd", 64)])
 def test_f32_io_f64_compute(solver, N):
     sos = W.make_sos(8, 0.8, 0.98, 0)
     x = W.make_signal(2 ** 20 + 12345, 0, np.float32)       # ragged tail, many tiles
@@ -78,8 +80,8 @@ def test_f32_arithmetic_near_fp32_floor(solver):
 def test_ragged_lengths(n):
     sos = W.make_sos(4, 0.5, 0.95, 9)
     x = W.make_signal(n, 3, np.float64)
-    for solver in ("ph", "cr"):
-        y, _ = run(sos, x, compute_dtype="f64", solver=solver, N=8, tile_groups=2)
+    for solver, N in (("ph", 8), ("cr", 8), ("phd", 16)):
+        y, _ = run(sos, x, compute_dtype="f64", solver=solver, N=N, tile_groups=2)
         assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12, (n, solver)
 
 
@@ -90,25 +92,27 @@ def test_zero_length_is_noop():
     assert y.numel() == 0
 
 
-@pytest.mark.parametrize("K", [1, 2, 16])
-def test_section_counts(K):
+@pytest.mark.parametrize("solver", ["cr", "phd"])
+@pytest.mark.parametrize("K", [1, 2, 3, 16])
+def test_section_counts(K, solver):
     sos = W.make_sos(K, 0.5, 0.95, 11)
     x = W.make_signal(50000, 4, np.float64)
-    y, _ = run(sos, x, compute_dtype="f64", N=16, tile_groups=4)
+    y, _ = run(sos, x, compute_dtype="f64", solver=solver, N=16, tile_groups=4)
     assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12
 
 
+@pytest.mark.parametrize("solver,N", [("cr", 8), ("phd", 16)])
 @pytest.mark.parametrize("offset", [-2, -1, 0, 1])
-def test_impulse_across_tile_boundary(offset):
+def test_impulse_across_tile_boundary(offset, solver, N):
     """An impulse just before/after a tile boundary reproduces the oracle's
     impulse response across the boundary (run-in carry)."""
     sos = W.make_sos(8, 0.5, 0.95, 13)
-    N, tg = 8, 4
+    tg = 4
     tile = N * 16 * tg          # group = N L samples, L = 16
     n = 6 * tile
     x = np.zeros(n)
     x[3 * tile + offset] = 1.0
-    y, _ = run(sos, x, compute_dtype="f64", solver="cr", N=N, tile_groups=tg)
+    y, _ = run(sos, x, compute_dtype="f64", solver=solver, N=N, tile_groups=tg)
     ref = oracle.sosfilt(x, sos)
     assert np.max(np.abs(y - ref)) < 1e-12 * np.max(np.abs(ref))
 
@@ -124,25 +128,36 @@ def test_cr_hazard_angles(theta):
     y, p = run(sos, x, compute_dtype="f64", solver="cr", N=64)
     assert p.info().solver[0] == "ph"
     assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12
+    # the deferred PH form has no division and needs no guard
+    y, p = run(sos, x, compute_dtype="f64", solver="phd", N=64)
+    assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12
 
 
-def test_unfactored_b0():
+@pytest.mark.parametrize("solver", ["cr", "phd"])
+def test_unfactored_b0(solver):
     sos = W.make_sos(4, 0.5, 0.95, 19)
     sos[2, 0:3] = [0.0, 0.7, -0.2]
     x = W.make_signal(30000, 6, np.float64)
-    y, p = run(sos, x, compute_dtype="f64", N=32)
+    y, p = run(sos, x, compute_dtype="f64", solver=solver, N=32)
     assert not p.info().b0_factored
     assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12
 
 
-def test_slow_pole_long_run_in():
-    """r = 0.9995: the run-in spans many tiles."""
+@pytest.mark.parametrize("solver,N,tol", [("cr", 8, 1e-11), ("ph", 16, 2e-10), ("phd", 16, 2e-10)])
+def test_slow_pole_long_run_in(solver, N, tol):
+    """r = 0.9995, theta = 0.01: the run-in spans many tiles.  This pole is
+    close to a double pole at z = 1, where the PH terminal scan (powers of
+    -C) loses digits: the FP64 model of the paper's PH at N = 16 is itself
+    6.6e-11 off an extended-precision reference here, cyclic reduction
+    1.6e-12 and the oracle 3e-13.  The PH-family bound is set from that."""
     r, th = 0.9995, 0.01
     sec = np.array([[1.0, 0.0, 0.0, 1.0, -2 * r * math.cos(th), r * r]])
     x = W.make_signal(2 ** 19, 7, np.float64)
-    y, p = run(sec, x, compute_dtype="f64", N=8, tile_groups=4)
+    y, p = run(sec, x, compute_dtype="f64", solver=solver, N=N, tile_groups=4)
     assert p.info().warm_samples > 4 * 8 * 64
-    assert oracle.rel_rms(y, oracle.sosfilt(x, sec)) < 1e-11
+    err = oracle.rel_rms(y, oracle.sosfilt(x, sec))
+    print("slow pole %s N=%d rel_rms=%.3e" % (solver, N, err))
+    assert err < tol
 
 
 def test_bad_arguments_rejected():

@@ -147,7 +147,8 @@ def test_cr_guard_falls_back_to_ph(theta, N):
     r = 0.9
     sec = np.array([[1.0, 0.0, 0.0, 1.0, -2 * r * math.cos(theta), r * r]])
     assert plan(sec, N=N, solver="cr").info().solver == ["ph"]
-    assert plan(sec, N=N, solver="auto").info().solver == ["ph"]
+    # auto: FP32 arithmetic (no deferred form) takes cyclic reduction with the guard
+    assert plan(sec, N=N, solver="auto", compute_dtype="f32").info().solver == ["ph"]
 
 
 def test_cr_flush_of_negligible_levels():
@@ -205,3 +206,53 @@ def test_run_in_truncation_is_negligible_in_the_oracle():
     pre = np.concatenate([np.random.default_rng(1).standard_normal(20000), x])
     late = oracle.sosfilt(pre, sos)[20000 + info.warm_samples:]
     assert oracle.rel_rms(late, full) < 1e-12
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_deferred_tables_match_oracle_responses(N):
+    """Theta and the coupling blocks of the deferred correction are the
+    cascade's responses to unit entry states, computed here by the oracle
+    (scaled rows: b0 factored, as the kernels use them)."""
+    K = 3
+    sos = W.make_sos(K, 0.5, 0.95, 41)
+    p = plan(sos, N=N, solver="phd")
+    assert p.info().solver == ["phd"] * K
+    rows, _ = M.normalise(sos)
+    scaled = np.column_stack([rows[:, 0:3], np.ones(K), rows[:, 3:5]])
+    Theta = p.table(S.SOS_TABLE_THETA).reshape(N, 2 * K)
+    for j in range(K):
+        for c in range(2):
+            zi = np.zeros((K, 4))
+            zi[j, 2 + c] = 1.0                  # y_j history
+            if j + 1 < K:
+                zi[j + 1, c] = 1.0              # x_{j+1} = y_j history
+            out = oracle.sosfilt(np.zeros(N), scaled, zi=zi)
+            assert np.allclose(Theta[:, 2 * j + c], out, rtol=1e-12, atol=1e-14)
+            for k in range(j + 1, K):
+                part = oracle.sosfilt(np.zeros(N), scaled[:k + 1], zi=zi[:k + 1])
+                blk = p.table(S.SOS_TABLE_COUPLING, k).reshape(k, 2, 2)[j]
+                assert np.allclose(blk[:, c], part[N - 2:N], rtol=1e-12, atol=1e-14)
+    # the diagonal blocks are -C of the PH factorisation
+    for k in range(K):
+        C = p.table(S.SOS_TABLE_C, k).reshape(2, 2)
+        zi = np.zeros((K, 4))
+        resp = np.zeros((2, 2))
+        for c in range(2):
+            zi[:] = 0.0
+            zi[k, 2 + c] = 1.0
+            out = oracle.sosfilt(np.zeros(N), scaled[k:k + 1], zi=zi[k:k + 1])
+            resp[:, c] = out[N - 2:N]
+        assert np.allclose(resp, -C, rtol=1e-12, atol=1e-15)
+
+
+def test_deferred_solver_limits():
+    sos = W.make_sos(4, 0.5, 0.9, 1)
+    for kw in (dict(N=8), dict(compute_dtype="f32", N=32)):
+        with pytest.raises(S.SosError) as e:
+            plan(sos, solver="phd", **kw)
+        assert e.value.code == S.SOS_E_UNSUPPORTED
+    with pytest.raises(S.SosError):
+        plan(W.make_sos(17, 0.5, 0.9, 1), solver="phd", N=16)
+    # auto takes cyclic reduction with the guard's PH fallback
+    assert set(plan(sos, N=32).info().solver) <= {"cr", "ph"}
+    assert set(plan(W.make_sos(17, 0.5, 0.9, 1), N=16).info().solver) <= {"cr", "ph"}
