@@ -64,17 +64,90 @@ def copy_ceiling(torch, x, y, steps=10):
     return 2 * x.numel() * x.element_size() / t / 1e9
 
 
+def bench_batch(S, W, torch, dev, args):
+    """The batched ragged workload: 4096 channels, lengths log-uniform in
+    [2^10, 2^22] float32 samples, K ~ U{1..16}, pole radius U[0.5, 0.95],
+    channel c drawn with seed c.  The autotuner picks N and the tile cap on
+    the real buffers; the chosen launch is captured in a HIP graph and the
+    graph replays are timed.  A sample of channels is checked against the
+    oracle (one channel at a time)."""
+    cfg = W.CONFIGS["batch"]
+    e = cfg.extra
+    lengths = W.batch_lengths(cfg.channels, e["log2_lo"], e["log2_hi"], cfg.seed)
+    Ks = W.batch_sections(cfg.channels, e["K_lo"], e["K_hi"], cfg.seed)
+    sos = [W.make_sos(int(Ks[c]), cfg.r_lo, cfg.r_hi, cfg.seed + c) for c in range(cfg.channels)]
+    total = int(lengths.sum())
+    t = time.time()
+    xb = torch.empty(total, dtype=torch.float32, device=dev)
+    off = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    for c in range(cfg.channels):
+        xb[off[c]:off[c] + lengths[c]] = torch.from_numpy(
+            W.make_signal(int(lengths[c]), cfg.seed + c, np.float32)).to(dev)
+    yb = torch.empty_like(xb)
+    log("batch: %d channels, %d samples, generated in %.1f s" % (cfg.channels, total, time.time() - t))
+    t = time.time()
+    best, rows = S.batch_tune(sos, lengths, xb, yb, Ns=(16, 32, 64), tiles=(0, 8, 16, 32), reps=3)
+    log("batch autotune (%.1f s): best N=%d tile_groups=%d %.3f ms" %
+        (time.time() - t, best["N"], best["tile_groups"], best["seconds"] * 1e3))
+    for r in rows:
+        log("  tune N=%2d tile_groups=%2d: %.3f ms  %.1f GS/s" %
+            (r["N"], r["tile_groups"], r["seconds"] * 1e3, total / r["seconds"] / 1e9))
+    plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver="ph", N=best["N"]) for s_ in sos]
+    b = S.Batch(plans, lengths, tile_groups=best["tile_groups"])
+    stream = torch.cuda.Stream()
+    S.filt_batched(b, xb, yb)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        S.filt_batched(b, xb, yb, stream=torch.cuda.current_stream())
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    steps = max(5, args.steps // 2)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            g.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / steps
+    gsps = total / sec / 1e9
+    log("batch graph replay: %.3f ms  %.1f GS/s  %.0f GB/s" % (sec * 1e3, gsps, 8.0 * total / sec / 1e9))
+    out = {"channels": cfg.channels, "samples": total, "mean_K": float(Ks.mean()), "N": best["N"],
+           "tile_groups": best["tile_groups"], "ms": sec * 1e3, "GSps": gsps,
+           "frac_hbm": 8.0 * total / sec / 1e9 / HBM_PEAK_GBS, "tune": rows}
+    if not args.no_cpu:
+        import oracle
+        pick = np.unique(np.concatenate([np.argsort(lengths)[[0, -1]], np.arange(0, cfg.channels, 512)]))
+        worst = 0.0
+        for c in pick:
+            x_c = W.make_signal(int(lengths[c]), cfg.seed + c, np.float32)
+            ref = oracle.sosfilt(x_c, sos[c])
+            got = yb[off[c]:off[c] + lengths[c]].cpu().numpy()
+            worst = max(worst, oracle.rel_rms(got, ref))
+        out["rel_rms_max_sampled"] = worst
+        out["checked_channels"] = [int(c) for c in pick]
+        log("batch: worst rel_rms over %d sampled channels %.3e" % (len(pick), worst))
+    del xb, yb
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--log2n", type=int, default=28)
-    ap.add_argument("--solver", default="ph")
+    ap.add_argument("--solver", default="auto")
     ap.add_argument("--N", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0, help="groups per tile (0: the library's choice)")
     ap.add_argument("--tile-sweep", action="store_true", help="time the main plan at several tile sizes")
     ap.add_argument("--sweep", action="store_true", help="also time PH and CR at every N")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the batched ragged workload (4096 channels), autotuned, graph-replayed")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
@@ -100,15 +173,16 @@ def main():
     x = torch.from_numpy(x_np).to(dev)
     y = torch.empty_like(x)
 
-    N = args.N or 32
+    N = args.N or 64
     plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=args.solver, N=N,
                   tile_groups=args.tile)
     info = plan.info()
     sec = timed_filter(S, torch, plan, x, y, args.steps, args.warmup)
     gsps = n / sec / 1e9
     achieved = 8.0 * n / sec / 1e9
-    log("main: N=%d solvers=%s warm=%d  %.3f ms/step  %.1f GS/s  %.0f GB/s"
-        % (N, info.solver, info.warm_samples, sec * 1e3, gsps, achieved))
+    log("main: N=%d solvers=%s warm=%d tile=%d waves/SIMD=%d  %.3f ms/step  %.1f GS/s  %.0f GB/s"
+        % (N, info.solver, info.warm_samples, plan.tile(n), info.waves_per_simd, sec * 1e3, gsps,
+           achieved))
     y_np = y.cpu().numpy()
 
     extra = {"plan": {"N": info.N, "solver": info.solver, "warm_samples": info.warm_samples,
@@ -137,11 +211,19 @@ def main():
                         continue      # the deferred form: FP64 arithmetic, N >= 16
                     p2 = S.Plan(sos, io_dtype="f32", compute_dtype=cd, solver=solver, N=NN)
                     s2 = timed_filter(S, torch, p2, x, y, max(3, args.steps // 2), 2)
-                    rows.append({"solver": solver, "N": NN, "compute": cd,
+                    i2 = p2.info()
+                    rows.append({"solver": solver, "N": NN, "compute": cd, "tile": p2.tile(n),
+                                 "waves_per_simd": i2.waves_per_simd,
                                  "ms": s2 * 1e3, "GSps": n / s2 / 1e9,
                                  "frac_hbm": 8.0 * n / s2 / 1e9 / HBM_PEAK_GBS})
-                    log("sweep %s N=%2d %s: %.3f ms %.1f GS/s" % (solver, NN, cd, s2 * 1e3, n / s2 / 1e9))
+                    log("sweep %s N=%2d %s: tile=%d occ=%d %.3f ms %.1f GS/s"
+                        % (solver, NN, cd, p2.tile(n) // (16 * NN), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
         extra["sweep"] = rows
+
+    if args.batch:
+        del x, y
+        torch.cuda.empty_cache()
+        extra["batch"] = bench_batch(S, W, torch, dev, args)
 
     cpu = None
     accuracy = {}

@@ -119,11 +119,19 @@ typedef struct {
                                    state exact to the working precision (a multiple of N*L) */
     double gain;                /* product of the b0 applied at the store (1 if not factored) */
     double transition_norm_W;   /* infinity norm of the cascade state transition over W samples */
+    int32_t simds;              /* SIMDs of the plan's device (0 for a host-only plan) */
+    int32_t waves_per_simd;     /* resident wavefronts per SIMD of the plan's kernel (0: host-only) */
 } sos_plan_info;
 
 /* info        host, filled in.
  * solver      host [K] or NULL: per section SOS_PH or SOS_CR as run. */
 sos_status sos_plan_query(sos_plan_t plan, sos_plan_info *info, int32_t *solver);
+
+/* Samples per tile that sos_filt uses for n samples: the plan's tile_groups,
+ * or the launch-shape model: the shortest tile that gives every SIMD at most
+ * m wavefronts (four tiles each), m the largest power of two of resident
+ * wavefronts per SIMD for the plan's kernel. */
+int64_t sos_plan_tile(sos_plan_t plan, int64_t n);
 
 /* Host FP64 tables, for inspection and tests.  Copies min(count, size) values
  * into out (host) and returns the table's size in *size (host, may be NULL).
@@ -164,6 +172,104 @@ size_t sos_workspace_size(sos_plan_t plan, int64_t n);
  */
 sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
                     void *workspace, sos_stream_t stream);
+
+/*
+ * Batched ragged channels (one launch for many independent signals, each
+ * with its own cascade).  The per-channel work is exactly sos_filt's: the
+ * same tile kernels (Sections V to VII) run on every channel, and only the
+ * scheduling is shared: each channel is cut into tiles, four tiles form one
+ * wavefront's work item, and the items of all channels are launched
+ * together, costliest first.
+ *
+ * sos_batch_plan -- fix the channel set and lengths once (allocates).
+ *
+ * plans    host [C]: channel c is filtered with plans[c] (the same plan may
+ *          serve several channels).  All plans must share N, io_dtype and
+ *          compute_dtype (else SOS_E_UNSUPPORTED) and none may use
+ *          SOS_PH_DEFERRED (SOS_E_UNSUPPORTED).  The plans must outlive the
+ *          batch: the batch refers to their device tables.
+ * C        number of channels, >= 1.
+ * n        host [C]: channel lengths, >= 0.
+ * offsets  host [C] or NULL: first sample of channel c in the concatenated
+ *          x and y buffers.  NULL packs the channels densely in order
+ *          (offset[c] = n[0] + ... + n[c-1]).  Channels must not overlap.
+ *          A channel whose offset is not a multiple of 16 bytes is still
+ *          exact but loads and stores element by element.
+ * opts     host, may be NULL: tile_groups > 0 caps the groups per tile
+ *          (0 = chosen from the total length); flags SOS_FLAG_HOST_ONLY
+ *          builds the schedule without device memory (queries only, and
+ *          host-only plans are then accepted).
+ * out      host, receives the batch handle (unchanged on error).
+ */
+typedef struct sos_batch_s *sos_batch_t;   /* opaque, owned by the caller */
+
+typedef struct {
+    int32_t tile_groups;
+    uint32_t flags;
+} sos_batch_opts;
+
+sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
+                          const int64_t *offsets, const sos_batch_opts *opts, sos_batch_t *out);
+
+/* Release the batch and its device schedule.  NULL is accepted. */
+sos_status sos_batch_destroy(sos_batch_t batch);
+
+/*
+ * sos_batch_query -- the schedule, for inspection and tests.  Every output
+ * pointer is host memory and may be NULL.
+ * total     samples spanned by the concatenated buffers (max offset + n).
+ * items     wavefront work items (4 tiles each) of the launch.
+ * offsets   [C]: first sample of each channel.
+ * tile      [C]: samples per tile of each channel (a multiple of 16 N).
+ * order     [C]: channel indices in launch order (costliest items first).
+ */
+sos_status sos_batch_query(sos_batch_t batch, int64_t *total, int64_t *items, int64_t *offsets,
+                           int64_t *tile, int32_t *order);
+
+/*
+ * sos_filt_batched -- y_c = cascade_c(x_c) for every channel, zero initial
+ * state, one kernel launch on `stream`.
+ *
+ * x, y       device, `total` samples of the plans' io_dtype each, channel c
+ *            at its offset; 16-byte aligned; must not overlap.  Samples of
+ *            y between channels are not written.
+ * workspace  unused (NULL).
+ * Asynchronous, no allocation, no synchronisation, so it can be captured
+ * in a HIP graph.  Calls with one batch may run concurrently.
+ */
+sos_status sos_filt_batched(sos_batch_t batch, const void *x, void *y, void *workspace,
+                            sos_stream_t stream);
+
+/*
+ * sos_batch_tune -- autotuner for batches: times sos_filt_batched for every
+ * candidate (N, tile_groups) on the caller's own buffers and reports the
+ * fastest.  L is not a candidate: it is fixed by the 16-lane DPP row.
+ *
+ * sos, K     host [C]: channel c's [K[c]][6] coefficient rows (as sos_plan).
+ * n, offsets as sos_batch_plan.
+ * base       host, may be NULL: dtypes and solver of the plans (its N and
+ *            tile_groups are ignored).
+ * Ns, nN     host: candidate N values; tiles, nt: candidate tile_groups
+ *            (0 = the library's choice).
+ * x, y       device buffers laid out as the batch (y is overwritten).
+ * reps       timed launches per candidate (after one untimed launch).
+ * results    host [nN * nt] or NULL: every candidate's seconds per launch,
+ *            N-major.
+ * best       host: the fastest candidate.
+ * Synchronous: it creates and destroys plans and batches (allocates) and
+ * waits for its own launches on `stream`.  Errors from any candidate's plan
+ * or launch end the search and are returned.
+ */
+typedef struct {
+    int32_t N;
+    int32_t tile_groups;
+    double seconds;
+} sos_tune_result;
+
+sos_status sos_batch_tune(const double *const *sos, const int32_t *K, int32_t C, const int64_t *n,
+                          const int64_t *offsets, const sos_opts *base, const int32_t *Ns, int32_t nN,
+                          const int32_t *tiles, int32_t nt, const void *x, void *y, int32_t reps,
+                          sos_stream_t stream, sos_tune_result *results, sos_tune_result *best);
 
 const char *sos_status_string(sos_status s);
 

@@ -31,6 +31,17 @@ namespace sosf {
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Coefficient tables are read through the constant address space: they are
+// never written while a kernel runs, and uniform loads from it go through
+// the scalar cache.
+template <typename T>
+using ctab = const __attribute__((address_space(4))) T *;
+
+template <typename T>
+__device__ __forceinline__ ctab<T> as_ctab(const T *p) {
+  return (ctab<T>)(p);
+}
+
 // ------------------------------------------------------------ lane moves
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
@@ -68,7 +79,7 @@ __device__ __forceinline__ T last_of_row(T v) { return dpp<0x15f, false>(v); }
 // 2-vectors z = (p, q): round j adds A^(2^j) times the value 2^j lanes below
 // (Kogge-Stone doubling).  pw holds A^(2^j) row-major for j = 0..3.
 template <typename T>
-__device__ __forceinline__ void row_scan_2x2(T &p, T &q, const T *__restrict__ pw) {
+__device__ __forceinline__ void row_scan_2x2(T &p, T &q, ctab<T> pw) {
 #define SOSF_ROUND(J, D)                                                          \
   {                                                                               \
     const T m00 = pw[4 * J], m01 = pw[4 * J + 1], m10 = pw[4 * J + 2], m11 = pw[4 * J + 3]; \
@@ -83,8 +94,10 @@ __device__ __forceinline__ void row_scan_2x2(T &p, T &q, const T *__restrict__ p
 
 // ------------------------------------------------------------ one section
 
-// Per-section boundary values carried from group to group (Section V):
-// st[0] = x[-2], st[1] = x[-1], st[2] = y[-2], st[3] = y[-1], one set per row.
+// Boundary values carried from group to group (Section V), one set per
+// row: x[-2], x[-1] of each section's input and y[-2], y[-1] of its output.
+// A section's input is the previous section's output, so the row keeps the
+// raw input's pair and every section's output pair (2 + 2K values).
 
 // The block loops below are fully unrolled; left alone, the scheduler hoists
 // the FIR of every block ahead of the recursion, which keeps inputs and FIR
@@ -100,7 +113,7 @@ constexpr int kSchedChunk = SOSF_SCHED_CHUNK;
 // then also runs in place, so no register is live twice and the section
 // loop needs no copies.
 template <int N, typename T, bool B0ONE>
-__device__ __forceinline__ void fir_pass(T (&X)[N], const T *__restrict__ c, T xm1, T xm2) {
+__device__ __forceinline__ void fir_pass(T (&X)[N], ctab<T> c, T xm1, T xm2) {
   const T b0 = c[OFF_B0], b1 = c[OFF_B1], b2 = c[OFF_B2];
 #pragma unroll
   for (int m = N - 1; m >= 0; --m) {
@@ -131,11 +144,15 @@ __device__ __forceinline__ void particular_pass(T (&X)[N], T a1, T a2, T w1, T w
 }
 
 // PH factorisation (Section VI-B) of one section on one group per row.
+//
+// Boundary values: (xs2, xs1) = (x[-2], x[-1]) of this section's input on
+// entry; ys = (y[-2], y[-1]) of its output, read and then replaced by the
+// group's last two outputs.  Section k's input is section k-1's output, so
+// on exit (xs2, xs1) holds the old ys: the next section's input state.
 template <int N, typename T, bool B0ONE>
-__device__ __forceinline__ void ph_section(T (&X)[N], const T *__restrict__ c, T *st) {
+__device__ __forceinline__ void ph_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1, T *ys) {
   const T a1 = c[OFF_A1], a2 = c[OFF_A2];
-  const T xs2 = st[0], xs1 = st[1], ys2 = st[2], ys1 = st[3];
-  const T nx2 = last_of_row(X[N - 2]), nx1 = last_of_row(X[N - 1]);
+  const T ys2 = ys[0], ys1 = ys[1];
   fir_pass<N, T, B0ONE>(X, c, shift_r(X[N - 1], xs1), shift_r(X[N - 2], xs2));
   __builtin_amdgcn_sched_barrier(0);
   // step 1, eq. particular_recurrence: every lane a zero-state recurrence
@@ -153,26 +170,26 @@ __device__ __forceinline__ void ph_section(T (&X)[N], const T *__restrict__ c, T
   // step 3, eq. PH_forward: the homogeneous correction from the true
   // terminal values of the preceding lane (R y_{N-2}, R y_{N-1})
   const T pr = shr<1>(p), qr = shr<1>(q);
-  const T *__restrict__ u1 = c + OFF_U1;
-  const T *__restrict__ u2 = c + OFF_U1 + N;
+  const ctab<T> u1 = c + OFF_U1;
+  const ctab<T> u2 = c + OFF_U1 + N;
 #pragma unroll
   for (int m = 0; m < N - 2; ++m) X[m] = fma_(-u2[m], pr, fma_(-u1[m], qr, X[m]));
-  st[0] = nx2;
-  st[1] = nx1;
-  st[2] = last_of_row(p);
-  st[3] = last_of_row(q);
+  ys[0] = last_of_row(p);
+  ys[1] = last_of_row(q);
+  xs2 = ys2;
+  xs1 = ys1;
 }
 
 // Cyclic reduction (Section VI-C) of one section on one group per row.
 // Level i works on the blocks m = s(j+1)-1 (s = 2^i, j = 0..N/s-1); even j
 // are eliminated, odd j retained.  A reference below j = 0 wraps to the last
 // blocks through R.
+// Boundary values as for ph_section.
 template <int N, typename T, bool B0ONE>
-__device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T *st) {
+__device__ __forceinline__ void cr_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1, T *ys) {
   constexpr int LG = __builtin_ctz(N);
   const T a1 = c[OFF_A1], a2 = c[OFF_A2];
-  const T xs2 = st[0], xs1 = st[1], ys2 = st[2], ys1 = st[3];
-  const T nx2 = last_of_row(X[N - 2]), nx1 = last_of_row(X[N - 1]);
+  const T ys2 = ys[0], ys1 = ys[1];
   fir_pass<N, T, B0ONE>(X, c, shift_r(X[N - 1], xs1), shift_r(X[N - 2], xs2));
   __builtin_amdgcn_sched_barrier(0);
   // the previous group's outputs enter the first element of blocks 0 and 1
@@ -221,10 +238,10 @@ __device__ __forceinline__ void cr_section(T (&X)[N], const T *__restrict__ c, T
       X[m] = fma_(-cc, y1, fma_(-dd, y3, X[m]));
     }
   }
-  st[0] = nx2;
-  st[1] = nx1;
-  st[2] = last_of_row(X[N - 2]);
-  st[3] = last_of_row(X[N - 1]);
+  ys[0] = last_of_row(X[N - 2]);
+  ys[1] = last_of_row(X[N - 1]);
+  xs2 = ys2;
+  xs1 = ys1;
 }
 
 // ------------------------------------------------------------ memory
@@ -339,24 +356,59 @@ template <int N, typename TI>
 __host__ __device__ constexpr int stage_bytes() {
   return kWavesPerBlock * Stage<N, TI>::ELEMS * (int)sizeof(TI);
 }
+// Boundary values per row: the raw input's (x[-2], x[-1]), then every
+// section's (y[-2], y[-1]).
+__host__ __device__ constexpr int state_elems(int K) { return 2 + 2 * K; }
 template <int N, typename TI, typename T>
 __host__ __device__ constexpr int lds_bytes(int K) {
-  return stage_bytes<N, TI>() + kWavesPerBlock * kRows * K * 4 * (int)sizeof(T);
+  return stage_bytes<N, TI>() + kWavesPerBlock * kRows * state_elems(K) * (int)sizeof(T);
 }
 
-// Tile t = [t*tile, (t+1)*tile) is filtered by row (t mod 4) of wavefront
-// t / 4.  The row first runs the cascade from zero state over the `warm`
-// samples that precede its tile (its carry-in: after `warm` samples the
-// cascade state no longer depends, to the working precision, on anything
-// earlier), then filters the tile, chaining groups through each section's
-// boundary values.  All four rows run the same number of groups; samples
-// outside [0, n) are zeros and are not stored.
+// One wavefront filters four tiles, one per row: row r's tile starts at
+// sample t0 (per lane row).  The row first runs the cascade from zero state
+// over the `warm` samples that precede its tile (its carry-in: after `warm`
+// samples the cascade state no longer depends, to the working precision, on
+// anything earlier), then filters the tile, chaining groups through each
+// section's boundary values.  All four rows run the same number of groups;
+// samples outside [0, n) are zeros and are not stored.  `aligned`: x and y
+// are 16-byte aligned, so whole groups may use vector loads and stores.
+//
+// SOLVER: SOS_PH or SOS_CR when every section uses that solver (no branch
+// in the section loop), SOS_AUTO for a per-section choice.
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+__device__ __forceinline__ void filter_rows(const TI *__restrict__ x, TI *__restrict__ y,
+                                            ctab<T> tab, const int32_t *__restrict__ solver,
+                                            int64_t n, int K,
+                                            int stride, int64_t t0, int64_t warm, int64_t tile,
+                                            bool aligned, T gain, T *st, TI *buf) {
+  for (int i = 0; i < state_elems(K); ++i) st[i] = T(0);   // the row's lanes write the same value
+  const int64_t G = (int64_t)N * kL;
+  const int64_t warm_groups = warm / G, steps = warm_groups + tile / G;
+  T X[N];
+  for (int64_t it = 0; it < steps; ++it) {
+    const int64_t g = t0 - warm + it * G;
+    const bool full = aligned && __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= n)) == 0;
+    load_group<N, TI, T>(X, x, g, n, full, buf);
+    T xs2 = st[0], xs1 = st[1];
+    st[0] = last_of_row(X[N - 2]);
+    st[1] = last_of_row(X[N - 1]);
+    for (int k = 0; k < K; ++k) {
+      const ctab<T> c = tab + (int64_t)k * stride;
+      if (SOLVER == SOS_CR || (SOLVER == SOS_AUTO && solver[k] == SOS_CR))
+        cr_section<N, T, B0ONE>(X, c, xs2, xs1, st + 2 + 2 * k);
+      else
+        ph_section<N, T, B0ONE>(X, c, xs2, xs1, st + 2 + 2 * k);
+    }
+    if (it >= warm_groups) store_group<N, TI, T>(X, y, g, n, full, gain, buf);
+  }
+}
+
+// Single signal: tile t = [t*tile, (t+1)*tile) is filtered by row (t mod 4)
+// of wavefront t / 4.
 //
 // The pointers are separate restrict-qualified arguments so that the
 // compiler may read the coefficient table (uniform addresses, never
 // written here) through the scalar cache.
-// SOLVER: SOS_PH or SOS_CR when every section uses that solver (no branch
-// in the section loop), SOS_AUTO for a per-section choice.
 template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const T *__restrict__ tab,
@@ -373,26 +425,53 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_kernel(
   if (wave * kRows >= a.ntiles) return;   // uniform per wave
   const int row = lane_id() >> 4;
   const int64_t t0 = (wave * kRows + row) * a.tile;   // this row's tile
-  T(*st)[4] = reinterpret_cast<T(*)[4]>(state + (int64_t)(w * kRows + row) * a.K * 4);
-  for (int i = 0; i < a.K * 4; ++i) st[i >> 2][i & 3] = T(0);   // the row's lanes write the same value
+  T *st = state + (int64_t)(w * kRows + row) * state_elems(a.K);
   TI *buf = stage + (w * kRows + row) * Stage<N, TI>::ROWBUF;
-  const int64_t G = (int64_t)N * kL;
-  const int64_t warm_groups = a.warm / G, steps = warm_groups + a.tile / G;
-  const T gain = (T)a.gain;
-  T X[N];
-  for (int64_t it = 0; it < steps; ++it) {
-    const int64_t g = t0 - a.warm + it * G;
-    const bool full = __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= a.n)) == 0;
-    load_group<N, TI, T>(X, x, g, a.n, full, buf);
-    for (int k = 0; k < a.K; ++k) {
-      const T *__restrict__ c = tab + (int64_t)k * a.stride;
-      if (SOLVER == SOS_CR || (SOLVER == SOS_AUTO && solver[k] == SOS_CR))
-        cr_section<N, T, B0ONE>(X, c, st[k]);
-      else
-        ph_section<N, T, B0ONE>(X, c, st[k]);
-    }
-    if (it >= warm_groups) store_group<N, TI, T>(X, y, g, a.n, full, gain, buf);
-  }
+  filter_rows<N, TI, T, B0ONE, SOLVER>(x, y, as_ctab(tab), solver, a.n, a.K, a.stride, t0, a.warm, a.tile,
+                                       true, (T)a.gain, st, buf);
+}
+
+// Batched ragged channels.  Each channel c has its own plan (K, tables, b0
+// gain), length and offset into the concatenated x and y.  Its tiles are
+// taken four at a time as wave items; item i belongs to channel
+// item_chan[i], and the channels are ordered so that costly items come
+// first.
+struct BatchChan {
+  const void *tab;          // the channel plan's device table (compute dtype)
+  const int32_t *solver;    // device [K]
+  int64_t off, n;           // first sample in x / y, length
+  int64_t tile, warm;       // samples per row tile and of run-in (multiples of the group)
+  int64_t first_item;       // the channel's first wave item
+  int32_t K, stride;
+  double gain;
+  int32_t aligned;          // x + off and y + off are 16-byte aligned
+  int32_t pad;
+};
+
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_batched_kernel(
+    const TI *__restrict__ x, TI *__restrict__ y, const BatchChan *__restrict__ chans,
+    const int32_t *__restrict__ item_chan, int64_t items, int32_t kmax) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  TI *stage = reinterpret_cast<TI *>(smem);
+  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, TI>());
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (item >= items) return;   // uniform per wave
+  const BatchChan &ch = chans[item_chan[item]];
+  const int64_t quad = item - ch.first_item;
+  const int64_t ntiles = (ch.n + ch.tile - 1) / ch.tile;
+  const int row = lane_id() >> 4;
+  const int64_t t0 = (quad * kRows + row) * ch.tile;
+  // rows past the channel's end idle; the run-in never reaches before the
+  // channel's start (the state there is zero)
+  const int64_t last = (quad * kRows + kRows - 1 < ntiles - 1 ? quad * kRows + kRows - 1 : ntiles - 1);
+  const int64_t warm = ch.warm < last * ch.tile ? ch.warm : last * ch.tile;
+  T *st = state + (int64_t)(w * kRows + row) * state_elems(kmax);
+  TI *buf = stage + (w * kRows + row) * Stage<N, TI>::ROWBUF;
+  filter_rows<N, TI, T, B0ONE, SOLVER>(x + ch.off, y + ch.off, as_ctab(static_cast<const T *>(ch.tab)),
+                                       ch.solver, ch.n, ch.K, ch.stride, t0, warm, ch.tile,
+                                       ch.aligned != 0, (T)ch.gain, st, buf);
 }
 
 }  // namespace sosf

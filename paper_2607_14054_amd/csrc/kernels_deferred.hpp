@@ -81,7 +81,7 @@ __host__ __device__ constexpr int deferred_lds_bytes(int K, int kbm) {
 // through the cascade).  FIRST: the raw input keeps its true history.
 // Returns the section's zero-state terminal values in (d0, d1).
 template <int N, bool B0ONE, bool FIRST>
-__device__ __forceinline__ void deferred_zero_state(double (&X)[N], const double *__restrict__ c,
+__device__ __forceinline__ void deferred_zero_state(double (&X)[N], ctab<double> c,
                                                     double *st, double &d0, double &d1) {
   typedef double T;
   T xm1 = T(0), xm2 = T(0);
@@ -103,7 +103,7 @@ __device__ __forceinline__ void deferred_zero_state(double (&X)[N], const double
 // to the sections j < k already solved (two independent accumulation
 // chains), the group's entry state on lane 0, then the row scan.  Writes
 // R S_k (entry state in lane 0) to rs and the exit state to st.
-__device__ __forceinline__ void deferred_terminal(double d0, double d1, const double *__restrict__ c,
+__device__ __forceinline__ void deferred_terminal(double d0, double d1, ctab<double> c,
                                                   const double *cp, double *rs, double *st, int k,
                                                   int D) {
   typedef double T;
@@ -128,7 +128,7 @@ __device__ __forceinline__ void deferred_terminal(double d0, double d1, const do
   d0 += f0;
   d1 += f1;
   const T e2 = st[2 + 2 * k], e1 = st[3 + 2 * k];
-  const T *__restrict__ A = c + OFF_PH_POW;   // -C
+  const ctab<T> A = c + OFF_PH_POW;   // -C
   const T i0 = fma_(A[0], e2, A[1] * e1), i1 = fma_(A[2], e2, A[3] * e1);
   d0 += l0 ? i0 : T(0);
   d1 += l0 ? i1 : T(0);
@@ -181,14 +181,14 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_deferred_kernel(
     // software pipelined: the zero-state pass of section k does not depend
     // on the terminal solve of section k-1, so the two run interleaved
     T d0, d1;
-    deferred_zero_state<N, B0ONE, true>(X, tab, st, d0, d1);
+    deferred_zero_state<N, B0ONE, true>(X, as_ctab(tab), st, d0, d1);
     for (int k = 1; k < K; ++k) {
       const T p0 = d0, p1 = d1;
-      deferred_zero_state<N, B0ONE, false>(X, tab + (int64_t)k * a.stride, st, d0, d1);
-      deferred_terminal(p0, p1, tab + (int64_t)(k - 1) * a.stride, coup_s + 2 * (k - 1) * (k - 2),
+      deferred_zero_state<N, B0ONE, false>(X, as_ctab(tab) + (int64_t)k * a.stride, st, d0, d1);
+      deferred_terminal(p0, p1, as_ctab(tab) + (int64_t)(k - 1) * a.stride, coup_s + 2 * (k - 1) * (k - 2),
                         rs, st, k - 1, D);
     }
-    deferred_terminal(d0, d1, tab + (int64_t)(K - 1) * a.stride, coup_s + 2 * (K - 1) * (K - 2), rs,
+    deferred_terminal(d0, d1, as_ctab(tab) + (int64_t)(K - 1) * a.stride, coup_s + 2 * (K - 1) * (K - 2), rs,
                       st, K - 1, D);
     __builtin_amdgcn_wave_barrier();
     // homogeneous correction of all sections (step 3): Y = W_K + Theta RS,

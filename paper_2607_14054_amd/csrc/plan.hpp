@@ -52,6 +52,7 @@ struct sos_plan_s {
   int64_t warm = 0;                // run-in samples, multiple of N*L
   double warm_norm = 0.0;
   int device = -1;
+  int simds = 1024, waves_per_simd = 4;   // residency of the plan's kernel (launch-shape model)
   void *d_table = nullptr;         // device copy in the compute dtype
   void *d_solver = nullptr;        // device int8 per section: 1 = PH, 2 = CR
 };

@@ -8,6 +8,7 @@
 #include <new>
 
 #include "kernels.hpp"
+#include "dispatch.hpp"
 #include "kernels_deferred.hpp"
 #include "plan.hpp"
 
@@ -57,29 +58,28 @@ struct Ptrs {
   const int32_t *solver;
 };
 
-template <int N, typename TI, typename T, int SOLVER>
-sos_status launch_s(const Ptrs &q, const FiltArgs &a, bool b0one, hipStream_t s) {
-  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
-  const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
-  const TI *x = static_cast<const TI *>(q.x);
-  TI *y = static_cast<TI *>(q.y);
-  const T *tab = static_cast<const T *>(q.tab);
-  const unsigned lds = (unsigned)lds_bytes<N, TI, T>(a.K);
-  if (b0one)
-    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, true, SOLVER>), dim3((unsigned)blocks),
-                       dim3(kWavesPerBlock * 64), lds, s, x, y, tab, q.solver, a);
-  else
-    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, false, SOLVER>), dim3((unsigned)blocks),
-                       dim3(kWavesPerBlock * 64), lds, s, x, y, tab, q.solver, a);
-  return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
-}
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+struct LaunchRows {
+  static sos_status run(const Ptrs &q, const FiltArgs &a, hipStream_t s) {
+    const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
+    const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
+    const unsigned lds = (unsigned)lds_bytes<N, TI, T>(a.K);
+    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, B0ONE, SOLVER>), dim3((unsigned)blocks),
+                       dim3(kWavesPerBlock * 64), lds, s,
+                       static_cast<const TI *>(q.x), static_cast<TI *>(q.y),
+                       static_cast<const T *>(q.tab), q.solver, a);
+    return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+  }
+};
 
-template <int N, typename TI, typename T>
-sos_status launch_n(const Ptrs &q, const FiltArgs &a, bool b0one, int mix, hipStream_t s) {
-  if (mix == SOS_PH) return launch_s<N, TI, T, SOS_PH>(q, a, b0one, s);
-  if (mix == SOS_CR) return launch_s<N, TI, T, SOS_CR>(q, a, b0one, s);
-  return launch_s<N, TI, T, SOS_AUTO>(q, a, b0one, s);
-}
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+struct ResidencyRows {
+  static sos_status run(int K, Residency *r) {
+    *r = residency_of(reinterpret_cast<const void *>(&sos_rows_kernel<N, TI, T, B0ONE, SOLVER>),
+                      (size_t)lds_bytes<N, TI, T>(K), kWavesPerBlock * 64);
+    return SOS_OK;
+  }
+};
 
 template <int N, typename TI, int KBM>
 sos_status launch_deferred_k(const Ptrs &q, const void *coup, const void *theta, const FiltArgs &a,
@@ -119,30 +119,44 @@ sos_status launch_deferred(int N, const Ptrs &q, const void *coup, const void *t
   }
 }
 
-template <typename TI, typename T>
-sos_status launch_t(int N, const Ptrs &q, const FiltArgs &a, bool b0one, int mix, hipStream_t s) {
-  switch (N) {
-    case 8: return launch_n<8, TI, T>(q, a, b0one, mix, s);
-    case 16: return launch_n<16, TI, T>(q, a, b0one, mix, s);
-    case 32: return launch_n<32, TI, T>(q, a, b0one, mix, s);
-    case 64: return launch_n<64, TI, T>(q, a, b0one, mix, s);
-    default: return SOS_E_UNSUPPORTED;
-  }
+template <int N, typename TI>
+Residency deferred_residency_n(int K, bool b0one) {
+  const int kbm = K <= 4 ? 2 : (K <= 8 ? 4 : 8);
+  const size_t lds = (size_t)deferred_lds_bytes<N, TI>(K, kbm);
+  const void *f;
+  if (kbm == 2) f = b0one ? reinterpret_cast<const void *>(&sos_rows_deferred_kernel<N, TI, true, 2>)
+                          : reinterpret_cast<const void *>(&sos_rows_deferred_kernel<N, TI, false, 2>);
+  else if (kbm == 4) f = b0one ? reinterpret_cast<const void *>(&sos_rows_deferred_kernel<N, TI, true, 4>)
+                               : reinterpret_cast<const void *>(&sos_rows_deferred_kernel<N, TI, false, 4>);
+  else f = b0one ? reinterpret_cast<const void *>(&sos_rows_deferred_kernel<N, TI, true, 8>)
+                 : reinterpret_cast<const void *>(&sos_rows_deferred_kernel<N, TI, false, 8>);
+  return residency_of(f, lds, kWavesPerBlock * 64);
 }
 
-// Tile length for n samples: long enough that the run-in costs at most
-// about 1/16 of the tile, short enough to give the chip enough rows (four
-// per wavefront) in flight.
+template <typename TI>
+Residency deferred_residency(int N, int K, bool b0one) {
+  if (N == 16) return deferred_residency_n<16, TI>(K, b0one);
+  if (N == 32) return deferred_residency_n<32, TI>(K, b0one);
+  return deferred_residency_n<64, TI>(K, b0one);
+}
+
+int solver_mix(const sos_plan_s &p) {
+  int mix = p.solver[0];
+  for (int k = 1; k < p.K; ++k)
+    if (p.solver[k] != mix) mix = SOS_AUTO;
+  return mix;
+}
+
+// Tile length for n samples: the plan's fixed choice, or the launch-shape
+// model for the kernel the plan runs.
 int64_t choose_tile(const sos_plan_s &p, int64_t n) {
   const int64_t G = (int64_t)p.N * kL;
-  const int64_t groups = (n + G - 1) / G;
   if (p.tile_groups > 0) return (int64_t)p.tile_groups * G;
-  const int64_t gw = p.warm / G;
-  int64_t tg = std::max<int64_t>(16 * gw, 8);
-  const int64_t want_tiles = 16384;
-  const int64_t tg_par = std::max<int64_t>(groups / want_tiles, 1);
-  if (tg_par < tg) tg = std::max<int64_t>(tg_par, std::max<int64_t>(4 * gw, 4));
-  return tg * G;
+  const int64_t groups = (n + G - 1) / G;
+  Residency r;
+  r.simds = p.simds;
+  r.waves_per_simd = p.waves_per_simd;
+  return model_tile_groups(groups, p.warm / G, r) * G;
 }
 
 }  // namespace
@@ -192,7 +206,18 @@ sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan
     build_deferred_tables(*p);
     for (int k = 0; k < K; ++k) p->solver[k] = SOS_PH_DEFERRED;
   }
-  if (st == SOS_OK && !(o.flags & SOS_FLAG_HOST_ONLY)) st = upload(*p);
+  if (st == SOS_OK && !(o.flags & SOS_FLAG_HOST_ONLY)) {
+    st = upload(*p);
+    Residency r;
+    if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED)
+      r = p->io_dtype == SOS_F32 ? deferred_residency<float>(p->N, p->K, p->b0_factored)
+                                 : deferred_residency<double>(p->N, p->K, p->b0_factored);
+    else if (st == SOS_OK)
+      dispatch_rows<ResidencyRows>(p->N, p->io_dtype, p->compute_dtype, p->b0_factored, solver_mix(*p),
+                                   p->K, &r);
+    p->simds = r.simds;
+    p->waves_per_simd = r.waves_per_simd;
+  }
   if (st != SOS_OK) {
     sos_plan_destroy(p);
     return st;
@@ -229,6 +254,8 @@ sos_status sos_plan_query(sos_plan_t p, sos_plan_info *info, int32_t *solver) {
     info->warm_samples = p->warm;
     info->gain = p->gain;
     info->transition_norm_W = p->warm_norm;
+    info->simds = p->d_table ? p->simds : 0;
+    info->waves_per_simd = p->d_table ? p->waves_per_simd : 0;
   }
   if (solver)
     for (int k = 0; k < p->K; ++k) solver[k] = p->solver[k];
@@ -269,6 +296,11 @@ sos_status sos_plan_table(sos_plan_t p, int32_t table, int32_t section, double *
   return SOS_OK;
 }
 
+int64_t sos_plan_tile(sos_plan_t p, int64_t n) {
+  if (!p || n < 0) return 0;
+  return choose_tile(*p, n);
+}
+
 size_t sos_workspace_size(sos_plan_t p, int64_t n) {
   (void)p;
   (void)n;
@@ -302,13 +334,7 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
     return launch_deferred<double>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);
   }
   // one solver for every section lets the kernel drop the per-section branch
-  int mix = p->solver[0];
-  for (int k = 1; k < p->K; ++k)
-    if (p->solver[k] != mix) mix = SOS_AUTO;
-  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F32) return launch_t<float, float>(p->N, q, a, b0one, mix, s);
-  if (p->io_dtype == SOS_F32 && p->compute_dtype == SOS_F64) return launch_t<float, double>(p->N, q, a, b0one, mix, s);
-  if (p->io_dtype == SOS_F64 && p->compute_dtype == SOS_F64) return launch_t<double, double>(p->N, q, a, b0one, mix, s);
-  return SOS_E_UNSUPPORTED;
+  return dispatch_rows<LaunchRows>(p->N, p->io_dtype, p->compute_dtype, b0one, solver_mix(*p), q, a, s);
 }
 
 }  // extern "C"

@@ -24,8 +24,9 @@ SOS_FLAG_HOST_ONLY = 0x1
  SOS_TABLE_CR_LEVELS, SOS_TABLE_CR_TERMINAL, SOS_TABLE_CR_POWERS, SOS_TABLE_TRANSITION,
  SOS_TABLE_THETA, SOS_TABLE_COUPLING) = range(11)
 
-EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table",
-            "sos_workspace_size", "sos_filt", "sos_status_string"]
+EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_plan_tile",
+            "sos_workspace_size", "sos_filt", "sos_batch_plan", "sos_batch_destroy",
+            "sos_batch_query", "sos_filt_batched", "sos_batch_tune", "sos_status_string"]
 
 _DTYPES = {"f32": SOS_F32, "f64": SOS_F64, np.float32: SOS_F32, np.float64: SOS_F64}
 _SOLVERS = {"auto": SOS_AUTO, "ph": SOS_PH, "cr": SOS_CR, "phd": SOS_PH_DEFERRED}
@@ -47,7 +48,16 @@ class _Info(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("N", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("io_dtype", ctypes.c_int32), ("compute_dtype", ctypes.c_int32),
                 ("b0_factored", ctypes.c_int32), ("warm_samples", ctypes.c_int64),
-                ("gain", ctypes.c_double), ("transition_norm_W", ctypes.c_double)]
+                ("gain", ctypes.c_double), ("transition_norm_W", ctypes.c_double),
+                ("simds", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("tile_groups", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class _TuneResult(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("tile_groups", ctypes.c_int32), ("seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -65,12 +75,26 @@ def lib():
         L.sos_plan_destroy.argtypes = [vp]
         L.sos_plan_query.argtypes = [vp, ctypes.POINTER(_Info), ctypes.POINTER(ctypes.c_int32)]
         L.sos_plan_table.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_double), i32, ctypes.POINTER(ctypes.c_int32)]
+        L.sos_plan_tile.argtypes = [vp, i64]
+        L.sos_plan_tile.restype = ctypes.c_int64
         L.sos_workspace_size.argtypes = [vp, i64]
         L.sos_workspace_size.restype = ctypes.c_size_t
         L.sos_filt.argtypes = [vp, vp, vp, i64, vp, vp]
         L.sos_status_string.argtypes = [ctypes.c_int]
         L.sos_status_string.restype = ctypes.c_char_p
-        for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt"):
+        p64 = ctypes.POINTER(ctypes.c_int64)
+        L.sos_batch_plan.argtypes = [ctypes.POINTER(vp), i32, p64, p64, ctypes.POINTER(_BatchOpts),
+                                     ctypes.POINTER(vp)]
+        L.sos_batch_destroy.argtypes = [vp]
+        L.sos_batch_query.argtypes = [vp, p64, p64, p64, p64, ctypes.POINTER(ctypes.c_int32)]
+        L.sos_filt_batched.argtypes = [vp, vp, vp, vp, vp]
+        pi32 = ctypes.POINTER(ctypes.c_int32)
+        L.sos_batch_tune.argtypes = [ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), pi32, i32, p64, p64,
+                                     ctypes.POINTER(_Opts), pi32, i32, pi32, i32, vp, vp, i32, vp,
+                                     ctypes.POINTER(_TuneResult), ctypes.POINTER(_TuneResult)]
+        for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt",
+                  "sos_batch_plan", "sos_batch_destroy", "sos_batch_query", "sos_filt_batched",
+                  "sos_batch_tune"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -97,6 +121,8 @@ class PlanInfo:
     gain: float
     transition_norm_W: float
     solver: list
+    simds: int
+    waves_per_simd: int
 
 
 class Plan:
@@ -139,7 +165,7 @@ class Plan:
         return PlanInfo(inf.K, inf.N, inf.L, "f32" if inf.io_dtype == SOS_F32 else "f64",
                         "f32" if inf.compute_dtype == SOS_F32 else "f64", bool(inf.b0_factored),
                         int(inf.warm_samples), float(inf.gain), float(inf.transition_norm_W),
-                        [names[int(v)] for v in sol])
+                        [names[int(v)] for v in sol], int(inf.simds), int(inf.waves_per_simd))
 
     def table(self, which: int, section: int = 0) -> np.ndarray:
         size = ctypes.c_int32()
@@ -149,6 +175,10 @@ class Plan:
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     size.value, None), "sos_plan_table")
         return out
+
+    def tile(self, n: int) -> int:
+        """Samples per tile sos_filt uses for n samples."""
+        return int(lib().sos_plan_tile(self._h, int(n)))
 
     def workspace_size(self, n: int) -> int:
         return int(lib().sos_workspace_size(self._h, int(n)))
@@ -178,3 +208,108 @@ def filt(plan: Plan, x, y=None, stream=None):
                           n, ctypes.c_void_p(wsb.data_ptr()) if wsb is not None else None,
                           _stream_ptr(stream)), "sos_filt")
     return y
+
+
+def _i64p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+
+
+class Batch:
+    """Owns a sos_batch_t: channel c (length lengths[c]) filtered with
+    plans[c], at offsets[c] of the concatenated buffers (None: dense)."""
+
+    def __init__(self, plans, lengths, offsets=None, tile_groups=0, host_only=False):
+        self.plans = list(plans)        # the batch refers to their device tables
+        C = len(self.plans)
+        n = np.ascontiguousarray(np.asarray(lengths, dtype=np.int64))
+        if n.shape != (C,):
+            raise ValueError("one length per plan")
+        off = None
+        if offsets is not None:
+            off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+            if off.shape != (C,):
+                raise ValueError("one offset per plan")
+        hs = (ctypes.c_void_p * C)(*[p.handle.value for p in self.plans])
+        o = _BatchOpts(int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0)
+        h = ctypes.c_void_p()
+        _check(lib().sos_batch_plan(hs, C, _i64p(n), _i64p(off) if off is not None else None,
+                                    ctypes.byref(o), ctypes.byref(h)), "sos_batch_plan")
+        self._h = h
+        self.C = C
+        self.lengths = n
+        self.io_dtype = self.plans[0].io_dtype
+        q = self.query()
+        self.total = q["total"]
+        self.offsets = q["offsets"]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def query(self) -> dict:
+        total, items = ctypes.c_int64(), ctypes.c_int64()
+        off = np.zeros(self.C, np.int64)
+        tile = np.zeros(self.C, np.int64)
+        order = np.zeros(self.C, np.int32)
+        _check(lib().sos_batch_query(self._h, ctypes.byref(total), ctypes.byref(items), _i64p(off),
+                                     _i64p(tile), order.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+               "sos_batch_query")
+        return {"total": int(total.value), "items": int(items.value), "offsets": off, "tile": tile,
+                "order": order}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().sos_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def filt_batched(batch: Batch, x, y=None, stream=None):
+    """Every channel of a concatenated 1-D device tensor x (batch.total
+    samples) through its own cascade; returns y (same layout)."""
+    import torch
+    want = torch.float32 if batch.io_dtype == "f32" else torch.float64
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == want and x.dim() == 1
+            and x.numel() >= batch.total and x.is_contiguous()):
+        raise ValueError("x must be a contiguous 1-D device tensor of dtype %s with %d samples"
+                         % (want, batch.total))
+    if y is None:
+        y = torch.zeros_like(x)
+    if not (y.is_cuda and y.dtype == want and y.numel() >= batch.total and y.is_contiguous()):
+        raise ValueError("y must be a contiguous device tensor like x")
+    _check(lib().sos_filt_batched(batch.handle, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(y.data_ptr()), None, _stream_ptr(stream)),
+           "sos_filt_batched")
+    return y
+
+
+def batch_tune(sos_list, lengths, x, y, offsets=None, io_dtype="f32", compute_dtype="f64",
+               solver="ph", Ns=(16, 32, 64), tiles=(0, 8, 16, 32), reps=3, stream=None):
+    """sos_batch_tune: the fastest (N, tile_groups) for this batch on the
+    given device buffers.  Returns (best, rows) with rows one dict per
+    candidate."""
+    C = len(sos_list)
+    arrs = [np.ascontiguousarray(np.asarray(s, dtype=np.float64)) for s in sos_list]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * C)(
+        *[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
+    K = np.array([a.shape[0] for a in arrs], dtype=np.int32)
+    n = np.ascontiguousarray(np.asarray(lengths, dtype=np.int64))
+    off = None if offsets is None else np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], 0, 16, 0, 0)
+    Na = np.asarray(Ns, dtype=np.int32)
+    Ta = np.asarray(tiles, dtype=np.int32)
+    res = (_TuneResult * (len(Na) * len(Ta)))()
+    best = _TuneResult()
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    _check(lib().sos_batch_tune(ptrs, K.ctypes.data_as(pi32), C, _i64p(n),
+                                _i64p(off) if off is not None else None, ctypes.byref(o),
+                                Na.ctypes.data_as(pi32), len(Na), Ta.ctypes.data_as(pi32), len(Ta),
+                                ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), int(reps),
+                                _stream_ptr(stream), res, ctypes.byref(best)), "sos_batch_tune")
+    rows = [{"N": r.N, "tile_groups": r.tile_groups, "seconds": r.seconds} for r in res]
+    return {"N": best.N, "tile_groups": best.tile_groups, "seconds": best.seconds}, rows

@@ -1,0 +1,186 @@
+"""GPU parity of the batched ragged-channel entry point (sos_filt_batched)
+against the FP64 oracle, channel by channel.
+
+Tolerances are those of the single-signal tests: 1e-12 relative RMS for
+FP64 in/out with FP64 arithmetic (r <= 0.95 draws), 1e-6 for FP32 in/out
+with FP64 arithmetic (FP32 output rounding is ~6e-8).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_14054_amd import sosfilt as S
+from paper_2607_14054_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+
+# lengths that hit the edge cases: empty, shorter than a lane's run, one
+# group short / exact / one over, several tiles with a ragged tail
+EDGE_LENGTHS = [0, 1, 17, 511, 512, 513, 4096, 5000, 70001, 300000]
+
+
+def channel_inputs(lengths, Ks, dtype, seed=0):
+    sos = [W.make_sos(int(k), 0.5, 0.95, seed + c) for c, k in enumerate(Ks)]
+    xs = [W.make_signal(int(n), seed + c, dtype) for c, n in enumerate(lengths)]
+    return sos, xs
+
+
+def pack(xs, offsets, total, dtype, fill=0.0):
+    buf = np.full(max(total, 1), fill, dtype=dtype)
+    for x, o in zip(xs, offsets):
+        buf[o:o + len(x)] = x
+    return buf
+
+
+def run_batch(sos, xs, io, N, solver="ph", offsets=None, tile_groups=0, fill=0.0):
+    dtype = np.float64 if io == "f64" else np.float32
+    plans = [S.Plan(s, io_dtype=io, compute_dtype="f64", solver=solver, N=N) for s in sos]
+    b = S.Batch(plans, [len(x) for x in xs], offsets=offsets, tile_groups=tile_groups)
+    xb = torch.from_numpy(pack(xs, b.offsets, b.total, dtype)).to(DEV)
+    yb = torch.from_numpy(np.full(max(b.total, 1), fill, dtype=dtype)).to(DEV)
+    S.filt_batched(b, xb, yb)
+    torch.cuda.synchronize()
+    return yb.cpu().numpy(), b
+
+
+@pytest.mark.parametrize("solver,N", [("ph", 8), ("ph", 32), ("cr", 16), ("cr", 64)])
+def test_batched_ragged_f64(solver, N):
+    Ks = [1 + (7 * c) % 16 for c in range(len(EDGE_LENGTHS))]   # 1..16, mixed
+    sos, xs = channel_inputs(EDGE_LENGTHS, Ks, np.float64, seed=100)
+    y, b = run_batch(sos, xs, "f64", N, solver=solver, tile_groups=2)
+    for c, (s, x) in enumerate(zip(sos, xs)):
+        o = b.offsets[c]
+        got = y[o:o + len(x)]
+        if len(x) == 0:
+            continue
+        err = oracle.rel_rms(got, oracle.sosfilt(x, s))
+        assert err < 1e-12, (c, len(x), Ks[c], err)
+
+
+def test_batched_f32_dense_unaligned():
+    """Dense packing of odd lengths puts channel starts off 16-byte
+    boundaries: those channels take the element-wise load/store path."""
+    lengths = [3, 1001, 777, 65537, 12345, 200003]
+    Ks = [8, 3, 16, 8, 1, 5]
+    sos, xs = channel_inputs(lengths, Ks, np.float32, seed=200)
+    y, b = run_batch(sos, xs, "f32", 32, tile_groups=4)
+    assert any((o * 4) % 16 for o in b.offsets)
+    for c, (s, x) in enumerate(zip(sos, xs)):
+        o = b.offsets[c]
+        err = oracle.rel_rms(y[o:o + len(x)], oracle.sosfilt(x, s))
+        assert err < 1e-6, (c, err)
+
+
+def test_batched_gaps_untouched_and_order():
+    """Explicit offsets with gaps and out of order: samples between channels
+    keep their value; the launch order puts costly channels first."""
+    lengths = [40000, 5000, 123457]
+    Ks = [2, 16, 8]
+    offsets = [300000, 0, 100000]
+    sos, xs = channel_inputs(lengths, Ks, np.float64, seed=300)
+    y, b = run_batch(sos, xs, "f64", 16, offsets=offsets, fill=-7.0)
+    mask = np.ones(b.total, bool)
+    for c, (s, x) in enumerate(zip(sos, xs)):
+        o = offsets[c]
+        mask[o:o + len(x)] = False
+        assert oracle.rel_rms(y[o:o + len(x)], oracle.sosfilt(x, s)) < 1e-12
+    assert np.all(y[:b.total][mask] == -7.0)
+    q = b.query()
+    assert sorted(q["order"].tolist()) == [0, 1, 2]
+
+
+def test_batched_graph_replays_match_eager():
+    """One launch captured in a HIP graph and replayed with new input in the
+    captured buffer; every replay equals the eager call on that input."""
+    lengths = [5000, 70001, 1, 300000, 4096]
+    Ks = [8, 16, 1, 4, 12]
+    sos, xs = channel_inputs(lengths, Ks, np.float32, seed=400)
+    plans = [S.Plan(s, io_dtype="f32", compute_dtype="f64", N=32) for s in sos]
+    b = S.Batch(plans, lengths)
+    xin = torch.from_numpy(pack(xs, b.offsets, b.total, np.float32)).to(DEV)
+    yout = torch.zeros_like(xin)
+    stream = torch.cuda.Stream()
+    S.filt_batched(b, xin, yout)      # load the code object before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        S.filt_batched(b, xin, yout, stream=torch.cuda.current_stream())
+    for rep in range(3):
+        fresh = torch.from_numpy(W.make_signal(b.total, 500 + rep, np.float32)).to(DEV)
+        xin.copy_(fresh)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        replay = yout.clone()
+        eager = S.filt_batched(b, fresh, torch.zeros_like(fresh))
+        torch.cuda.synchronize()
+        assert torch.equal(replay, eager), rep
+
+
+def test_request_stream_1_to_64_channels():
+    """A ragged stream of small requests: each request a batch of 1-64
+    channels with its own lengths and cascades."""
+    rng = np.random.default_rng(600)
+    for req in range(6):
+        C = int(rng.integers(1, 65))
+        lengths = np.floor(2.0 ** rng.uniform(6, 15, size=C)).astype(np.int64)
+        Ks = rng.integers(1, 17, size=C)
+        sos, xs = channel_inputs(lengths, Ks, np.float32, seed=1000 * (req + 1))
+        y, b = run_batch(sos, xs, "f32", 16)
+        for c, (s, x) in enumerate(zip(sos, xs)):
+            o = b.offsets[c]
+            assert oracle.rel_rms(y[o:o + len(x)], oracle.sosfilt(x, s)) < 1e-6, (req, c)
+
+
+def test_batched_bad_arguments():
+    import ctypes
+    lib = S.lib()
+    p8 = S.Plan(W.make_sos(2, 0.5, 0.9, 1), io_dtype="f32", N=8)
+    p16 = S.Plan(W.make_sos(2, 0.5, 0.9, 1), io_dtype="f32", N=16)
+    with pytest.raises(S.SosError) as e:
+        S.Batch([p8, p16], [100, 100])
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    with pytest.raises(S.SosError) as e:
+        S.Batch([p8, p8], [100, 100], offsets=[0, 50])      # overlapping channels
+    assert e.value.code == S.SOS_E_ARG
+    b = S.Batch([p8, p8], [1000, 1000])
+    x = torch.zeros(4096, dtype=torch.float32, device=DEV)
+    rc = lib.sos_filt_batched(b.handle, ctypes.c_void_p(x.data_ptr()),
+                              ctypes.c_void_p(x.data_ptr() + 64), None, None)
+    assert rc == S.SOS_E_ARG                                 # x and y overlap
+    rc = lib.sos_filt_batched(b.handle, ctypes.c_void_p(x.data_ptr() + 4),
+                              ctypes.c_void_p(x.data_ptr() + 8192), None, None)
+    assert rc == S.SOS_E_ARG                                 # misaligned
+
+
+@pytest.mark.slow
+def test_batched_config_full_size_sampled():
+    """The full batched workload (4096 channels, lengths log-uniform in
+    [2^10, 2^22], K ~ U{1..16}, FP32): one launch, then a sample of channels
+    across the length range checked against the oracle."""
+    cfg = W.CONFIGS["batch"]
+    e = cfg.extra
+    lengths = W.batch_lengths(cfg.channels, e["log2_lo"], e["log2_hi"], cfg.seed)
+    Ks = W.batch_sections(cfg.channels, e["K_lo"], e["K_hi"], cfg.seed)
+    plans = [S.Plan(W.make_sos(int(Ks[c]), cfg.r_lo, cfg.r_hi, cfg.seed + c), io_dtype="f32",
+                    compute_dtype="f64", N=32) for c in range(cfg.channels)]
+    b = S.Batch(plans, lengths)
+    xb = torch.empty(b.total, dtype=torch.float32, device=DEV)
+    for c in range(cfg.channels):
+        o, n = int(b.offsets[c]), int(lengths[c])
+        xb[o:o + n] = torch.from_numpy(W.make_signal(n, cfg.seed + c, np.float32)).to(DEV)
+    yb = S.filt_batched(b, xb)
+    torch.cuda.synchronize()
+    pick = np.unique(np.concatenate([np.argsort(lengths)[[0, 1, -2, -1]],
+                                     np.arange(0, cfg.channels, 409)]))
+    for c in pick:
+        o, n = int(b.offsets[c]), int(lengths[c])
+        x = W.make_signal(n, cfg.seed + c, np.float32)
+        ref = oracle.sosfilt(x, W.make_sos(int(Ks[c]), cfg.r_lo, cfg.r_hi, cfg.seed + c))
+        err = oracle.rel_rms(yb[o:o + n].cpu().numpy(), ref)
+        assert err < 1e-6, (c, n, int(Ks[c]), err)

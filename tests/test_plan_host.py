@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_functions():
     text = open(os.path.join(ROOT, "include", "sosfilt.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:const char\s*\*|sos_status|size_t)\s*\*?\s*(sos_\w+)\s*\(",
+    return sorted(set(re.findall(r"^\s*(?:const char\s*\*|sos_status|size_t|int64_t)\s*\*?\s*(sos_\w+)\s*\(",
                                  text, re.M)))
 
 
@@ -256,3 +256,85 @@ def test_deferred_solver_limits():
     # auto takes cyclic reduction with the guard's PH fallback
     assert set(plan(sos, N=32).info().solver) <= {"cr", "ph"}
     assert set(plan(W.make_sos(17, 0.5, 0.9, 1), N=16).info().solver) <= {"cr", "ph"}
+
+
+# ---------------------------------------------------------------- batches
+
+def _host_plans(Ks, N=32, io="f32", seed=0):
+    return [S.Plan(W.make_sos(int(k), 0.5, 0.95, seed + c), io_dtype=io, N=N, host_only=True)
+            for c, k in enumerate(Ks)]
+
+
+@pytest.mark.parametrize("cap", [0, 1, 3, 32])
+def test_batch_schedule_covers_every_channel(cap):
+    rng = np.random.default_rng(7)
+    C = 40
+    lengths = np.floor(2.0 ** rng.uniform(0, 20, size=C)).astype(np.int64)
+    lengths[[3, 17]] = 0
+    Ks = rng.integers(1, 17, size=C)
+    N = 16
+    G = N * 16
+    b = S.Batch(_host_plans(Ks, N=N), lengths, tile_groups=cap, host_only=True)
+    q = b.query()
+    # dense packing in channel order
+    assert np.array_equal(q["offsets"], np.concatenate([[0], np.cumsum(lengths)[:-1]]))
+    assert q["total"] == lengths.sum()
+    assert sorted(q["order"].tolist()) == list(range(C))
+    items = 0
+    for c in range(C):
+        t = int(q["tile"][c])
+        assert t > 0 and t % G == 0
+        if cap:
+            assert t <= cap * G
+        ntiles = -(-int(lengths[c]) // t)
+        quads = -(-ntiles // 4)
+        # tiles as even as the length allows: the quads could not be fewer
+        if ntiles:
+            assert (quads - 1) * 4 * t < lengths[c] + 4 * t
+        items += quads
+    assert q["items"] == items
+
+
+def test_batch_order_costliest_first():
+    Ks = [1, 16, 4]
+    lengths = [2 ** 20, 2 ** 20, 2 ** 20]
+    b = S.Batch(_host_plans(Ks), lengths, host_only=True)
+    assert b.query()["order"].tolist() == [1, 2, 0]
+
+
+def test_batch_explicit_offsets():
+    b = S.Batch(_host_plans([2, 3, 4]), [100, 0, 50], offsets=[1000, 5, 0], host_only=True)
+    q = b.query()
+    assert q["offsets"].tolist() == [1000, 5, 0] and q["total"] == 1100
+    with pytest.raises(S.SosError) as e:
+        S.Batch(_host_plans([2, 3]), [100, 100], offsets=[0, 99], host_only=True)
+    assert e.value.code == S.SOS_E_ARG
+    with pytest.raises(S.SosError) as e:
+        S.Batch(_host_plans([2]), [10], offsets=[-1], host_only=True)
+    assert e.value.code == S.SOS_E_ARG
+
+
+def test_batch_rejections():
+    mixed_n = _host_plans([2], N=16) + _host_plans([2], N=32)
+    with pytest.raises(S.SosError) as e:
+        S.Batch(mixed_n, [10, 10], host_only=True)
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    mixed_io = _host_plans([2], io="f32") + _host_plans([2], io="f64")
+    with pytest.raises(S.SosError) as e:
+        S.Batch(mixed_io, [10, 10], host_only=True)
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    phd = [S.Plan(W.make_sos(2, 0.5, 0.9, 0), N=32, solver="phd", host_only=True)]
+    with pytest.raises(S.SosError) as e:
+        S.Batch(phd, [10], host_only=True)
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    with pytest.raises(S.SosError) as e:
+        S.Batch(_host_plans([2]), [-1], host_only=True)
+    assert e.value.code == S.SOS_E_ARG
+    # host-only plans cannot back a device batch; a host-only batch cannot filter
+    with pytest.raises(S.SosError) as e:
+        S.Batch(_host_plans([2]), [10])
+    assert e.value.code == S.SOS_E_ARG
+    import ctypes
+    b = S.Batch(_host_plans([2]), [10], host_only=True)
+    assert S.lib().sos_filt_batched(b.handle, None, None, None, None) == S.SOS_E_ARG
+    assert S.lib().sos_batch_plan(None, 1, None, None, None, None) == S.SOS_E_ARG
