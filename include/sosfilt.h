@@ -241,6 +241,44 @@ sos_status sos_filt_batched(sos_batch_t batch, const void *x, void *y, void *wor
                             sos_stream_t stream);
 
 /*
+ * Reverse-mode gradient (adjoint) of y = cascade(x) for a loss L with
+ * upstream gradient gy = dL/dy.  With u_k the input and w_k the output of
+ * section k, and A_k, B_k the banded Toeplitz matrices of its denominator
+ * and numerator (the matrix form of the recurrence in Section II):
+ *   mu_k = A_k^{-T} lambda_k,  lambda_{k-1} = B_k^T mu_k,  lambda_K = gy,
+ *   gx = dL/dx = lambda_0,
+ *   dL/db_j = sum_i mu_k[i] u_k[i-j],  dL/da_j = -sum_i mu_k[i] w_k[i-j],
+ * then the chain rule through the division of each row by its a0.  The
+ * transposed filters run backwards in time, so the kernels take the groups
+ * in reversed time and reuse the PH solve of Section VI-B for A^{-T}.
+ *
+ * sos_backward_workspace_size -- device bytes sos_filt_backward needs for n
+ * samples: every section's output (FP64, K n samples, padded) and the
+ * per-tile partial sums.  0 for a host-only plan.
+ */
+size_t sos_backward_workspace_size(sos_plan_t plan, int64_t n);
+
+/*
+ * sos_filt_backward -- gx = dL/dx and gsos = dL/d(sos) for y = cascade(x).
+ *
+ * x, gy      device, n samples of the plan's io_dtype: the forward input
+ *            and dL/dy.
+ * gx         device, n samples (io_dtype), written; must not overlap x or gy.
+ * gsos       device, [K][6] float64 row-major, written: the gradient with
+ *            respect to the caller's rows (b0, b1, b2, a0, a1, a2).
+ * n          >= 0; n == 0 writes gsos = 0 only.
+ * workspace  device, sos_backward_workspace_size(plan, n) bytes, 16-byte
+ *            aligned; its contents on entry do not matter.
+ * The adjoint always runs PH with FP64 arithmetic at N = 16, whatever the
+ * plan's solver, N and compute dtype (the same cascade, exact to rounding).
+ * It first re-runs the forward pass to save every section's output, so the
+ * caller's forward result is not needed.  Sums over the signal are formed
+ * per tile and added in a fixed order: results are deterministic.
+ */
+sos_status sos_filt_backward(sos_plan_t plan, const void *x, const void *gy, void *gx,
+                             double *gsos, int64_t n, void *workspace, sos_stream_t stream);
+
+/*
  * sos_batch_tune -- autotuner for batches: times sos_filt_batched for every
  * candidate (N, tile_groups) on the caller's own buffers and reports the
  * fastest.  L is not a candidate: it is fixed by the 16-lane DPP row.

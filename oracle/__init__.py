@@ -29,6 +29,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sosfilt_oracle.c")
+_IMPL = os.path.join(_HERE, "backward_impl.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -40,7 +41,7 @@ CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc; returns its path."""
     stale = (not os.path.exists(_LIB)
-             or os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
+             or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC), os.path.getmtime(_IMPL)))
     if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp])
@@ -62,9 +63,10 @@ def _load():
             lib.oracle_sosfilt_ld.argtypes = [dp, i64, dp, i32, dp]
             lib.oracle_sosfilt_f32arith.argtypes = [fp, i64, dp, i32, fp]
             lib.oracle_sosfilt_backward_f64.argtypes = [dp, i64, dp, i32, dp, dp, dp]
+            lib.oracle_sosfilt_backward_ld.argtypes = [dp, i64, dp, i32, dp, dp, dp]
             for f in (lib.oracle_sosfilt_f64, lib.oracle_sosfilt_f32in,
                       lib.oracle_sosfilt_ld, lib.oracle_sosfilt_f32arith,
-                      lib.oracle_sosfilt_backward_f64):
+                      lib.oracle_sosfilt_backward_f64, lib.oracle_sosfilt_backward_ld):
                 f.restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -143,6 +145,22 @@ def sosfilt_backward(x, sos, gy):
     gs = np.zeros_like(s)
     _check(lib.oracle_sosfilt_backward_f64(_dptr(xd), xd.shape[0], _dptr(s), s.shape[0],
                                            _dptr(gd), _dptr(gx), _dptr(gs)))
+    return gx, gs
+
+
+def sosfilt_backward_ld(x, sos, gy):
+    """The adjoint of sosfilt_backward in x86 extended precision (long
+    double), rounded to FP64: the arbiter for FP64 adjoints."""
+    lib = _load()
+    s = _sos(sos)
+    xd = np.ascontiguousarray(x, dtype=np.float64)
+    gd = np.ascontiguousarray(gy, dtype=np.float64)
+    if gd.shape != xd.shape:
+        raise ValueError("gy must have the shape of x")
+    gx = np.empty_like(xd)
+    gs = np.zeros_like(s)
+    _check(lib.oracle_sosfilt_backward_ld(_dptr(xd), xd.shape[0], _dptr(s), s.shape[0],
+                                          _dptr(gd), _dptr(gx), _dptr(gs)))
     return gx, gs
 
 

@@ -270,6 +270,33 @@ struct Stage {
   static constexpr int ELEMS = kRows * ROWBUF;  // per wave
 };
 
+// Lane l's run of the row's staged group <-> its N registers.
+template <int N, typename TI, typename T>
+__device__ __forceinline__ void stage_to_regs(T (&X)[N], const TI *__restrict__ buf) {
+  typedef typename Vec16<TI>::type VT;
+  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
+  const int rl = row_lane();
+#pragma unroll
+  for (int j = 0; j < N / V; ++j) {
+    VT v = *reinterpret_cast<const VT *>(buf + rl * RUN + j * V);
+#pragma unroll
+    for (int i = 0; i < V; ++i) X[j * V + i] = T(v[i]);
+  }
+}
+template <int N, typename TI, typename T>
+__device__ __forceinline__ void regs_to_stage(const T (&X)[N], T gain, TI *__restrict__ buf) {
+  typedef typename Vec16<TI>::type VT;
+  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
+  const int rl = row_lane();
+#pragma unroll
+  for (int j = 0; j < N / V; ++j) {
+    VT v;
+#pragma unroll
+    for (int i = 0; i < V; ++i) v[i] = (TI)(X[j * V + i] * gain);
+    *reinterpret_cast<VT *>(buf + rl * RUN + j * V) = v;
+  }
+}
+
 // g: this row's group start (may be negative or run past n in the run-in
 // and at the end; those samples read as zero).  full: every row of the wave
 // has a whole group inside [0, n).
@@ -296,12 +323,7 @@ __device__ __forceinline__ void load_group(T (&X)[N], const TI *__restrict__ x, 
     }
   }
   __builtin_amdgcn_wave_barrier();
-#pragma unroll
-  for (int j = 0; j < N / V; ++j) {
-    VT v = *reinterpret_cast<const VT *>(buf + rl * RUN + j * V);
-#pragma unroll
-    for (int i = 0; i < V; ++i) X[j * V + i] = T(v[i]);
-  }
+  stage_to_regs<N, TI, T>(X, buf);
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -311,13 +333,7 @@ __device__ __forceinline__ void store_group(const T (&X)[N], TI *__restrict__ y,
   typedef typename Vec16<TI>::type VT;
   constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
   const int rl = row_lane();
-#pragma unroll
-  for (int j = 0; j < N / V; ++j) {
-    VT v;
-#pragma unroll
-    for (int i = 0; i < V; ++i) v[i] = (TI)(X[j * V + i] * gain);
-    *reinterpret_cast<VT *>(buf + rl * RUN + j * V) = v;
-  }
+  regs_to_stage<N, TI, T>(X, gain, buf);
   __builtin_amdgcn_wave_barrier();
   if (full) {
     VT *dst = reinterpret_cast<VT *>(y + g);

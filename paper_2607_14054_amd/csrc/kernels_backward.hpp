@@ -1,0 +1,308 @@
+// Adjoint of the cascade (reverse-mode gradient) on the tile machinery.
+//
+// For y = F_K ... F_1 x with section k mapping its input u_k to its output
+// w_k = u_{k+1} (A_k w_k = B_k u_k in the matrix form of Section II, A_k and
+// B_k lower-triangular banded Toeplitz), and a loss with upstream gradient
+// lambda_K = dL/dy:
+//   mu_k = A_k^{-T} lambda_k,      lambda_{k-1} = B_k^T mu_k,  dL/dx = lambda_0,
+//   dL/db_j = sum_i mu_k[i] u_k[i-j],   dL/da_j = -sum_i mu_k[i] w_k[i-j].
+// A^{-T} and B^T are the same filters run backwards in time, so in reversed
+// time r[t] = s[n' - 1 - t] every step is a causal filter again: the all-pole
+// 1/A_k (the PH solve of Section VI-B with a trivial numerator) and the FIR
+// B_k.  The sums become sum_t mu_r[t - j] u_r[t], lags of mu that the FIR
+// already reads, so they are fused into it.
+//
+// Two kernels: a forward PH pass that writes every section's output w_k
+// (true scale) to the workspace, and the reversed-time adjoint pass that
+// reads them back one section at a time.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace sosf {
+
+// Sum over the 16 lanes of a row, in every lane of the row.
+template <typename T>
+__device__ __forceinline__ T row_sum(T v) {
+  v += shr<1>(v);
+  v += shr<2>(v);
+  v += shr<4>(v);
+  v += shr<8>(v);
+  return last_of_row(v);
+}
+
+// Reversed-time group I/O.  A signal s of n samples is read as
+// r[t] = s[np - 1 - t], np = n rounded up to the vector width (r[t] = 0 for
+// t < np - n); the row's group g of r is the ascending source range
+// [np - g - G, np - g), moved with 16-byte vectors reversed in the stage.
+// full: every row's range lies inside [0, n).
+template <int N, typename TI, typename T>
+__device__ __forceinline__ void load_group_rev(T (&X)[N], const TI *__restrict__ x, int64_t g,
+                                               int64_t n, int64_t np, bool full,
+                                               TI *__restrict__ buf) {
+  typedef typename Vec16<TI>::type VT;
+  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN, G = N * kL;
+  const int rl = row_lane();
+  if (full) {
+    const VT *src = reinterpret_cast<const VT *>(x + (np - g - G));
+#pragma unroll
+    for (int j = 0; j < N / V; ++j) {
+      const int e = G - V - (j * kL + rl) * V;   // reversed position of the vector's last element
+      const VT v = __builtin_nontemporal_load(src + j * kL + rl);
+      VT w;
+#pragma unroll
+      for (int i = 0; i < V; ++i) w[i] = v[V - 1 - i];
+      *reinterpret_cast<VT *>(buf + (e / N) * RUN + (e % N)) = w;
+    }
+  } else {
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+      const int e = j * kL + rl;
+      const int64_t i = np - 1 - g - e;
+      buf[(e / N) * RUN + (e % N)] = (i >= 0 && i < n) ? x[i] : TI(0);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  stage_to_regs<N, TI, T>(X, buf);
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <int N, typename TI, typename T>
+__device__ __forceinline__ void store_group_rev(const T (&X)[N], TI *__restrict__ y, int64_t g,
+                                                int64_t n, int64_t np, bool full,
+                                                TI *__restrict__ buf) {
+  typedef typename Vec16<TI>::type VT;
+  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN, G = N * kL;
+  const int rl = row_lane();
+  regs_to_stage<N, TI, T>(X, T(1), buf);
+  __builtin_amdgcn_wave_barrier();
+  if (full) {
+    VT *dst = reinterpret_cast<VT *>(y + (np - g - G));
+#pragma unroll
+    for (int j = 0; j < N / V; ++j) {
+      const int e = G - V - (j * kL + rl) * V;
+      const VT w = *reinterpret_cast<const VT *>(buf + (e / N) * RUN + (e % N));
+      VT v;
+#pragma unroll
+      for (int i = 0; i < V; ++i) v[i] = w[V - 1 - i];
+      __builtin_nontemporal_store(v, dst + j * kL + rl);
+    }
+  } else {
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+      const int e = j * kL + rl;
+      const int64_t i = np - 1 - g - e;
+      if (i >= 0 && i < n) y[i] = buf[(e / N) * RUN + (e % N)];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// All-pole part of a section by PH (Section VI-B with b = (1, 0, 0)): X := (1/A) X
+// on the group, ys = (y[-2], y[-1]) of the output, replaced by the group's
+// last two outputs.
+template <int N>
+__device__ __forceinline__ void allpole_ph(double (&X)[N], ctab<double> c, double *ys) {
+  typedef double T;
+  const T a1 = c[OFF_A1], a2 = c[OFF_A2];
+  const T ys2 = ys[0], ys1 = ys[1];
+  const bool l0 = row_lane() == 0;
+  particular_pass<N, T>(X, a1, a2, l0 ? ys1 : T(0), l0 ? ys2 : T(0));
+  T p = X[N - 2], q = X[N - 1];
+  row_scan_2x2(p, q, c + OFF_PH_POW);
+  X[N - 2] = p;
+  X[N - 1] = q;
+  const T pr = shr<1>(p), qr = shr<1>(q);
+  const ctab<T> u1 = c + OFF_U1;
+  const ctab<T> u2 = c + OFF_U1 + N;
+#pragma unroll
+  for (int m = 0; m < N - 2; ++m) X[m] = fma_(-u2[m], pr, fma_(-u1[m], qr, X[m]));
+  ys[0] = last_of_row(p);
+  ys[1] = last_of_row(q);
+}
+
+// Adjoint rows per section (kBwdRow doubles): b0 b1 b2 a1 a2 (divided by a0,
+// b0 not factored), the forward pass's cumulative b0 scale, the caller's a0.
+enum : int { BW_B0 = 0, BW_B1 = 1, BW_B2 = 2, BW_A1 = 3, BW_A2 = 4, BW_SCALE = 5, BW_A0 = 6 };
+
+struct BwdArgs {
+  int64_t n, np;            // samples; n rounded up to the vector width
+  int64_t tile, warm, ntiles;
+  int64_t sstride;          // elements between saved section outputs
+  int32_t K, stride;
+};
+
+// Forward pass that saves w_k (true scale, FP64) of every section k to
+// saved + k * sstride.  PH, FP64 arithmetic, tiles as in sos_rows_kernel.
+template <int N, typename TI, bool B0ONE>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
+    const TI *__restrict__ x, double *__restrict__ saved, const double *__restrict__ tab,
+    const double *__restrict__ bwd, BwdArgs a) {
+  typedef double T;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  // the stage holds one group per row in FP64 (the saved outputs), which
+  // also fits the input's group
+  unsigned char *stage = smem;
+  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, double>());
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (wave * kRows >= a.ntiles) return;
+  const int row = lane_id() >> 4;
+  const int64_t t0 = (wave * kRows + row) * a.tile;
+  T *st = state + (int64_t)(w * kRows + row) * state_elems(a.K);
+  unsigned char *rowbuf = stage + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  TI *buf = reinterpret_cast<TI *>(rowbuf);
+  double *dbuf = reinterpret_cast<double *>(rowbuf);
+  const ctab<T> ct = as_ctab(tab), cb = as_ctab(bwd);
+  for (int i = 0; i < state_elems(a.K); ++i) st[i] = T(0);
+  const int64_t G = (int64_t)N * kL;
+  const int64_t warm_groups = a.warm / G, steps = warm_groups + a.tile / G;
+  T X[N];
+  for (int64_t it = 0; it < steps; ++it) {
+    const int64_t g = t0 - a.warm + it * G;
+    const bool full = __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= a.n)) == 0;
+    const bool live = it >= warm_groups;
+    load_group<N, TI, T>(X, x, g, a.n, full, buf);
+    T xs2 = st[0], xs1 = st[1];
+    st[0] = last_of_row(X[N - 2]);
+    st[1] = last_of_row(X[N - 1]);
+    for (int k = 0; k < a.K; ++k) {
+      ph_section<N, T, B0ONE>(X, ct + (int64_t)k * a.stride, xs2, xs1, st + 2 + 2 * k);
+      if (live) store_group<N, double, T>(X, saved + (int64_t)k * a.sstride, g, a.n, full,
+                                          cb[kBwdRow * k + BW_SCALE], dbuf);
+    }
+  }
+}
+
+// Reversed-time adjoint.  Row r of wavefront w takes reversed-time tile
+// t = 4w + r: run-in, then per group lambda = r(gy), and for k = K-1 .. 0
+// mu = (1/A_k) lambda, the five sums of section k, lambda = B_k mu; the
+// group's final lambda is r(dL/dx).  Per row, the sums of the tile's groups
+// go to partials[t][k][0..4]: sum mu[t] u[t], mu[t-1] u[t], mu[t-2] u[t],
+// mu[t-1] w[t], mu[t-2] w[t] (reversed time, t over the tile).
+template <int N, typename TI>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
+    const TI *__restrict__ gy, TI *__restrict__ gx, const TI *__restrict__ x,
+    const double *__restrict__ saved, const double *__restrict__ tab, const double *__restrict__ bwd,
+    double *__restrict__ partials, BwdArgs a) {
+  typedef double T;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  unsigned char *stage = smem;   // one FP64 group per row
+  // per row: the 2K output states of the all-pole stages, then 5K sums
+  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, double>());
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (wave * kRows >= a.ntiles) return;
+  const int row = lane_id() >> 4;
+  const int64_t tile_index = wave * kRows + row;
+  const int64_t t0 = tile_index * a.tile;
+  T *st = state + (int64_t)(w * kRows + row) * (7 * a.K);
+  T *acc = st + 2 * a.K;
+  unsigned char *rowbuf = stage + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  TI *buf = reinterpret_cast<TI *>(rowbuf);
+  double *dbuf = reinterpret_cast<double *>(rowbuf);
+  const ctab<T> ct = as_ctab(tab), cb = as_ctab(bwd);
+  for (int i = 0; i < 7 * a.K; ++i) st[i] = T(0);
+  const int64_t G = (int64_t)N * kL;
+  const int64_t pad = a.np - a.n;
+  const int64_t warm_groups = a.warm / G, steps = warm_groups + a.tile / G;
+  T X[N], U[N], Wk[N];
+  for (int64_t it = 0; it < steps; ++it) {
+    const int64_t g = t0 - a.warm + it * G;
+    const bool full = __builtin_amdgcn_ballot_w64(!(g >= pad && g + G <= a.np)) == 0;
+    const bool live = it >= warm_groups;   // uniform per wave
+    load_group_rev<N, TI, T>(X, gy, g, a.n, a.np, full, buf);
+    if (live)
+      load_group_rev<N, double, T>(Wk, saved + (int64_t)(a.K - 1) * a.sstride, g, a.n, a.np, full, dbuf);
+    for (int k = a.K - 1; k >= 0; --k) {
+      const ctab<T> c = ct + (int64_t)k * a.stride;
+      const ctab<T> b = cb + kBwdRow * k;
+      T *ys = st + 2 * k;
+      const T old2 = ys[0], old1 = ys[1];
+      allpole_ph<N>(X, c, ys);                                 // X = mu_k
+      const T m1 = shift_r(X[N - 1], old1), m2 = shift_r(X[N - 2], old2);
+      const T b0 = b[BW_B0], b1 = b[BW_B1], b2 = b[BW_B2];
+      if (live) {
+        if (k == 0)
+          load_group_rev<N, TI, T>(U, x, g, a.n, a.np, full, buf);
+        else
+          load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * a.sstride, g, a.n, a.np, full, dbuf);
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0), s4 = T(0);
+#pragma unroll
+        for (int m = N - 1; m >= 0; --m) {
+          const T p1 = m >= 1 ? X[m - 1] : m1;
+          const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? m1 : m2);
+          s0 = fma_(X[m], U[m], s0);
+          s1 = fma_(p1, U[m], s1);
+          s2 = fma_(p2, U[m], s2);
+          s3 = fma_(p1, Wk[m], s3);
+          s4 = fma_(p2, Wk[m], s4);
+          X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
+        }
+        s0 = row_sum(s0);
+        s1 = row_sum(s1);
+        s2 = row_sum(s2);
+        s3 = row_sum(s3);
+        s4 = row_sum(s4);
+        T *ak = acc + 5 * k;
+        ak[0] += s0;
+        ak[1] += s1;
+        ak[2] += s2;
+        ak[3] += s3;
+        ak[4] += s4;
+#pragma unroll
+        for (int m = 0; m < N; ++m) Wk[m] = U[m];
+      } else {
+#pragma unroll
+        for (int m = N - 1; m >= 0; --m) {
+          const T p1 = m >= 1 ? X[m - 1] : m1;
+          const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? m1 : m2);
+          X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
+        }
+      }
+    }
+    if (live) store_group_rev<N, TI, T>(X, gx, g, a.n, a.np, full, buf);
+  }
+  // one lane per row writes the row's sums (rows past the last tile, in the
+  // last wavefront, have none)
+  if (row_lane() == 0 && tile_index < a.ntiles)
+    for (int i = 0; i < 5 * a.K; ++i) partials[tile_index * 5 * a.K + i] = acc[i];
+}
+
+// dL/d(sos) from the per-tile sums: block k sums partials[t][k][j] over the
+// tiles in a fixed order (deterministic), then applies the chain rule
+// through the division by a0: with normalised c = (b0, b1, b2, a1, a2)/a0,
+// dL/db_j = gb_j / a0, dL/da_j = ga_j / a0 (j = 1, 2) and
+// dL/da0 = -(gb . (b0, b1, b2) + ga . (a1, a2)) / a0.
+__global__ __launch_bounds__(256) void sos_adjoint_reduce_kernel(const double *__restrict__ partials,
+                                                                 int64_t ntiles, int32_t K,
+                                                                 const double *__restrict__ bwd,
+                                                                 double *__restrict__ gsos) {
+  __shared__ double red[5][256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double s[5] = {0, 0, 0, 0, 0};
+  for (int64_t t = tid; t < ntiles; t += 256)
+    for (int j = 0; j < 5; ++j) s[j] += partials[(t * K + k) * 5 + j];
+  for (int j = 0; j < 5; ++j) red[j][tid] = s[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int j = 0; j < 5; ++j) red[j][tid] += red[j][tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double *b = bwd + kBwdRow * k;
+    const double a0 = b[BW_A0];
+    const double gb0 = red[0][0], gb1 = red[1][0], gb2 = red[2][0];
+    const double ga1 = -red[3][0], ga2 = -red[4][0];
+    double *g = gsos + 6 * k;
+    g[0] = gb0 / a0;
+    g[1] = gb1 / a0;
+    g[2] = gb2 / a0;
+    g[3] = -(gb0 * b[BW_B0] + gb1 * b[BW_B1] + gb2 * b[BW_B2] + ga1 * b[BW_A1] + ga2 * b[BW_A2]) / a0;
+    g[4] = ga1 / a0;
+    g[5] = ga2 / a0;
+  }
+}
+
+}  // namespace sosf

@@ -84,6 +84,9 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
   p.b0_factored = factor;
   p.gain = 1.0;
   p.rows = nrm;
+  p.rows_norm = nrm;
+  p.a0.resize(K);
+  for (int k = 0; k < K; ++k) p.a0[k] = sos[6 * k + 3];
   if (factor) {
     for (int k = 0; k < K; ++k) {
       double *o = &p.rows[5 * k];

@@ -13,6 +13,8 @@ constexpr int kL = 16;           // block size L = lanes of one DPP row
 constexpr int kLogL = 4;
 constexpr int kRows = 4;         // independent blocks (rows) per 64-wide wavefront
 constexpr int kMaxLevels = 10;   // log2 of the largest N the tables hold
+constexpr int kBwdN = 16;        // N of the adjoint kernels
+constexpr int kBwdRow = 8;       // doubles per section in the adjoint rows
 
 // Offsets (in elements of the compute dtype) inside one section's row of the
 // device table.  Row length = tab_stride(N).
@@ -36,6 +38,8 @@ struct sos_plan_s {
   bool b0_factored = false;
   double gain = 1.0;
   std::vector<double> rows;        // K x 5: b0 b1 b2 a1 a2 as the kernel uses them
+  std::vector<double> rows_norm;   // K x 5: b0 b1 b2 a1 a2 divided by a0, b0 not factored
+  std::vector<double> a0;          // K: the caller's a0
   std::vector<int32_t> solver;     // K: SOS_PH or SOS_CR
   std::vector<double> C;           // K x 4
   std::vector<double> cr_term;     // K x 2: e, f at the terminal level
@@ -55,9 +59,19 @@ struct sos_plan_s {
   int simds = 1024, waves_per_simd = 4;   // residency of the plan's kernel (launch-shape model)
   void *d_table = nullptr;         // device copy in the compute dtype
   void *d_solver = nullptr;        // device int8 per section: 1 = PH, 2 = CR
+  // adjoint support (device plans only): a PH plan of the same cascade with
+  // N = kBwdN and FP64 arithmetic, and per section the rows of the adjoint
+  // (b0 b1 b2 a1 a2 unfactored, the cumulative b0 gain of the forward
+  // pass's scaling, the caller's a0)
+  sos_plan_s *bwd = nullptr;
+  void *d_bwd_rows = nullptr;
 };
 
 namespace sosf {
 sos_status build_plan_tables(sos_plan_s &p, const double *sos);
 void build_deferred_tables(sos_plan_s &p);
+// the adjoint's sub-plan and rows (sosfilt_backward.hip)
+sos_status attach_adjoint(sos_plan_s &p, const double *sos);
 }
+sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
+                       sos_plan_t *out);

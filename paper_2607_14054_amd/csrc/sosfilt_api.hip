@@ -177,6 +177,16 @@ const char *sos_status_string(sos_status s) {
 }
 
 sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan_t *out) {
+  if (opts && (opts->flags & ~SOS_FLAG_HOST_ONLY)) return SOS_E_ARG;
+  return create_plan(sos, K, opts, true, out);
+}
+
+}  // extern "C"
+
+// Plan creation; `adjoint` also attaches the adjoint's sub-plan (device
+// plans only).
+sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
+                       sos_plan_t *out) {
   if (!sos || !out || K < 1 || K > SOS_MAX_SECTIONS) return SOS_E_ARG;
   sos_opts o{SOS_F32, SOS_F64, SOS_AUTO, 0, 0, 0, 0};
   if (opts) o = *opts;
@@ -217,6 +227,7 @@ sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan
                                    p->K, &r);
     p->simds = r.simds;
     p->waves_per_simd = r.waves_per_simd;
+    if (st == SOS_OK && adjoint) st = attach_adjoint(*p, sos);
   }
   if (st != SOS_OK) {
     sos_plan_destroy(p);
@@ -225,6 +236,8 @@ sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan
   *out = p;
   return SOS_OK;
 }
+
+extern "C" {
 
 sos_status sos_plan_destroy(sos_plan_t p) {
   if (!p) return SOS_OK;
@@ -236,8 +249,10 @@ sos_status sos_plan_destroy(sos_plan_t p) {
     if (p->d_solver) hipFree(p->d_solver);
     if (p->d_theta) hipFree(p->d_theta);
     if (p->d_coupling) hipFree(p->d_coupling);
+    if (p->d_bwd_rows) hipFree(p->d_bwd_rows);
     if (p->device >= 0 && cur >= 0 && cur != p->device) hipSetDevice(cur);
   }
+  if (p->bwd) sos_plan_destroy(p->bwd);
   delete p;
   return SOS_OK;
 }

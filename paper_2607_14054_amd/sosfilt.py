@@ -26,7 +26,8 @@ SOS_FLAG_HOST_ONLY = 0x1
 
 EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_plan_tile",
             "sos_workspace_size", "sos_filt", "sos_batch_plan", "sos_batch_destroy",
-            "sos_batch_query", "sos_filt_batched", "sos_batch_tune", "sos_status_string"]
+            "sos_batch_query", "sos_filt_batched", "sos_batch_tune", "sos_backward_workspace_size",
+            "sos_filt_backward", "sos_status_string"]
 
 _DTYPES = {"f32": SOS_F32, "f64": SOS_F64, np.float32: SOS_F32, np.float64: SOS_F64}
 _SOLVERS = {"auto": SOS_AUTO, "ph": SOS_PH, "cr": SOS_CR, "phd": SOS_PH_DEFERRED}
@@ -92,9 +93,12 @@ def lib():
         L.sos_batch_tune.argtypes = [ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), pi32, i32, p64, p64,
                                      ctypes.POINTER(_Opts), pi32, i32, pi32, i32, vp, vp, i32, vp,
                                      ctypes.POINTER(_TuneResult), ctypes.POINTER(_TuneResult)]
+        L.sos_backward_workspace_size.argtypes = [vp, i64]
+        L.sos_backward_workspace_size.restype = ctypes.c_size_t
+        L.sos_filt_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt",
                   "sos_batch_plan", "sos_batch_destroy", "sos_batch_query", "sos_filt_batched",
-                  "sos_batch_tune"):
+                  "sos_batch_tune", "sos_filt_backward"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -313,3 +317,27 @@ def batch_tune(sos_list, lengths, x, y, offsets=None, io_dtype="f32", compute_dt
                                 _stream_ptr(stream), res, ctypes.byref(best)), "sos_batch_tune")
     rows = [{"N": r.N, "tile_groups": r.tile_groups, "seconds": r.seconds} for r in res]
     return {"N": best.N, "tile_groups": best.tile_groups, "seconds": best.seconds}, rows
+
+
+def filt_backward(plan: Plan, x, gy, gx=None, stream=None):
+    """(gx, gsos) for y = cascade(x) and upstream gradient gy: 1-D device
+    tensors of the plan's io dtype; gsos is a [K, 6] float64 device tensor
+    with respect to the rows (b0, b1, b2, a0, a1, a2)."""
+    import torch
+    want = torch.float32 if plan.io_dtype == "f32" else torch.float64
+    for name, t in (("x", x), ("gy", gy)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.dim() == 1
+                and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous 1-D device tensor of dtype %s" % (name, want))
+    if gy.shape != x.shape:
+        raise ValueError("gy must have the shape of x")
+    n = x.numel()
+    if gx is None:
+        gx = torch.empty_like(x)
+    gsos = torch.empty((plan.K, 6), dtype=torch.float64, device=x.device)
+    ws = int(lib().sos_backward_workspace_size(plan.handle, n))
+    wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=x.device)
+    _check(lib().sos_filt_backward(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                   ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gsos.data_ptr()), n,
+                                   ctypes.c_void_p(wsb.data_ptr()), _stream_ptr(stream)), "sos_filt_backward")
+    return gx, gsos

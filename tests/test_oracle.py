@@ -259,3 +259,20 @@ def test_pins_catch_planted_mistakes(slip):
     ref[2:] += 0.3 * h0[:-2]
     assert oracle.rel_rms(good, ref) < 1e-13
     assert oracle.rel_rms(bad, ref) > 1e-3
+
+
+def test_extended_precision_adjoint_pins():
+    """The long-double adjoint (the arbiter of FP64 adjoints): its dL/dx
+    equals the extended-precision forward cascade run on the time-reversed
+    upstream gradient (H^T = J H J for a Toeplitz H, J the reversal), and its
+    dL/dsos agrees with the FP64 adjoint to that adjoint's rounding."""
+    sos = W.make_sos(8, 0.5, 0.95, 48)
+    x = W.make_signal(3000, 41, np.float64)
+    g = W.grad_seed_signal(3000, 41, np.float64)
+    lx, ls = oracle.sosfilt_backward_ld(x, sos, g)
+    ref = oracle.sosfilt_ld(g[::-1].copy(), sos)[::-1]
+    assert oracle.rel_rms(lx, ref) < 1e-15
+    ox, os_ = oracle.sosfilt_backward(x, sos, g)
+    scale = np.max(np.abs(ls), axis=1, keepdims=True)
+    assert np.max(np.abs(os_ - ls) / scale) < 1e-9
+    assert oracle.rel_rms(ox, lx) < 1e-11
