@@ -135,6 +135,164 @@ def bench_batch(S, W, torch, dev, args):
     return out
 
 
+HEADLINE_SOURCES = ("kernels.hpp", "plan.hpp", "plan.cpp", "dispatch.hpp", "sosfilt_api.hip")
+
+
+def kernel_source_hash():
+    """Digest of the sources the single-signal tile kernel and its launch
+    are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2607_14054_amd", "csrc")
+    for f in HEADLINE_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(N, solver_opt, solvers, n):
+    """HBM bytes per launch of the headline kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same
+    counter's reading for a plain copy of known size), or None when the
+    summary does not cover this configuration or the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("source_hash") != kernel_source_hash() or t.get("N") != N
+            or t.get("solvers") != solvers or t.get("n") != n):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def bench_grad(S, W, torch, dev, args):
+    """The adjoint workload: 64 channels x 2^18 float32 samples, K = 8,
+    r in [0.5, 0.95], loss sum(y * g) with g ~ N(0, 1) (seed + 2); channel c
+    drawn with seed c.  Per channel one forward (sos_filt) and one backward
+    (sos_filt_backward) on the same stream; the 64 channels run back to back
+    and the whole pass is timed.  A sample of channels is checked against the
+    oracle adjoint."""
+    cfg = W.CONFIGS["grad"]
+    C, n = cfg.channels, cfg.n
+    plans, xs, gs, sos = [], [], [], []
+    for c in range(C):
+        s_c = W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed + c)
+        sos.append(s_c)
+        plans.append(S.Plan(s_c, io_dtype="f32", compute_dtype="f64", solver="auto", N=64))
+        xs.append(torch.from_numpy(W.make_signal(n, cfg.seed + c, np.float32)).to(dev))
+        gs.append(torch.from_numpy(W.grad_seed_signal(n, cfg.seed + c, np.float32)).to(dev))
+    ys = [torch.empty_like(xs[0]) for _ in range(C)]
+    gxs = [torch.empty_like(xs[0]) for _ in range(C)]
+    gsos = [torch.empty((cfg.K, 6), dtype=torch.float64, device=dev) for _ in range(C)]
+    wsz = max(S.lib().sos_backward_workspace_size(p.handle, n) for p in plans)
+    import ctypes
+    lib = S.lib()
+    # the channels are independent: spread them over a few streams (the
+    # device runs up to four hardware queues), one workspace per stream
+    nstreams = 4
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    wss = [torch.empty(wsz, dtype=torch.uint8, device=dev) for _ in range(nstreams)]
+    main = torch.cuda.current_stream()
+
+    def one_pass():
+        ev = torch.cuda.Event()
+        ev.record(main)
+        for st in streams:
+            st.wait_event(ev)
+        for c in range(C):
+            st = streams[c % nstreams]
+            S.filt(plans[c], xs[c], ys[c], stream=st)
+            rc = lib.sos_filt_backward(plans[c].handle, ctypes.c_void_p(xs[c].data_ptr()),
+                                       ctypes.c_void_p(gs[c].data_ptr()), ctypes.c_void_p(gxs[c].data_ptr()),
+                                       ctypes.c_void_p(gsos[c].data_ptr()), n,
+                                       ctypes.c_void_p(wss[c % nstreams].data_ptr()),
+                                       ctypes.c_void_p(st.cuda_stream))
+            if rc != 0:
+                raise RuntimeError("sos_filt_backward failed: %d" % rc)
+        for st in streams:
+            done = torch.cuda.Event()
+            done.record(st)
+            main.wait_event(done)
+
+    one_pass()
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 4)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(main)
+    for _ in range(steps):
+        one_pass()
+    e1.record(main)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / steps
+    total = C * n
+    out = {"channels": C, "samples": total, "K": cfg.K, "ms": sec * 1e3, "GSps": total / sec / 1e9}
+    log("grad: %d x %d forward+backward %.3f ms  %.1f GS/s" % (C, n, sec * 1e3, total / sec / 1e9))
+    if not args.no_cpu:
+        import oracle
+        worst_x, worst_s = 0.0, 0.0
+        for c in (0, C // 2, C - 1):
+            rx, rs = oracle.sosfilt_backward(xs[c].cpu().numpy().astype(np.float64), sos[c],
+                                             gs[c].cpu().numpy().astype(np.float64))
+            worst_x = max(worst_x, oracle.rel_rms(gxs[c].cpu().numpy(), rx))
+            g = gsos[c].cpu().numpy()
+            worst_s = max(worst_s, float(np.max(np.abs(g - rs) / np.max(np.abs(rs), axis=1, keepdims=True))))
+        out["gx_rel_rms_max"] = worst_x
+        out["gsos_row_err_max"] = worst_s
+        log("grad: sampled channels gx rel_rms %.2e, gsos row err %.2e" % (worst_x, worst_s))
+    return out
+
+
+def bench_precision(S, W, torch, dev, args):
+    """The precision workload: 256 channels x 2^20 float32 samples, K = 8,
+    pole radius U[0.9, 0.999], channel c drawn with seed c.  One batched
+    launch per arithmetic type; the relative RMS and max error against the
+    FP64 oracle on a sample of channels, with the plain sequential FP32
+    cascade's error on the same channels (the FP32 floor)."""
+    cfg = W.CONFIGS["precision"]
+    C, n = cfg.channels, cfg.n
+    sos = [W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed + c) for c in range(C)]
+    xb = torch.empty(C * n, dtype=torch.float32, device=dev)
+    for c in range(C):
+        xb[c * n:(c + 1) * n] = torch.from_numpy(W.make_signal(n, cfg.seed + c, np.float32)).to(dev)
+    pick = [0, 1, C // 3, C // 2, C - 1]
+    refs = {}
+    if not args.no_cpu:
+        import oracle
+        for c in pick:
+            x_c = xb[c * n:(c + 1) * n].cpu().numpy()
+            refs[c] = (oracle.sosfilt(x_c, sos[c]), oracle.sosfilt_f32arith(x_c, sos[c]))
+    out = {"channels": C, "samples": C * n, "rows": []}
+    for compute, solver, N in (("f64", "auto", 64), ("f64", "ph", 64), ("f32", "ph", 64), ("f32", "cr", 64)):
+        plans = [S.Plan(s_, io_dtype="f32", compute_dtype=compute, solver=solver, N=N) for s_ in sos]
+        b = S.Batch(plans, [n] * C)
+        yb = S.filt_batched(b, xb)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            S.filt_batched(b, xb, yb)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / 3
+        row = {"compute": compute, "solver": solver, "N": N, "GSps": C * n / sec / 1e9}
+        if refs:
+            import oracle
+            errs = [oracle.rel_rms(yb[c * n:(c + 1) * n].cpu().numpy(), refs[c][0]) for c in pick]
+            maxs = [oracle.max_rel(yb[c * n:(c + 1) * n].cpu().numpy(), refs[c][0]) for c in pick]
+            floor = [oracle.rel_rms(refs[c][1], refs[c][0]) for c in pick]
+            row.update({"rel_rms_max": max(errs), "rel_rms_median": float(np.median(errs)),
+                        "max_rel_max": max(maxs), "fp32_floor_max": max(floor)})
+        out["rows"].append(row)
+        log("precision %s/%s N=%d: %.1f GS/s %s" % (compute, solver, N, row["GSps"],
+                                                   {k: v for k, v in row.items() if "rel" in k or "floor" in k}))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +306,12 @@ def main():
     ap.add_argument("--sweep", action="store_true", help="also time PH and CR at every N")
     ap.add_argument("--batch", action="store_true",
                     help="also time the batched ragged workload (4096 channels), autotuned, graph-replayed")
+    ap.add_argument("--grad", action="store_true",
+                    help="also time the adjoint workload (64 channels x 2^18, forward + backward)")
+    ap.add_argument("--precision", action="store_true",
+                    help="also report the error per arithmetic type on the precision workload")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the plain copy of the signal (counter calibration)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
@@ -172,6 +336,12 @@ def main():
     log("generated %d samples in %.1f s" % (n, time.time() - t))
     x = torch.from_numpy(x_np).to(dev)
     y = torch.empty_like(x)
+    if args.copy_only:
+        for _ in range(args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log("copy: %d launches of %d bytes read + %d written" % (args.steps, 4 * n, 4 * n))
+        return
 
     N = args.N or 64
     plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=args.solver, N=N,
@@ -220,10 +390,15 @@ def main():
                         % (solver, NN, cd, p2.tile(n) // (16 * NN), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
         extra["sweep"] = rows
 
-    if args.batch:
+    if args.batch or args.grad or args.precision:
         del x, y
         torch.cuda.empty_cache()
+    if args.batch:
         extra["batch"] = bench_batch(S, W, torch, dev, args)
+    if args.grad:
+        extra["grad"] = bench_grad(S, W, torch, dev, args)
+    if args.precision:
+        extra["precision"] = bench_precision(S, W, torch, dev, args)
 
     cpu = None
     accuracy = {}
@@ -258,7 +433,8 @@ def main():
                                "pole radius U[0.8,0.98], seed 0" % args.log2n,
                    "io_dtype": "f32", "N": info.N, "L": info.L, "solver": args.solver},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(N, args.solver, info.solver, n)},
         "cpu_baseline": cpu,
         "accuracy": accuracy,
     }
