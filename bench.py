@@ -266,16 +266,27 @@ def bench_precision(S, W, torch, dev, args):
             x_c = xb[c * n:(c + 1) * n].cpu().numpy()
             refs[c] = (oracle.sosfilt(x_c, sos[c]), oracle.sosfilt_f32arith(x_c, sos[c]))
     out = {"channels": C, "samples": C * n, "rows": []}
-    for compute, solver, N in (("f64", "auto", 64), ("f64", "ph", 64), ("f32", "ph", 64), ("f32", "cr", 64)):
+    for compute, solver, N in (("f64", "auto", 64), ("f64", "ph", 64), ("f32", "ph", 64), ("f32", "cr", 64),
+                               ("f64", "block", 64), ("f16", "block", 64), ("bf16", "block", 64)):
         plans = [S.Plan(s_, io_dtype="f32", compute_dtype=compute, solver=solver, N=N) for s_ in sos]
-        b = S.Batch(plans, [n] * C)
-        yb = S.filt_batched(b, xb)
+        yb = torch.empty_like(xb)
+        if solver == "block":
+            # comparison solver, not batched: one launch per channel
+            def once():
+                for c in range(C):
+                    S.filt(plans[c], xb[c * n:(c + 1) * n], yb[c * n:(c + 1) * n])
+        else:
+            b = S.Batch(plans, [n] * C)
+
+            def once():
+                S.filt_batched(b, xb, yb)
+        once()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(3):
-            S.filt_batched(b, xb, yb)
+            once()
         e1.record()
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3 / 3
@@ -374,20 +385,21 @@ def main():
 
     if args.sweep:
         rows = []
-        for solver in ("ph", "cr", "phd"):
-            for NN in (8, 16, 32, 64):
-                for cd in ("f64", "f32"):
-                    if solver == "phd" and (NN < 16 or cd == "f32"):
-                        continue      # the deferred form: FP64 arithmetic, N >= 16
-                    p2 = S.Plan(sos, io_dtype="f32", compute_dtype=cd, solver=solver, N=NN)
-                    s2 = timed_filter(S, torch, p2, x, y, max(3, args.steps // 2), 2)
-                    i2 = p2.info()
-                    rows.append({"solver": solver, "N": NN, "compute": cd, "tile": p2.tile(n),
-                                 "waves_per_simd": i2.waves_per_simd,
-                                 "ms": s2 * 1e3, "GSps": n / s2 / 1e9,
-                                 "frac_hbm": 8.0 * n / s2 / 1e9 / HBM_PEAK_GBS})
-                    log("sweep %s N=%2d %s: tile=%d occ=%d %.3f ms %.1f GS/s"
-                        % (solver, NN, cd, p2.tile(n) // (16 * NN), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
+        cases = [(s_, NN, cd) for s_ in ("ph", "cr", "phd") for NN in (8, 16, 32, 64)
+                 for cd in ("f64", "f32") if not (s_ == "phd" and (NN < 16 or cd == "f32"))]
+        # comparison points: scalar filtering, block filtering (Toeplitz on MFMA)
+        cases += [("scalar", 64, "f64"), ("scalar", 64, "f32"), ("block", 64, "f64"),
+                  ("block", 64, "f16"), ("block", 64, "bf16")]
+        for solver, NN, cd in cases:
+            p2 = S.Plan(sos, io_dtype="f32", compute_dtype=cd, solver=solver, N=NN)
+            s2 = timed_filter(S, torch, p2, x, y, max(3, args.steps // 2), 2)
+            i2 = p2.info()
+            rows.append({"solver": solver, "N": NN, "compute": cd, "tile": p2.tile(n),
+                         "waves_per_simd": i2.waves_per_simd,
+                         "ms": s2 * 1e3, "GSps": n / s2 / 1e9,
+                         "frac_hbm": 8.0 * n / s2 / 1e9 / HBM_PEAK_GBS})
+            log("sweep %s N=%2d %s: tile=%d samples occ=%d %.3f ms %.1f GS/s"
+                % (solver, NN, cd, p2.tile(n), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
         extra["sweep"] = rows
 
     if args.batch or args.grad or args.precision:

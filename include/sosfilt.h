@@ -54,16 +54,30 @@ typedef enum {
     SOS_E_NOMEM = 6         /* host or device allocation failed (plan creation only) */
 } sos_status;
 
-typedef enum { SOS_F32 = 0, SOS_F64 = 1 } sos_dtype;
+typedef enum {
+    SOS_F32 = 0,
+    SOS_F64 = 1,
+    SOS_F16 = 2,   /* product type of SOS_BLOCK only: FP16 MFMA, FP32 accumulation */
+    SOS_BF16 = 3   /* product type of SOS_BLOCK only: BF16 MFMA, FP32 accumulation */
+} sos_dtype;
 
 typedef enum {
     SOS_AUTO = 0,        /* cyclic reduction, with PH for sections the CR guard rejects */
     SOS_PH = 1,          /* PH factorisation (Section VI-B) for every section */
     SOS_CR = 2,          /* cyclic reduction (Section VI-C), guard still applies */
-    SOS_PH_DEFERRED = 3  /* PH with the homogeneous correction (eq. PH_forward) of all
+    SOS_PH_DEFERRED = 3, /* PH with the homogeneous correction (eq. PH_forward) of all
                             sections deferred to the end of the cascade and applied as
                             one FP64 matrix-core product; FP64 arithmetic, N >= 16,
                             K <= 16 */
+    SOS_SCALAR = 4,      /* comparison point: scalar filtering (the plain recurrence of
+                            Section II, one lane per segment, run-in carry); K <= 16,
+                            N ignored */
+    SOS_BLOCK = 5        /* block filtering (Section IV, eq. block_filtering_equation):
+                            the 16 x 16 Toeplitz product H x on MFMA in the
+                            compute_dtype (SOS_F64, SOS_F16 or SOS_BF16; FP32
+                            accumulation for the latter two), the boundary terms, the
+                            block-to-block recurrence and the carries in FP64;
+                            K <= 32, N ignored */
 } sos_solver;
 
 /* Plan flags. */
@@ -72,7 +86,8 @@ typedef enum {
 
 typedef struct {
     int32_t io_dtype;       /* sos_dtype of x and y (default SOS_F32) */
-    int32_t compute_dtype;  /* sos_dtype of the in-kernel arithmetic (default SOS_F64) */
+    int32_t compute_dtype;  /* sos_dtype of the in-kernel arithmetic (default SOS_F64); SOS_F16
+                               and SOS_BF16 only with SOS_BLOCK */
     int32_t solver;         /* sos_solver (default SOS_AUTO) */
     int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32) */
     int32_t L;              /* samples per block = lanes of a DPP row: 16 (0 = 16) */
@@ -185,8 +200,8 @@ sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
  *
  * plans    host [C]: channel c is filtered with plans[c] (the same plan may
  *          serve several channels).  All plans must share N, io_dtype and
- *          compute_dtype (else SOS_E_UNSUPPORTED) and none may use
- *          SOS_PH_DEFERRED (SOS_E_UNSUPPORTED).  The plans must outlive the
+ *          compute_dtype (else SOS_E_UNSUPPORTED), and all must use
+ *          SOS_AUTO, SOS_PH or SOS_CR (else SOS_E_UNSUPPORTED).  The plans must outlive the
  *          batch: the batch refers to their device tables.
  * C        number of channels, >= 1.
  * n        host [C]: channel lengths, >= 0.

@@ -1,0 +1,234 @@
+// Block filtering (eq. block_filtering_equation) with the dense Toeplitz
+// product on the matrix cores.
+//
+// A section maps each block of 16 samples by
+//   y_n = H x_n + Gx xbar_{n-1} + Gy ybar_{n-1},
+// H the 16 x 16 lower-triangular Toeplitz matrix of the first 16 impulse
+// response samples, xbar and ybar the last two input and output samples of
+// the previous block, Gx and Gy the block's responses to them (eq.
+// block_filtering_matrices, with the minus sign of H_a folded into Gy).
+//
+// One wavefront filters one tile, 256 samples (16 blocks) at a time.  The
+// 16 blocks are the 16 columns of one MFMA product H X, whose precision is
+// the plan's product type: FP64 (16x16x4 FP64 MFMA), or FP16 / BF16 (16x16x16
+// with FP32 accumulation).  Everything after the product is FP64:
+// * the blocks' terminal outputs chain through the 2 x 2 recurrence
+//   z_j = c_j + M z_{j-1} (M = the last two rows of Gy), solved along the 16
+//   lanes of a DPP row by the same log-depth scan as the PH terminal block;
+//   in the low-precision forms the two terminal rows of H x are recomputed
+//   in FP64, so that no product rounding enters this recurrence;
+// * the boundary correction Gx xbar + Gy ybar of every output (4 FMA per
+//   sample, the paper's 4/L block FMAs);
+// * the carries between groups and sections.
+// In the low-precision forms each section's input is scaled by a power of
+// two (the inverse RMS gain of the sections before it for white input)
+// before rounding, and the product is scaled back in FP64.
+#pragma once
+
+#include "kernels_deferred.hpp"
+
+namespace sosf {
+
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+enum : int { PT_F64 = 0, PT_F16 = 1, PT_BF16 = 2 };
+
+// Per-section FP64 block table (kBlockStride doubles).
+enum : int {
+  BT_GXT = 0,      // 4: rows 14, 15 of Gx, row-major
+  BT_POW = 4,      // 16: M^(2^i), i = 0..3, row-major
+  BT_SCALE = 20,   // input scale before rounding to the product type
+  BT_ISCALE = 21,  // its inverse
+  BT_G = 32,       // 64: per lane row q and register r: Gx[m][0..1], Gy[m][0..1] (m per layout)
+  BT_HT = 96,      // 32: per lane row q and register r: h[14 - m], h[15 - m] (0 past the diagonal)
+  kBlockStride = 128
+};
+constexpr int kBlockGroup = 256;   // samples per MFMA (16 blocks of 16)
+constexpr int kBlockKMax = 32;     // the tables of all sections sit in LDS
+
+struct BlockArgs {
+  int64_t n, tile, warm, ntiles;
+  int32_t K;
+  int32_t pad;
+};
+
+__device__ __forceinline__ short to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+  return (short)(u >> 16);
+}
+
+// Row of the 16 x 16 tile held in register r of lane (q, j): the FP64 MFMA
+// layout is m = q + 4 r, the FP32-accumulating 16x16x16 layout m = 4 q + r.
+template <int PT>
+__host__ __device__ constexpr int block_row(int q, int r) {
+  return PT == PT_F64 ? q + 4 * r : 4 * q + r;
+}
+
+// Four consecutive samples (16-byte aligned) <-> four FP64 values.
+__device__ __forceinline__ void load4(double (&V)[4], const float *p) {
+  const vf4 v = __builtin_nontemporal_load(reinterpret_cast<const vf4 *>(p));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) V[i] = (double)v[i];
+}
+__device__ __forceinline__ void load4(double (&V)[4], const double *p) {
+  const vd2 u = __builtin_nontemporal_load(reinterpret_cast<const vd2 *>(p));
+  const vd2 v = __builtin_nontemporal_load(reinterpret_cast<const vd2 *>(p) + 1);
+  V[0] = u[0];
+  V[1] = u[1];
+  V[2] = v[0];
+  V[3] = v[1];
+}
+__device__ __forceinline__ void store4(float *p, const double (&V)[4]) {
+  vf4 v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = (float)V[i];
+  __builtin_nontemporal_store(v, reinterpret_cast<vf4 *>(p));
+}
+__device__ __forceinline__ void store4(double *p, const double (&V)[4]) {
+  const vd2 u = {V[0], V[1]}, v = {V[2], V[3]};
+  __builtin_nontemporal_store(u, reinterpret_cast<vd2 *>(p));
+  __builtin_nontemporal_store(v, reinterpret_cast<vd2 *>(p) + 1);
+}
+
+template <typename TI, int PT>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
+    const TI *__restrict__ x, TI *__restrict__ y, const double *__restrict__ bt,
+    const void *__restrict__ aop, BlockArgs a) {
+  typedef double T;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  // LDS: the block's copies of the per-lane correction rows and of the MFMA
+  // A operands (every wavefront reads all of them once per group), then the
+  // carries of each wavefront
+  constexpr int AOP = PT == PT_F64 ? 256 * 8 : 256 * 2;   // A-operand bytes per section
+  double *g_s = reinterpret_cast<double *>(smem);   // per section: G (64), then HT (32)
+  unsigned char *a_s = smem + (size_t)a.K * 96 * sizeof(double);
+  for (int i = threadIdx.x; i < a.K * 96; i += kWavesPerBlock * 64)
+    g_s[i] = bt[(int64_t)(i / 96) * kBlockStride + BT_G + (i % 96)];
+  for (int i = threadIdx.x; i < a.K * AOP / 16; i += kWavesPerBlock * 64)
+    reinterpret_cast<vf4 *>(a_s)[i] = reinterpret_cast<const vf4 *>(aop)[i];
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (wave >= a.ntiles) return;
+  const int lane = lane_id(), q = lane >> 4, j = lane & 15;
+  // carries (uniform per wavefront): the raw input's last two samples, then
+  // each section's last two outputs
+  T *st = reinterpret_cast<T *>(a_s + (size_t)a.K * AOP) + w * (2 + 2 * a.K);
+  for (int i = 0; i < 2 + 2 * a.K; ++i) st[i] = T(0);
+  const ctab<T> cb = as_ctab(bt);
+  const int64_t t0 = wave * a.tile;
+  const int64_t steps = (a.warm + a.tile) / kBlockGroup;
+  const int src_prev = 48 + ((j + 15) & 15);   // lane (3, j - 1)
+  for (int64_t it = 0; it < steps; ++it) {
+    const int64_t g = t0 - a.warm + it * kBlockGroup;
+    const int64_t e0 = g + 16 * j + 4 * q;   // this lane's 4 consecutive samples
+    T V[4];
+    if (e0 >= 0 && e0 + 4 <= a.n) {
+      load4(V, x + e0);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) V[i] = (e0 + i >= 0 && e0 + i < a.n) ? T(x[e0 + i]) : T(0);
+    }
+    // the raw input's two samples before block j: lane (3, j - 1), or the carry
+    T xb2 = __shfl(V[2], src_prev), xb1 = __shfl(V[3], src_prev);
+    if (j == 0) {
+      xb2 = st[0];
+      xb1 = st[1];
+    }
+    const T nraw2 = __shfl(V[2], 63), nraw1 = __shfl(V[3], 63);
+    if (PT == PT_F64) row_transpose4(V);   // to the FP64 MFMA layout, m = q + 4 r
+    for (int k = 0; k < a.K; ++k) {
+      const ctab<T> c = cb + (int64_t)k * kBlockStride;
+      T P[4];
+      if (PT == PT_F64) {
+        const double *A = reinterpret_cast<const double *>(a_s) + k * 256;
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s * 64 + lane], V[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[r] = acc[r];
+      } else {
+        const T sc = c[BT_SCALE], isc = c[BT_ISCALE];
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+        if (PT == PT_F16) {
+          const v4h A = reinterpret_cast<const v4h *>(a_s)[k * 64 + lane];
+          v4h B;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) B[r] = (_Float16)(float)(V[r] * sc);
+          acc = __builtin_amdgcn_mfma_f32_16x16x16f16(A, B, acc, 0, 0, 0);
+        } else {
+          const v4s A = reinterpret_cast<const v4s *>(a_s)[k * 64 + lane];
+          v4s B;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) B[r] = to_bf16((float)(V[r] * sc));
+          acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, B, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[r] = T(acc[r]) * isc;
+      }
+      // terminal outputs (rows 14, 15) of block j, in every lane of column j.
+      // The low-precision forms recompute them in FP64 (two rows of H, over
+      // the four lanes of the column): the block-to-block recurrence then
+      // carries no product rounding.
+      T p14, p15;
+      if (PT == PT_F64) {
+        p14 = __shfl(P[3], 32 + j);
+        p15 = __shfl(P[3], 48 + j);
+      } else {
+        const double *ht = g_s + k * 96 + 64 + q * 8;
+        T s14 = T(0), s15 = T(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          s14 = fma_(ht[2 * r], V[r], s14);
+          s15 = fma_(ht[2 * r + 1], V[r], s15);
+        }
+        s14 += __shfl_xor(s14, 16);
+        s15 += __shfl_xor(s15, 16);
+        s14 += __shfl_xor(s14, 32);
+        s15 += __shfl_xor(s15, 32);
+        p14 = s14;
+        p15 = s15;
+        // the outputs of rows 14 and 15 themselves come from the FP64 values
+        if (q == 3) {
+          P[2] = s14;
+          P[3] = s15;
+        }
+      }
+      T c0 = fma_(c[BT_GXT + 1], xb1, fma_(c[BT_GXT + 0], xb2, p14));
+      T c1 = fma_(c[BT_GXT + 3], xb1, fma_(c[BT_GXT + 2], xb2, p15));
+      const T yp2 = st[2 + 2 * k], yp1 = st[3 + 2 * k];
+      if (j == 0) {
+        c0 = fma_(c[BT_POW + 1], yp1, fma_(c[BT_POW + 0], yp2, c0));
+        c1 = fma_(c[BT_POW + 3], yp1, fma_(c[BT_POW + 2], yp2, c1));
+      }
+      row_scan_2x2(c0, c1, c + BT_POW);    // z_j: the true last two outputs of block j
+      const T yb2 = shift_r(c0, yp2), yb1 = shift_r(c1, yp1);
+      const double *G = g_s + k * 96 + q * 16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        V[r] = fma_(G[4 * r + 3], yb1, fma_(G[4 * r + 2], yb2, fma_(G[4 * r + 1], xb1, fma_(G[4 * r], xb2, P[r]))));
+      st[2 + 2 * k] = last_of_row(c0);
+      st[3 + 2 * k] = last_of_row(c1);
+      // the next section's input before block j is this section's output there
+      xb2 = yb2;
+      xb1 = yb1;
+    }
+    st[0] = nraw2;
+    st[1] = nraw1;
+    if (g >= t0) {
+      if (PT == PT_F64) row_transpose4(V);   // back to 4 consecutive samples per lane
+      if (e0 >= 0 && e0 + 4 <= a.n) {
+        store4(y + e0, V);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (e0 + i >= 0 && e0 + i < a.n) y[e0 + i] = (TI)V[i];
+      }
+    }
+  }
+}
+
+}  // namespace sosf

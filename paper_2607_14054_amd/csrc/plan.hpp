@@ -5,6 +5,8 @@
 #include <cstdint>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "../../include/sosfilt.h"
 
 namespace sosf {
@@ -65,6 +67,13 @@ struct sos_plan_s {
   // pass's scaling, the caller's a0)
   sos_plan_s *bwd = nullptr;
   void *d_bwd_rows = nullptr;
+  // block filtering (solver SOS_BLOCK): product type, FP64 block tables and
+  // the MFMA A operands of the Toeplitz products
+  int block_pt = 0;
+  std::vector<double> block_tab;
+  std::vector<unsigned char> block_aop;
+  void *d_block = nullptr;
+  void *d_aop = nullptr;
 };
 
 namespace sosf {
@@ -72,6 +81,11 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos);
 void build_deferred_tables(sos_plan_s &p);
 // the adjoint's sub-plan and rows (sosfilt_backward.hip)
 sos_status attach_adjoint(sos_plan_s &p, const double *sos);
+// block filtering plans (sosfilt_block.hip)
+sos_status build_block_plan(sos_plan_s &p);
+sos_status upload_block_plan(sos_plan_s &p);
+int64_t block_tile(const sos_plan_s &p, int64_t n);
+sos_status launch_block(const sos_plan_s &p, const void *x, void *y, int64_t n, hipStream_t s);
 }
 sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
                        sos_plan_t *out);

@@ -10,6 +10,8 @@
 #include "kernels.hpp"
 #include "dispatch.hpp"
 #include "kernels_deferred.hpp"
+#include "kernels_scalar.hpp"
+#include "kernels_block.hpp"
 #include "plan.hpp"
 
 using namespace sosf;
@@ -147,6 +149,62 @@ int solver_mix(const sos_plan_s &p) {
   return mix;
 }
 
+// Scalar filtering (comparison point): kernel instance by I/O and compute
+// type, b0 factoring and the bound on K.
+template <typename TI, typename T, int KMAX>
+const void *scalar_kernel_k(bool b0one) {
+  return b0one ? reinterpret_cast<const void *>(&sos_scalar_kernel<TI, T, true, KMAX>)
+               : reinterpret_cast<const void *>(&sos_scalar_kernel<TI, T, false, KMAX>);
+}
+template <typename TI, typename T>
+const void *scalar_kernel_t(int K, bool b0one) {
+  if (K <= 4) return scalar_kernel_k<TI, T, 4>(b0one);
+  if (K <= 8) return scalar_kernel_k<TI, T, 8>(b0one);
+  return scalar_kernel_k<TI, T, 16>(b0one);
+}
+const void *scalar_kernel(const sos_plan_s &p) {
+  if (p.io_dtype == SOS_F32 && p.compute_dtype == SOS_F32) return scalar_kernel_t<float, float>(p.K, p.b0_factored);
+  if (p.io_dtype == SOS_F32) return scalar_kernel_t<float, double>(p.K, p.b0_factored);
+  return scalar_kernel_t<double, double>(p.K, p.b0_factored);
+}
+size_t scalar_lds(const sos_plan_s &p) {
+  return (size_t)kWavesPerBlock * (p.io_dtype == SOS_F32 ? ScalarStage<float>::ELEMS * 4
+                                                           : ScalarStage<double>::ELEMS * 8);
+}
+Residency scalar_residency(const sos_plan_s &p) {
+  return residency_of(scalar_kernel(p), scalar_lds(p), kWavesPerBlock * 64);
+}
+
+// Segment length of the scalar kernel: every SIMD gets m wavefronts of 64
+// segments, m as in model_tile_groups.
+int64_t scalar_segment(const sos_plan_s &p, int64_t n) {
+  int64_t m = 1;
+  while (2 * m <= p.waves_per_simd) m *= 2;
+  const int64_t lanes = (int64_t)p.simds * m * 64;
+  const int64_t seg = (n + lanes - 1) / lanes;
+  return std::max<int64_t>((seg + kScalarChunk - 1) / kScalarChunk * kScalarChunk, kScalarChunk);
+}
+
+sos_status launch_scalar(const sos_plan_s &p, const void *x, void *y, int64_t n, hipStream_t s) {
+  ScalarArgs a;
+  a.n = n;
+  a.seg = p.tile_groups > 0 ? (int64_t)p.tile_groups * kScalarChunk : scalar_segment(p, n);
+  a.warm = p.warm;
+  a.nseg = (n + a.seg - 1) / a.seg;
+  a.K = p.K;
+  a.stride = p.stride;
+  a.gain = p.gain;
+  const int64_t blocks = (a.nseg + kWavesPerBlock * 64 - 1) / (kWavesPerBlock * 64);
+  const void *xa = x, *ta = p.d_table;
+  void *ya = y;
+  void *args[] = {&xa, &ya, &ta, &a};   // addresses of the kernel's four arguments
+  const void *f = scalar_kernel(p);
+  if (hipLaunchKernel(f, dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), args, scalar_lds(p), s) !=
+      hipSuccess)
+    return SOS_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+}
+
 // Tile length for n samples: the plan's fixed choice, or the launch-shape
 // model for the kernel the plan runs.
 int64_t choose_tile(const sos_plan_s &p, int64_t n) {
@@ -193,13 +251,18 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   if (o.N == 0) o.N = 32;
   if (o.L == 0) o.L = 16;
   if (o.io_dtype != SOS_F32 && o.io_dtype != SOS_F64) return SOS_E_ARG;
-  if (o.compute_dtype != SOS_F32 && o.compute_dtype != SOS_F64) return SOS_E_ARG;
-  if (o.solver < SOS_AUTO || o.solver > SOS_PH_DEFERRED) return SOS_E_ARG;
+  if (o.compute_dtype < SOS_F32 || o.compute_dtype > SOS_BF16) return SOS_E_ARG;
+  if (o.solver < SOS_AUTO || o.solver > SOS_BLOCK) return SOS_E_ARG;
+  const bool low = o.compute_dtype == SOS_F16 || o.compute_dtype == SOS_BF16;
+  if (low && o.solver != SOS_BLOCK) return SOS_E_UNSUPPORTED;
+  if (o.solver == SOS_BLOCK && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
   if (o.tile_groups < 0) return SOS_E_ARG;
   if (!pow2_in(o.N, 8, 64) || o.L != kL) return SOS_E_UNSUPPORTED;
-  if (o.io_dtype == SOS_F64 && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
+  if (o.io_dtype == SOS_F64 && (o.compute_dtype == SOS_F32 || low)) return SOS_E_UNSUPPORTED;
   const bool deferred_ok = o.compute_dtype == SOS_F64 && o.N >= 16 && K <= 16;
   if (o.solver == SOS_PH_DEFERRED && !deferred_ok) return SOS_E_UNSUPPORTED;
+  if (o.solver == SOS_SCALAR && K > kScalarKMax) return SOS_E_UNSUPPORTED;
+  if (o.solver == SOS_BLOCK && K > kBlockKMax) return SOS_E_UNSUPPORTED;
   sos_plan_s *p = new (std::nothrow) sos_plan_s;
   if (!p) return SOS_E_NOMEM;
   p->K = K;
@@ -216,13 +279,28 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
     build_deferred_tables(*p);
     for (int k = 0; k < K; ++k) p->solver[k] = SOS_PH_DEFERRED;
   }
+  if (st == SOS_OK && p->solver_opt == SOS_BLOCK) {
+    for (int k = 0; k < K; ++k) p->solver[k] = SOS_BLOCK;
+    st = build_block_plan(*p);
+  }
+  if (st == SOS_OK && p->solver_opt == SOS_SCALAR) {
+    for (int k = 0; k < K; ++k) p->solver[k] = SOS_SCALAR;
+    // the scalar kernel's run-in moves in whole chunks
+    p->warm = (p->warm + kScalarChunk - 1) / kScalarChunk * kScalarChunk;
+  }
   if (st == SOS_OK && !(o.flags & SOS_FLAG_HOST_ONLY)) {
     st = upload(*p);
     Residency r;
     if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED)
       r = p->io_dtype == SOS_F32 ? deferred_residency<float>(p->N, p->K, p->b0_factored)
                                  : deferred_residency<double>(p->N, p->K, p->b0_factored);
-    else if (st == SOS_OK)
+    else if (st == SOS_OK && p->solver_opt == SOS_SCALAR)
+      r = scalar_residency(*p);
+    else if (st == SOS_OK && p->solver_opt == SOS_BLOCK) {
+      st = upload_block_plan(*p);
+      r.simds = p->simds;
+      r.waves_per_simd = p->waves_per_simd;
+    } else if (st == SOS_OK)
       dispatch_rows<ResidencyRows>(p->N, p->io_dtype, p->compute_dtype, p->b0_factored, solver_mix(*p),
                                    p->K, &r);
     p->simds = r.simds;
@@ -250,6 +328,8 @@ sos_status sos_plan_destroy(sos_plan_t p) {
     if (p->d_theta) hipFree(p->d_theta);
     if (p->d_coupling) hipFree(p->d_coupling);
     if (p->d_bwd_rows) hipFree(p->d_bwd_rows);
+    if (p->d_block) hipFree(p->d_block);
+    if (p->d_aop) hipFree(p->d_aop);
     if (p->device >= 0 && cur >= 0 && cur != p->device) hipSetDevice(cur);
   }
   if (p->bwd) sos_plan_destroy(p->bwd);
@@ -313,6 +393,9 @@ sos_status sos_plan_table(sos_plan_t p, int32_t table, int32_t section, double *
 
 int64_t sos_plan_tile(sos_plan_t p, int64_t n) {
   if (!p || n < 0) return 0;
+  if (p->solver_opt == SOS_SCALAR)
+    return p->tile_groups > 0 ? (int64_t)p->tile_groups * kScalarChunk : scalar_segment(*p, n);
+  if (p->solver_opt == SOS_BLOCK) return block_tile(*p, n);
   return choose_tile(*p, n);
 }
 
@@ -344,6 +427,8 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
   a.gain = p->gain;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const bool b0one = p->b0_factored;
+  if (p->solver_opt == SOS_SCALAR) return launch_scalar(*p, x, y, n, s);
+  if (p->solver_opt == SOS_BLOCK) return launch_block(*p, x, y, n, s);
   if (p->solver_opt == SOS_PH_DEFERRED) {
     if (p->io_dtype == SOS_F32) return launch_deferred<float>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);
     return launch_deferred<double>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);

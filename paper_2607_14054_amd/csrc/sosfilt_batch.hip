@@ -91,7 +91,8 @@ sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
     const sos_plan_s *p = plans[c];
     if (!p || n[c] < 0) return SOS_E_ARG;
     if (!host_only && !p->d_table) return SOS_E_ARG;   // a host-only plan cannot filter
-    if (p->solver_opt == SOS_PH_DEFERRED) return SOS_E_UNSUPPORTED;
+    if (p->solver_opt == SOS_PH_DEFERRED || p->solver_opt == SOS_SCALAR || p->solver_opt == SOS_BLOCK)
+      return SOS_E_UNSUPPORTED;
     if (p->N != plans[0]->N || p->io_dtype != plans[0]->io_dtype ||
         p->compute_dtype != plans[0]->compute_dtype)
       return SOS_E_UNSUPPORTED;

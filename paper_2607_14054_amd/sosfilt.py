@@ -17,8 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsosfilt.so")
 
 SOS_OK, SOS_E_ARG, SOS_E_COEF, SOS_E_UNSTABLE, SOS_E_UNSUPPORTED, SOS_E_DEVICE, SOS_E_NOMEM = range(7)
-SOS_F32, SOS_F64 = 0, 1
-SOS_AUTO, SOS_PH, SOS_CR, SOS_PH_DEFERRED = 0, 1, 2, 3
+SOS_F32, SOS_F64, SOS_F16, SOS_BF16 = 0, 1, 2, 3
+SOS_AUTO, SOS_PH, SOS_CR, SOS_PH_DEFERRED, SOS_SCALAR, SOS_BLOCK = 0, 1, 2, 3, 4, 5
 SOS_FLAG_HOST_ONLY = 0x1
 (SOS_TABLE_ROWS, SOS_TABLE_U1, SOS_TABLE_U2, SOS_TABLE_C, SOS_TABLE_PH_POWERS,
  SOS_TABLE_CR_LEVELS, SOS_TABLE_CR_TERMINAL, SOS_TABLE_CR_POWERS, SOS_TABLE_TRANSITION,
@@ -29,8 +29,11 @@ EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", 
             "sos_batch_query", "sos_filt_batched", "sos_batch_tune", "sos_backward_workspace_size",
             "sos_filt_backward", "sos_status_string"]
 
-_DTYPES = {"f32": SOS_F32, "f64": SOS_F64, np.float32: SOS_F32, np.float64: SOS_F64}
-_SOLVERS = {"auto": SOS_AUTO, "ph": SOS_PH, "cr": SOS_CR, "phd": SOS_PH_DEFERRED}
+_DTYPES = {"f32": SOS_F32, "f64": SOS_F64, "f16": SOS_F16, "bf16": SOS_BF16,
+           np.float32: SOS_F32, np.float64: SOS_F64}
+_DTYPE_NAMES = {SOS_F32: "f32", SOS_F64: "f64", SOS_F16: "f16", SOS_BF16: "bf16"}
+_SOLVERS = {"auto": SOS_AUTO, "ph": SOS_PH, "cr": SOS_CR, "phd": SOS_PH_DEFERRED, "scalar": SOS_SCALAR,
+            "block": SOS_BLOCK}
 
 
 class SosError(RuntimeError):
@@ -165,9 +168,9 @@ class Plan:
         inf = _Info()
         sol = (ctypes.c_int32 * self.K)()
         _check(lib().sos_plan_query(self._h, ctypes.byref(inf), sol), "sos_plan_query")
-        names = {SOS_PH: "ph", SOS_CR: "cr", SOS_PH_DEFERRED: "phd"}
-        return PlanInfo(inf.K, inf.N, inf.L, "f32" if inf.io_dtype == SOS_F32 else "f64",
-                        "f32" if inf.compute_dtype == SOS_F32 else "f64", bool(inf.b0_factored),
+        names = {SOS_PH: "ph", SOS_CR: "cr", SOS_PH_DEFERRED: "phd", SOS_SCALAR: "scalar", SOS_BLOCK: "block"}
+        return PlanInfo(inf.K, inf.N, inf.L, _DTYPE_NAMES[inf.io_dtype],
+                        _DTYPE_NAMES[inf.compute_dtype], bool(inf.b0_factored),
                         int(inf.warm_samples), float(inf.gain), float(inf.transition_norm_W),
                         [names[int(v)] for v in sol], int(inf.simds), int(inf.waves_per_simd))
 
