@@ -246,6 +246,30 @@ def bench_grad(S, W, torch, dev, args):
     return out
 
 
+def bench_grad_long(S, W, torch, dev, args):
+    """The adjoint on one long channel: 2^26 float32 samples, K = 8,
+    r in [0.5, 0.95]; one sos_filt_backward per step."""
+    n = 1 << 26
+    sos = W.make_sos(8, 0.5, 0.95, 0)
+    x = torch.from_numpy(W.make_signal(n, 0, np.float32)).to(dev)
+    g = torch.from_numpy(W.grad_seed_signal(n, 0, np.float32)).to(dev)
+    plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=64)
+    gx = torch.empty_like(x)
+    S.filt_backward(plan, x, g, gx)
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 4)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        S.filt_backward(plan, x, g, gx)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / steps
+    log("grad-long: 2^26 backward %.3f ms  %.1f GS/s" % (sec * 1e3, n / sec / 1e9))
+    return {"samples": n, "ms": sec * 1e3, "GSps": n / sec / 1e9}
+
+
 def bench_precision(S, W, torch, dev, args):
     """The precision workload: 256 channels x 2^20 float32 samples, K = 8,
     pole radius U[0.9, 0.999], channel c drawn with seed c.  One batched
@@ -319,6 +343,8 @@ def main():
                     help="also time the batched ragged workload (4096 channels), autotuned, graph-replayed")
     ap.add_argument("--grad", action="store_true",
                     help="also time the adjoint workload (64 channels x 2^18, forward + backward)")
+    ap.add_argument("--grad-long", action="store_true",
+                    help="also time the adjoint on one long channel (2^26 samples)")
     ap.add_argument("--precision", action="store_true",
                     help="also report the error per arithmetic type on the precision workload")
     ap.add_argument("--copy-only", action="store_true",
@@ -402,13 +428,15 @@ def main():
                 % (solver, NN, cd, p2.tile(n), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
         extra["sweep"] = rows
 
-    if args.batch or args.grad or args.precision:
+    if args.batch or args.grad or args.precision or args.grad_long:
         del x, y
         torch.cuda.empty_cache()
     if args.batch:
         extra["batch"] = bench_batch(S, W, torch, dev, args)
     if args.grad:
         extra["grad"] = bench_grad(S, W, torch, dev, args)
+    if args.grad_long:
+        extra["grad_long"] = bench_grad_long(S, W, torch, dev, args)
     if args.precision:
         extra["precision"] = bench_precision(S, W, torch, dev, args)
 
