@@ -171,74 +171,52 @@ def measured_traffic(N, solver_opt, solvers, n):
 def bench_grad(S, W, torch, dev, args):
     """The adjoint workload: 64 channels x 2^18 float32 samples, K = 8,
     r in [0.5, 0.95], loss sum(y * g) with g ~ N(0, 1) (seed + 2); channel c
-    drawn with seed c.  Per channel one forward (sos_filt) and one backward
-    (sos_filt_backward) on the same stream; the 64 channels run back to back
-    and the whole pass is timed.  A sample of channels is checked against the
-    oracle adjoint."""
+    drawn with seed c.  One step is the batched forward (sos_filt_batched)
+    and the batched adjoint (sos_filt_backward_batched) of all channels.  A
+    sample of channels is checked against the oracle adjoint."""
     cfg = W.CONFIGS["grad"]
     C, n = cfg.channels, cfg.n
-    plans, xs, gs, sos = [], [], [], []
+    sos = [W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed + c) for c in range(C)]
+    plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver="auto", N=64) for s_ in sos]
+    b = S.Batch(plans, [n] * C)
+    xb = torch.empty(b.total, dtype=torch.float32, device=dev)
+    gb = torch.empty_like(xb)
     for c in range(C):
-        s_c = W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed + c)
-        sos.append(s_c)
-        plans.append(S.Plan(s_c, io_dtype="f32", compute_dtype="f64", solver="auto", N=64))
-        xs.append(torch.from_numpy(W.make_signal(n, cfg.seed + c, np.float32)).to(dev))
-        gs.append(torch.from_numpy(W.grad_seed_signal(n, cfg.seed + c, np.float32)).to(dev))
-    ys = [torch.empty_like(xs[0]) for _ in range(C)]
-    gxs = [torch.empty_like(xs[0]) for _ in range(C)]
-    gsos = [torch.empty((cfg.K, 6), dtype=torch.float64, device=dev) for _ in range(C)]
-    wsz = max(S.lib().sos_backward_workspace_size(p.handle, n) for p in plans)
-    import ctypes
-    lib = S.lib()
-    # the channels are independent: spread them over a few streams (the
-    # device runs up to four hardware queues), one workspace per stream
-    nstreams = 4
-    streams = [torch.cuda.Stream() for _ in range(nstreams)]
-    wss = [torch.empty(wsz, dtype=torch.uint8, device=dev) for _ in range(nstreams)]
-    main = torch.cuda.current_stream()
+        xb[c * n:(c + 1) * n] = torch.from_numpy(W.make_signal(n, cfg.seed + c, np.float32)).to(dev)
+        gb[c * n:(c + 1) * n] = torch.from_numpy(W.grad_seed_signal(n, cfg.seed + c, np.float32)).to(dev)
+    yb = torch.empty_like(xb)
+    gx = torch.empty_like(xb)
 
     def one_pass():
-        ev = torch.cuda.Event()
-        ev.record(main)
-        for st in streams:
-            st.wait_event(ev)
-        for c in range(C):
-            st = streams[c % nstreams]
-            S.filt(plans[c], xs[c], ys[c], stream=st)
-            rc = lib.sos_filt_backward(plans[c].handle, ctypes.c_void_p(xs[c].data_ptr()),
-                                       ctypes.c_void_p(gs[c].data_ptr()), ctypes.c_void_p(gxs[c].data_ptr()),
-                                       ctypes.c_void_p(gsos[c].data_ptr()), n,
-                                       ctypes.c_void_p(wss[c % nstreams].data_ptr()),
-                                       ctypes.c_void_p(st.cuda_stream))
-            if rc != 0:
-                raise RuntimeError("sos_filt_backward failed: %d" % rc)
-        for st in streams:
-            done = torch.cuda.Event()
-            done.record(st)
-            main.wait_event(done)
+        S.filt_batched(b, xb, yb)
+        return S.filt_backward_batched(b, xb, gb, gx)
 
-    one_pass()
+    _, gsos, first = one_pass()
     torch.cuda.synchronize()
-    steps = max(3, args.steps // 4)
+    steps = max(3, args.steps // 2)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(main)
+    e0.record()
     for _ in range(steps):
         one_pass()
-    e1.record(main)
+    e1.record()
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) / 1e3 / steps
     total = C * n
     out = {"channels": C, "samples": total, "K": cfg.K, "ms": sec * 1e3, "GSps": total / sec / 1e9}
-    log("grad: %d x %d forward+backward %.3f ms  %.1f GS/s" % (C, n, sec * 1e3, total / sec / 1e9))
+    log("grad: %d x %d batched forward+backward %.3f ms  %.1f GS/s" % (C, n, sec * 1e3, total / sec / 1e9))
     if not args.no_cpu:
         import oracle
+        _, gsos, first = one_pass()
+        torch.cuda.synchronize()
+        g_all = gsos.cpu().numpy()
         worst_x, worst_s = 0.0, 0.0
         for c in (0, C // 2, C - 1):
-            rx, rs = oracle.sosfilt_backward(xs[c].cpu().numpy().astype(np.float64), sos[c],
-                                             gs[c].cpu().numpy().astype(np.float64))
-            worst_x = max(worst_x, oracle.rel_rms(gxs[c].cpu().numpy(), rx))
-            g = gsos[c].cpu().numpy()
+            x64 = xb[c * n:(c + 1) * n].cpu().numpy().astype(np.float64)
+            g64 = gb[c * n:(c + 1) * n].cpu().numpy().astype(np.float64)
+            rx, rs = oracle.sosfilt_backward(x64, sos[c], g64)
+            worst_x = max(worst_x, oracle.rel_rms(gx[c * n:(c + 1) * n].cpu().numpy(), rx))
+            g = g_all[first[c]:first[c] + cfg.K]
             worst_s = max(worst_s, float(np.max(np.abs(g - rs) / np.max(np.abs(rs), axis=1, keepdims=True))))
         out["gx_rel_rms_max"] = worst_x
         out["gsos_row_err_max"] = worst_s

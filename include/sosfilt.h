@@ -294,6 +294,27 @@ sos_status sos_filt_backward(sos_plan_t plan, const void *x, const void *gy, voi
                              double *gsos, int64_t n, void *workspace, sos_stream_t stream);
 
 /*
+ * Batched adjoint: sos_filt_backward for every channel of a device batch in
+ * three launches (the forward pass that saves the section outputs, the
+ * reversed-time adjoint, the reduction of the coefficient sums).
+ *
+ * sos_batch_backward_workspace_size -- device bytes of the workspace (0 if
+ * the batch has no adjoint: host-only batches).
+ * sos_batch_query_adjoint -- rows of gsos (the sum of the channels' K) and,
+ * into first_row (host [C] or NULL), each channel's first row.
+ * sos_filt_backward_batched -- x, gy: device, the batch's concatenated
+ * layout; gx: device, same layout, written at the channels' samples only,
+ * must not overlap x or gy; gsos: device float64 [rows][6], channel c's K
+ * rows from its first row, with respect to its rows (b0 b1 b2 a0 a1 a2);
+ * workspace: device, the size above, 16-byte aligned.  The semantics,
+ * precision and determinism are those of sos_filt_backward.
+ */
+size_t sos_batch_backward_workspace_size(sos_batch_t batch);
+sos_status sos_batch_query_adjoint(sos_batch_t batch, int64_t *gsos_rows, int64_t *first_row);
+sos_status sos_filt_backward_batched(sos_batch_t batch, const void *x, const void *gy, void *gx,
+                                     double *gsos, void *workspace, sos_stream_t stream);
+
+/*
  * sos_batch_tune -- autotuner for batches: times sos_filt_batched for every
  * candidate (N, tile_groups) on the caller's own buffers and reports the
  * fastest.  L is not a candidate: it is fixed by the 16-lane DPP row.

@@ -1,0 +1,32 @@
+// Descriptors of the adjoint kernels (kernels_backward.hpp), shared with the
+// batch structure.
+#pragma once
+
+#include <cstdint>
+
+namespace sosf {
+
+// One channel's adjoint geometry, as the row functions of the adjoint
+// kernels see it.
+struct AdjView {
+  int64_t n, np, tile, warm, ntiles, sstride;
+  int32_t K, stride;
+};
+
+// Batched channels: per channel its sub-plan's tables, its adjoint rows, its
+// signal offset and the offsets of its saved outputs and sums in the
+// workspace.  Work items are four tiles of one channel, as in the forward
+// batch.
+struct AdjChan {
+  const double *tab;        // the channel's adjoint sub-plan table
+  const double *bwd;        // the channel's adjoint rows
+  int64_t off, n, np, tile, warm, ntiles, first_item;
+  int64_t saved_off;        // doubles into the workspace
+  int64_t partial_off;      // doubles into the workspace (ntiles x 5K)
+  int64_t sstride;
+  int32_t K, stride;
+  int32_t aligned;          // the channel's signals start 16-byte aligned
+  int32_t gsos_row;         // first row of the channel in gsos
+};
+
+}  // namespace sosf

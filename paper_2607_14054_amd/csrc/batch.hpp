@@ -1,0 +1,37 @@
+// Internal batch structure shared by the batched forward (sosfilt_batch.hip)
+// and the batched adjoint (sosfilt_backward.hip).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "kernels.hpp"
+#include "adjoint_types.hpp"
+#include "plan.hpp"
+
+struct sos_batch_s {
+  int C = 0, N = 0, io_dtype = SOS_F32, compute_dtype = SOS_F64;
+  int kmax = 0, mix = SOS_PH;
+  bool b0one = true, host_only = false;
+  int device = -1;
+  int64_t total = 0, items = 0;
+  std::vector<int64_t> n, off, tile;
+  std::vector<int32_t> order;             // channels in launch order
+  std::vector<sosf::BatchChan> chans;     // in launch order
+  std::vector<int32_t> item_chan;         // item -> index into chans
+  sosf::BatchChan *d_chans = nullptr;
+  int32_t *d_item_chan = nullptr;
+  // adjoint schedule (device batches whose plans carry the adjoint)
+  bool adj = false, adj_b0one = true;
+  int64_t adj_items = 0, adj_rows = 0;    // wave items; rows of gsos (sum of K)
+  size_t adj_ws = 0;                      // workspace bytes
+  std::vector<int64_t> adj_gsos_row;      // per channel (caller order): first gsos row
+  sosf::AdjChan *d_adj = nullptr;
+  int32_t *d_adj_item = nullptr;          // item -> index into the adjoint channels
+  int32_t *d_adj_red = nullptr;           // gsos row -> index into the adjoint channels
+};
+
+namespace sosf {
+// builds and uploads the adjoint schedule (sosfilt_backward.hip)
+sos_status build_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups);
+}

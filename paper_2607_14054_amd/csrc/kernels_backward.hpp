@@ -18,6 +18,7 @@
 #pragma once
 
 #include "kernels.hpp"
+#include "adjoint_types.hpp"
 
 namespace sosf {
 
@@ -132,90 +133,69 @@ struct BwdArgs {
   int32_t K, stride;
 };
 
-// Forward pass that saves w_k (true scale, FP64) of every section k to
-// saved + k * sstride.  PH, FP64 arithmetic, tiles as in sos_rows_kernel.
+// Forward pass of one row's tile that saves w_k (true scale, FP64) of every
+// section k to saved + k * sstride.  PH, FP64 arithmetic, tiles as in
+// filter_rows.  st: 2 + 2K boundary values; rowbuf: one FP64 group.
 template <int N, typename TI, bool B0ONE>
-__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
-    const TI *__restrict__ x, double *__restrict__ saved, const double *__restrict__ tab,
-    const double *__restrict__ bwd, BwdArgs a) {
+__device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__restrict__ saved,
+                                          ctab<double> ct, ctab<double> cb, const AdjView &v,
+                                          int64_t tile_index, bool aligned, double *st,
+                                          unsigned char *rowbuf) {
   typedef double T;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // the stage holds one group per row in FP64 (the saved outputs), which
-  // also fits the input's group
-  unsigned char *stage = smem;
-  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, double>());
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
-  if (wave * kRows >= a.ntiles) return;
-  const int row = lane_id() >> 4;
-  const int64_t t0 = (wave * kRows + row) * a.tile;
-  T *st = state + (int64_t)(w * kRows + row) * state_elems(a.K);
-  unsigned char *rowbuf = stage + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
   TI *buf = reinterpret_cast<TI *>(rowbuf);
   double *dbuf = reinterpret_cast<double *>(rowbuf);
-  const ctab<T> ct = as_ctab(tab), cb = as_ctab(bwd);
-  for (int i = 0; i < state_elems(a.K); ++i) st[i] = T(0);
+  for (int i = 0; i < state_elems(v.K); ++i) st[i] = T(0);
   const int64_t G = (int64_t)N * kL;
-  const int64_t warm_groups = a.warm / G, steps = warm_groups + a.tile / G;
+  const int64_t t0 = tile_index * v.tile;
+  const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
   T X[N];
   for (int64_t it = 0; it < steps; ++it) {
-    const int64_t g = t0 - a.warm + it * G;
-    const bool full = __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= a.n)) == 0;
+    const int64_t g = t0 - v.warm + it * G;
+    const bool full = aligned && __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= v.n)) == 0;
     const bool live = it >= warm_groups;
-    load_group<N, TI, T>(X, x, g, a.n, full, buf);
+    load_group<N, TI, T>(X, x, g, v.n, full, buf);
     T xs2 = st[0], xs1 = st[1];
     st[0] = last_of_row(X[N - 2]);
     st[1] = last_of_row(X[N - 1]);
-    for (int k = 0; k < a.K; ++k) {
-      ph_section<N, T, B0ONE>(X, ct + (int64_t)k * a.stride, xs2, xs1, st + 2 + 2 * k);
-      if (live) store_group<N, double, T>(X, saved + (int64_t)k * a.sstride, g, a.n, full,
+    for (int k = 0; k < v.K; ++k) {
+      ph_section<N, T, B0ONE>(X, ct + (int64_t)k * v.stride, xs2, xs1, st + 2 + 2 * k);
+      if (live) store_group<N, double, T>(X, saved + (int64_t)k * v.sstride, g, v.n, full,
                                           cb[kBwdRow * k + BW_SCALE], dbuf);
     }
   }
 }
 
-// Reversed-time adjoint.  Row r of wavefront w takes reversed-time tile
-// t = 4w + r: run-in, then per group lambda = r(gy), and for k = K-1 .. 0
-// mu = (1/A_k) lambda, the five sums of section k, lambda = B_k mu; the
-// group's final lambda is r(dL/dx).  Per row, the sums of the tile's groups
-// go to partials[t][k][0..4]: sum mu[t] u[t], mu[t-1] u[t], mu[t-2] u[t],
-// mu[t-1] w[t], mu[t-2] w[t] (reversed time, t over the tile).
+// Reversed-time adjoint of one row's tile: run-in, then per group
+// lambda = r(gy), and for k = K-1 .. 0 mu = (1/A_k) lambda, the five sums of
+// section k, lambda = B_k mu; the group's final lambda is r(dL/dx).  The
+// tile's sums go to sums[k][0..4]: sum mu[t] u[t], mu[t-1] u[t],
+// mu[t-2] u[t], mu[t-1] w[t], mu[t-2] w[t] (reversed time, t over the tile).
+// st: 7K values (2K all-pole output states, then 5K running sums).
 template <int N, typename TI>
-__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
-    const TI *__restrict__ gy, TI *__restrict__ gx, const TI *__restrict__ x,
-    const double *__restrict__ saved, const double *__restrict__ tab, const double *__restrict__ bwd,
-    double *__restrict__ partials, BwdArgs a) {
+__device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__restrict__ gx,
+                                             const TI *__restrict__ x, const double *__restrict__ saved,
+                                             ctab<double> ct, ctab<double> cb, double *__restrict__ sums,
+                                             const AdjView &v, int64_t tile_index, bool aligned,
+                                             double *st, unsigned char *rowbuf) {
   typedef double T;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  unsigned char *stage = smem;   // one FP64 group per row
-  // per row: the 2K output states of the all-pole stages, then 5K sums
-  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, double>());
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
-  if (wave * kRows >= a.ntiles) return;
-  const int row = lane_id() >> 4;
-  const int64_t tile_index = wave * kRows + row;
-  const int64_t t0 = tile_index * a.tile;
-  T *st = state + (int64_t)(w * kRows + row) * (7 * a.K);
-  T *acc = st + 2 * a.K;
-  unsigned char *rowbuf = stage + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
   TI *buf = reinterpret_cast<TI *>(rowbuf);
   double *dbuf = reinterpret_cast<double *>(rowbuf);
-  const ctab<T> ct = as_ctab(tab), cb = as_ctab(bwd);
-  for (int i = 0; i < 7 * a.K; ++i) st[i] = T(0);
+  T *acc = st + 2 * v.K;
+  for (int i = 0; i < 7 * v.K; ++i) st[i] = T(0);
   const int64_t G = (int64_t)N * kL;
-  const int64_t pad = a.np - a.n;
-  const int64_t warm_groups = a.warm / G, steps = warm_groups + a.tile / G;
+  const int64_t t0 = tile_index * v.tile;
+  const int64_t pad = v.np - v.n;
+  const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
   T X[N], U[N], Wk[N];
   for (int64_t it = 0; it < steps; ++it) {
-    const int64_t g = t0 - a.warm + it * G;
-    const bool full = __builtin_amdgcn_ballot_w64(!(g >= pad && g + G <= a.np)) == 0;
+    const int64_t g = t0 - v.warm + it * G;
+    const bool full = aligned && __builtin_amdgcn_ballot_w64(!(g >= pad && g + G <= v.np)) == 0;
     const bool live = it >= warm_groups;   // uniform per wave
-    load_group_rev<N, TI, T>(X, gy, g, a.n, a.np, full, buf);
+    load_group_rev<N, TI, T>(X, gy, g, v.n, v.np, full, buf);
     if (live)
-      load_group_rev<N, double, T>(Wk, saved + (int64_t)(a.K - 1) * a.sstride, g, a.n, a.np, full, dbuf);
-    for (int k = a.K - 1; k >= 0; --k) {
-      const ctab<T> c = ct + (int64_t)k * a.stride;
+      load_group_rev<N, double, T>(Wk, saved + (int64_t)(v.K - 1) * v.sstride, g, v.n, v.np, full, dbuf);
+    for (int k = v.K - 1; k >= 0; --k) {
+      const ctab<T> c = ct + (int64_t)k * v.stride;
       const ctab<T> b = cb + kBwdRow * k;
       T *ys = st + 2 * k;
       const T old2 = ys[0], old1 = ys[1];
@@ -224,9 +204,9 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
       const T b0 = b[BW_B0], b1 = b[BW_B1], b2 = b[BW_B2];
       if (live) {
         if (k == 0)
-          load_group_rev<N, TI, T>(U, x, g, a.n, a.np, full, buf);
+          load_group_rev<N, TI, T>(U, x, g, v.n, v.np, full, buf);
         else
-          load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * a.sstride, g, a.n, a.np, full, dbuf);
+          load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * v.sstride, g, v.n, v.np, full, dbuf);
         T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0), s4 = T(0);
 #pragma unroll
         for (int m = N - 1; m >= 0; --m) {
@@ -261,25 +241,124 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
         }
       }
     }
-    if (live) store_group_rev<N, TI, T>(X, gx, g, a.n, a.np, full, buf);
+    if (live) store_group_rev<N, TI, T>(X, gx, g, v.n, v.np, full, buf);
   }
-  // one lane per row writes the row's sums (rows past the last tile, in the
-  // last wavefront, have none)
-  if (row_lane() == 0 && tile_index < a.ntiles)
-    for (int i = 0; i < 5 * a.K; ++i) partials[tile_index * 5 * a.K + i] = acc[i];
+  // one lane per row writes the row's sums (rows past the last tile have none)
+  if (row_lane() == 0 && tile_index < v.ntiles)
+    for (int i = 0; i < 5 * v.K; ++i) sums[i] = acc[i];
 }
 
-// dL/d(sos) from the per-tile sums: block k sums partials[t][k][j] over the
-// tiles in a fixed order (deterministic), then applies the chain rule
-// through the division by a0: with normalised c = (b0, b1, b2, a1, a2)/a0,
-// dL/db_j = gb_j / a0, dL/da_j = ga_j / a0 (j = 1, 2) and
-// dL/da0 = -(gb . (b0, b1, b2) + ga . (a1, a2)) / a0.
-__global__ __launch_bounds__(256) void sos_adjoint_reduce_kernel(const double *__restrict__ partials,
-                                                                 int64_t ntiles, int32_t K,
-                                                                 const double *__restrict__ bwd,
-                                                                 double *__restrict__ gsos) {
+__device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
+  AdjView v;
+  v.n = a.n;
+  v.np = a.np;
+  v.tile = a.tile;
+  v.warm = a.warm;
+  v.ntiles = a.ntiles;
+  v.sstride = a.sstride;
+  v.K = a.K;
+  v.stride = a.stride;
+  return v;
+}
+
+// Single signal: row r of wavefront w takes tile 4w + r.
+template <int N, typename TI, bool B0ONE>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
+    const TI *__restrict__ x, double *__restrict__ saved, const double *__restrict__ tab,
+    const double *__restrict__ bwd, BwdArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  // the stage holds one group per row in FP64 (the saved outputs), which
+  // also fits the input's group
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (wave * kRows >= a.ntiles) return;
+  const int row = lane_id() >> 4;
+  double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
+               (int64_t)(w * kRows + row) * state_elems(a.K);
+  unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  save_rows<N, TI, B0ONE>(x, saved, as_ctab(tab), as_ctab(bwd), adj_view(a), wave * kRows + row, true,
+                          st, rowbuf);
+}
+
+template <int N, typename TI>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
+    const TI *__restrict__ gy, TI *__restrict__ gx, const TI *__restrict__ x,
+    const double *__restrict__ saved, const double *__restrict__ tab, const double *__restrict__ bwd,
+    double *__restrict__ partials, BwdArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (wave * kRows >= a.ntiles) return;
+  const int row = lane_id() >> 4;
+  const int64_t tile_index = wave * kRows + row;
+  double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
+               (int64_t)(w * kRows + row) * (7 * a.K);
+  unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  adjoint_rows<N, TI>(gy, gx, x, saved, as_ctab(tab), as_ctab(bwd), partials + tile_index * 5 * a.K,
+                      adj_view(a), tile_index, true, st, rowbuf);
+}
+
+__device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
+  AdjView v;
+  v.n = c.n;
+  v.np = c.np;
+  v.tile = c.tile;
+  v.warm = c.warm;
+  v.ntiles = c.ntiles;
+  v.sstride = c.sstride;
+  v.K = c.K;
+  v.stride = c.stride;
+  return v;
+}
+
+template <int N, typename TI, bool B0ONE>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_batched_kernel(
+    const TI *__restrict__ x, double *__restrict__ ws, const AdjChan *__restrict__ chans,
+    const int32_t *__restrict__ item_chan, int64_t items, int32_t kmax) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (item >= items) return;
+  const AdjChan &c = chans[item_chan[item]];
+  const int row = lane_id() >> 4;
+  const int64_t tile_index = (item - c.first_item) * kRows + row;
+  double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
+               (int64_t)(w * kRows + row) * state_elems(kmax);
+  unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  save_rows<N, TI, B0ONE>(x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd), adj_view(c),
+                          tile_index, c.aligned != 0, st, rowbuf);
+}
+
+template <int N, typename TI>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_batched_kernel(
+    const TI *__restrict__ gy, TI *__restrict__ gx, const TI *__restrict__ x, double *__restrict__ ws,
+    const AdjChan *__restrict__ chans, const int32_t *__restrict__ item_chan, int64_t items,
+    int32_t kmax) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (item >= items) return;
+  const AdjChan &c = chans[item_chan[item]];
+  const int row = lane_id() >> 4;
+  const int64_t tile_index = (item - c.first_item) * kRows + row;
+  double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
+               (int64_t)(w * kRows + row) * (7 * kmax);
+  unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  adjoint_rows<N, TI>(gy + c.off, gx + c.off, x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd),
+                      ws + c.partial_off + tile_index * 5 * c.K, adj_view(c), tile_index, c.aligned != 0, st,
+                      rowbuf);
+}
+
+// dL/d(sos) from the per-tile sums of one section: the block sums
+// sums[t][k][j] over the tiles in a fixed order (deterministic), then
+// applies the chain rule through the division by a0: with normalised
+// c = (b0, b1, b2, a1, a2)/a0, dL/db_j = gb_j / a0, dL/da_j = ga_j / a0
+// (j = 1, 2) and dL/da0 = -(gb . (b0, b1, b2) + ga . (a1, a2)) / a0.
+__device__ __forceinline__ void adjoint_reduce(const double *__restrict__ partials, int64_t ntiles, int32_t K,
+                                               int k, const double *__restrict__ bwd,
+                                               double *__restrict__ g) {
   __shared__ double red[5][256];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   double s[5] = {0, 0, 0, 0, 0};
   for (int64_t t = tid; t < ntiles; t += 256)
     for (int j = 0; j < 5; ++j) s[j] += partials[(t * K + k) * 5 + j];
@@ -295,7 +374,6 @@ __global__ __launch_bounds__(256) void sos_adjoint_reduce_kernel(const double *_
     const double a0 = b[BW_A0];
     const double gb0 = red[0][0], gb1 = red[1][0], gb2 = red[2][0];
     const double ga1 = -red[3][0], ga2 = -red[4][0];
-    double *g = gsos + 6 * k;
     g[0] = gb0 / a0;
     g[1] = gb1 / a0;
     g[2] = gb2 / a0;
@@ -303,6 +381,24 @@ __global__ __launch_bounds__(256) void sos_adjoint_reduce_kernel(const double *_
     g[4] = ga1 / a0;
     g[5] = ga2 / a0;
   }
+}
+
+// block k: section k of the single signal
+__global__ __launch_bounds__(256) void sos_adjoint_reduce_kernel(const double *__restrict__ partials,
+                                                                 int64_t ntiles, int32_t K,
+                                                                 const double *__restrict__ bwd,
+                                                                 double *__restrict__ gsos) {
+  adjoint_reduce(partials, ntiles, K, blockIdx.x, bwd, gsos + 6 * blockIdx.x);
+}
+
+// block b: row b of the batch's gsos, i.e. section b - gsos_row of channel
+// red_chan[b]
+__global__ __launch_bounds__(256) void sos_adjoint_reduce_batched_kernel(
+    double *__restrict__ ws, const AdjChan *__restrict__ chans, const int32_t *__restrict__ red_chan,
+    double *__restrict__ gsos) {
+  const AdjChan &c = chans[red_chan[blockIdx.x]];
+  const int k = (int)blockIdx.x - c.gsos_row;
+  adjoint_reduce(ws + c.partial_off, c.ntiles, c.K, k, c.bwd, gsos + 6 * (int64_t)blockIdx.x);
 }
 
 }  // namespace sosf

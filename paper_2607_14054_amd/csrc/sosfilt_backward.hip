@@ -8,6 +8,7 @@
 #include "dispatch.hpp"
 #include "kernels_backward.hpp"
 #include "plan.hpp"
+#include "batch.hpp"
 
 using namespace sosf;
 
@@ -113,9 +114,171 @@ sos_status launch_adjoint(const sos_plan_s &p, const void *x, const void *gy, vo
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }
 
+template <typename TI>
+const void *adjoint_batched_kernel_ptr() {
+  return reinterpret_cast<const void *>(&sos_rows_adjoint_batched_kernel<kBwdN, TI>);
+}
+
+size_t adj_lds_save(int kmax) { return (size_t)lds_bytes<kBwdN, double, double>(kmax); }
+size_t adj_lds_adjoint(int kmax) {
+  return (size_t)stage_bytes<kBwdN, double>() + (size_t)kWavesPerBlock * kRows * 7 * kmax * sizeof(double);
+}
+
+template <typename TI>
+sos_status launch_adjoint_batched(const sos_batch_s &b, const void *x, const void *gy, void *gx, double *gsos,
+                                  void *ws, hipStream_t s) {
+  constexpr int N = kBwdN;
+  double *w = static_cast<double *>(ws);
+  if (b.adj_items > 0) {
+    const unsigned blocks = (unsigned)((b.adj_items + kWavesPerBlock - 1) / kWavesPerBlock);
+    const unsigned lds_f = (unsigned)adj_lds_save(b.kmax), lds_a = (unsigned)adj_lds_adjoint(b.kmax);
+    if (b.adj_b0one)
+      hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, true>), dim3(blocks), dim3(kWavesPerBlock * 64),
+                         lds_f, s, static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items,
+                         (int32_t)b.kmax);
+    else
+      hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, false>), dim3(blocks), dim3(kWavesPerBlock * 64),
+                         lds_f, s, static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items,
+                         (int32_t)b.kmax);
+    if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
+    hipLaunchKernelGGL((sos_rows_adjoint_batched_kernel<N, TI>), dim3(blocks), dim3(kWavesPerBlock * 64), lds_a,
+                       s, static_cast<const TI *>(gy), static_cast<TI *>(gx), static_cast<const TI *>(x), w,
+                       b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+    if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
+  }
+  hipLaunchKernelGGL(sos_adjoint_reduce_batched_kernel, dim3((unsigned)b.adj_rows), dim3(256), 0, s, w, b.d_adj,
+                     b.d_adj_red, gsos);
+  return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+}
+
 }  // namespace
 
+namespace sosf {
+
+// The batched adjoint's schedule: per channel its adjoint sub-plan, tiles in
+// groups of the sub-plan (reversed time, n rounded up to the vector width),
+// and its regions of the workspace (saved outputs, per-tile sums) and of
+// gsos.  Channels go in the forward batch's launch order.
+sos_status build_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups) {
+  b.adj = false;
+  for (int c = 0; c < b.C; ++c)
+    if (!plans[c]->bwd || !plans[c]->d_bwd_rows) return SOS_OK;   // no adjoint for this batch
+  const int64_t G = (int64_t)kBwdN * kL;
+  const int64_t V = b.io_dtype == SOS_F64 ? 2 : 4;
+  std::vector<int64_t> np(b.C);
+  int64_t total_groups = 0;
+  b.adj_b0one = true;
+  for (int c = 0; c < b.C; ++c) {
+    np[c] = (b.n[c] + V - 1) / V * V;
+    total_groups += (np[c] + G - 1) / G;
+    b.adj_b0one = b.adj_b0one && plans[c]->bwd->b0_factored;
+  }
+  const Residency r = residency_of(b.io_dtype == SOS_F64 ? adjoint_batched_kernel_ptr<double>()
+                                                         : adjoint_batched_kernel_ptr<float>(),
+                                   adj_lds_adjoint(b.kmax), kWavesPerBlock * 64);
+  const int64_t resident_rows = (int64_t)4 * r.simds * r.waves_per_simd;
+  b.adj_gsos_row.assign(b.C, 0);
+  int64_t rows = 0;
+  for (int c = 0; c < b.C; ++c) {
+    b.adj_gsos_row[c] = rows;
+    rows += plans[c]->K;
+  }
+  b.adj_rows = rows;
+  std::vector<AdjChan> chans(b.C);
+  std::vector<int32_t> item_chan, red(rows, 0);
+  int64_t ws = 0, items = 0;
+  const size_t esz = b.io_dtype == SOS_F64 ? 8 : 4;
+  for (int i = 0; i < b.C; ++i) {
+    const int32_t c = b.order[i];
+    const sos_plan_s *sub = plans[c]->bwd;
+    AdjChan &a = chans[i];
+    const int64_t groups = (np[c] + G - 1) / G;
+    int64_t tg = tile_groups > 0 ? tile_groups : std::max<int64_t>(16 * (sub->warm / G), 8);
+    if (tile_groups <= 0) {
+      const int64_t tg_par = std::max<int64_t>(total_groups / std::max<int64_t>(resident_rows, 1), 1);
+      if (tg_par < tg) tg = std::max<int64_t>(tg_par, std::max<int64_t>(4 * (sub->warm / G), 4));
+    }
+    const int64_t quads = groups ? (groups + 4 * tg - 1) / (4 * tg) : 0;
+    const int64_t tgc = quads ? (groups + 4 * quads - 1) / (4 * quads) : 1;
+    a.tab = static_cast<const double *>(sub->d_table);
+    a.bwd = static_cast<const double *>(plans[c]->d_bwd_rows);
+    a.off = b.off[c];
+    a.n = b.n[c];
+    a.np = np[c];
+    a.tile = tgc * G;
+    a.warm = sub->warm;
+    a.ntiles = groups ? (np[c] + a.tile - 1) / a.tile : 0;
+    a.first_item = items;
+    a.sstride = (b.n[c] + 63) / 64 * 64;
+    a.saved_off = ws;
+    ws += (int64_t)plans[c]->K * a.sstride;
+    a.partial_off = ws;
+    ws += (a.ntiles * 5 * plans[c]->K + 31) / 32 * 32;
+    a.K = plans[c]->K;
+    a.stride = sub->stride;
+    a.aligned = ((b.off[c] * (int64_t)esz) % 16) == 0;
+    a.gsos_row = (int32_t)b.adj_gsos_row[c];
+    for (int64_t q = 0; q < quads; ++q) item_chan.push_back(i);
+    items += quads;
+    for (int k = 0; k < plans[c]->K; ++k) red[b.adj_gsos_row[c] + k] = i;
+  }
+  b.adj_items = items;
+  b.adj_ws = (size_t)std::max<int64_t>(ws, 32) * sizeof(double);
+  if (hipGetDevice(&b.device) != hipSuccess) return SOS_E_DEVICE;
+  if (hipMalloc(&b.d_adj, chans.size() * sizeof(AdjChan)) != hipSuccess) {
+    b.d_adj = nullptr;
+    return SOS_E_NOMEM;
+  }
+  if (hipMalloc(&b.d_adj_item, std::max<size_t>(item_chan.size(), 1) * sizeof(int32_t)) != hipSuccess) {
+    b.d_adj_item = nullptr;
+    return SOS_E_NOMEM;
+  }
+  if (hipMalloc(&b.d_adj_red, std::max<size_t>(red.size(), 1) * sizeof(int32_t)) != hipSuccess) {
+    b.d_adj_red = nullptr;
+    return SOS_E_NOMEM;
+  }
+  if (hipMemcpy(b.d_adj, chans.data(), chans.size() * sizeof(AdjChan), hipMemcpyHostToDevice) != hipSuccess ||
+      (item_chan.size() &&
+       hipMemcpy(b.d_adj_item, item_chan.data(), item_chan.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+           hipSuccess) ||
+      (red.size() && hipMemcpy(b.d_adj_red, red.data(), red.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
+                         hipSuccess))
+    return SOS_E_DEVICE;
+  b.adj = true;
+  return SOS_OK;
+}
+
+}  // namespace sosf
+
 extern "C" {
+
+size_t sos_batch_backward_workspace_size(sos_batch_t b) { return (b && b->adj) ? b->adj_ws : 0; }
+
+sos_status sos_batch_query_adjoint(sos_batch_t b, int64_t *gsos_rows, int64_t *first_row) {
+  if (!b || !b->adj) return SOS_E_ARG;
+  if (gsos_rows) *gsos_rows = b->adj_rows;
+  if (first_row)
+    for (int c = 0; c < b->C; ++c) first_row[c] = b->adj_gsos_row[c];
+  return SOS_OK;
+}
+
+sos_status sos_filt_backward_batched(sos_batch_t b, const void *x, const void *gy, void *gx, double *gsos,
+                                     void *workspace, sos_stream_t stream) {
+  if (!b || !b->adj || !gsos || !workspace) return SOS_E_ARG;
+  if (b->adj_items > 0) {
+    if (!x || !gy || !gx) return SOS_E_ARG;
+    const size_t esz = b->io_dtype == SOS_F64 ? 8 : 4;
+    const uintptr_t xb = (uintptr_t)x, gyb = (uintptr_t)gy, gxb = (uintptr_t)gx;
+    const uintptr_t bytes = (uintptr_t)b->total * esz;
+    if ((xb | gyb | gxb | (uintptr_t)workspace) & 15) return SOS_E_ARG;
+    if ((gxb < xb + bytes && xb < gxb + bytes) || (gxb < gyb + bytes && gyb < gxb + bytes)) return SOS_E_ARG;
+  }
+  if ((uintptr_t)gsos & 7) return SOS_E_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (b->io_dtype == SOS_F32) return launch_adjoint_batched<float>(*b, x, gy, gx, gsos, workspace, s);
+  return launch_adjoint_batched<double>(*b, x, gy, gx, gsos, workspace, s);
+}
+
 
 size_t sos_backward_workspace_size(sos_plan_t p, int64_t n) {
   if (!p || n < 0 || !p->bwd) return 0;

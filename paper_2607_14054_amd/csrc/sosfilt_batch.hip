@@ -12,22 +12,9 @@
 #include "dispatch.hpp"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "batch.hpp"
 
 using namespace sosf;
-
-struct sos_batch_s {
-  int C = 0, N = 0, io_dtype = SOS_F32, compute_dtype = SOS_F64;
-  int kmax = 0, mix = SOS_PH;
-  bool b0one = true, host_only = false;
-  int device = -1;
-  int64_t total = 0, items = 0;
-  std::vector<int64_t> n, off, tile;
-  std::vector<int32_t> order;        // channels in launch order
-  std::vector<BatchChan> chans;      // in launch order
-  std::vector<int32_t> item_chan;    // item -> index into chans
-  BatchChan *d_chans = nullptr;
-  int32_t *d_item_chan = nullptr;
-};
 
 namespace {
 
@@ -65,15 +52,21 @@ struct ResidencyBatched {
 };
 
 void free_device(sos_batch_s *b) {
-  if (!b->d_chans && !b->d_item_chan) return;
+  void **ptrs[] = {reinterpret_cast<void **>(&b->d_chans), reinterpret_cast<void **>(&b->d_item_chan),
+                   reinterpret_cast<void **>(&b->d_adj), reinterpret_cast<void **>(&b->d_adj_item),
+                   reinterpret_cast<void **>(&b->d_adj_red)};
+  bool any = false;
+  for (void **q : ptrs) any = any || *q;
+  if (!any) return;
   int cur = -1;
   hipGetDevice(&cur);
   if (b->device >= 0 && cur != b->device) hipSetDevice(b->device);
-  if (b->d_chans) hipFree(b->d_chans);
-  if (b->d_item_chan) hipFree(b->d_item_chan);
+  for (void **q : ptrs)
+    if (*q) {
+      hipFree(*q);
+      *q = nullptr;
+    }
   if (b->device >= 0 && cur >= 0 && cur != b->device) hipSetDevice(cur);
-  b->d_chans = nullptr;
-  b->d_item_chan = nullptr;
 }
 
 }  // namespace
@@ -191,6 +184,14 @@ sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
     ch.pad = 0;
     for (int64_t q = 0; q < quads[c]; ++q) b->item_chan.push_back(i);
     b->items += quads[c];
+  }
+  if (!host_only) {
+    const sos_status sa = build_batch_adjoint(*b, plans, o.tile_groups);
+    if (sa != SOS_OK) {
+      free_device(b);
+      delete b;
+      return sa;
+    }
   }
   if (!host_only && b->items > 0) {
     if (hipGetDevice(&b->device) != hipSuccess) {

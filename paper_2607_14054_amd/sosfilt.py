@@ -27,7 +27,8 @@ SOS_FLAG_HOST_ONLY = 0x1
 EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_plan_tile",
             "sos_workspace_size", "sos_filt", "sos_batch_plan", "sos_batch_destroy",
             "sos_batch_query", "sos_filt_batched", "sos_batch_tune", "sos_backward_workspace_size",
-            "sos_filt_backward", "sos_status_string"]
+            "sos_filt_backward", "sos_batch_backward_workspace_size", "sos_batch_query_adjoint",
+            "sos_filt_backward_batched", "sos_status_string"]
 
 _DTYPES = {"f32": SOS_F32, "f64": SOS_F64, "f16": SOS_F16, "bf16": SOS_BF16,
            np.float32: SOS_F32, np.float64: SOS_F64}
@@ -99,9 +100,14 @@ def lib():
         L.sos_backward_workspace_size.argtypes = [vp, i64]
         L.sos_backward_workspace_size.restype = ctypes.c_size_t
         L.sos_filt_backward.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.sos_batch_backward_workspace_size.argtypes = [vp]
+        L.sos_batch_backward_workspace_size.restype = ctypes.c_size_t
+        L.sos_batch_query_adjoint.argtypes = [vp, p64, p64]
+        L.sos_filt_backward_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt",
                   "sos_batch_plan", "sos_batch_destroy", "sos_batch_query", "sos_filt_batched",
-                  "sos_batch_tune", "sos_filt_backward"):
+                  "sos_batch_tune", "sos_filt_backward", "sos_batch_query_adjoint",
+                  "sos_filt_backward_batched"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -344,3 +350,30 @@ def filt_backward(plan: Plan, x, gy, gx=None, stream=None):
                                    ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gsos.data_ptr()), n,
                                    ctypes.c_void_p(wsb.data_ptr()), _stream_ptr(stream)), "sos_filt_backward")
     return gx, gsos
+
+
+def filt_backward_batched(batch: Batch, x, gy, gx=None, stream=None):
+    """(gx, gsos, first_row) for every channel of a device batch: x, gy in
+    the batch's concatenated layout; gsos is a [rows, 6] float64 device
+    tensor whose rows first_row[c] .. first_row[c] + K_c - 1 belong to
+    channel c."""
+    import torch
+    want = torch.float32 if batch.io_dtype == "f32" else torch.float64
+    for name, t in (("x", x), ("gy", gy)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.dim() == 1
+                and t.is_contiguous() and t.numel() >= batch.total):
+            raise ValueError("%s must be a contiguous 1-D device tensor of dtype %s with %d samples"
+                             % (name, want, batch.total))
+    if gx is None:
+        gx = torch.zeros_like(x)
+    rows = ctypes.c_int64()
+    first = np.zeros(batch.C, np.int64)
+    _check(lib().sos_batch_query_adjoint(batch.handle, ctypes.byref(rows), _i64p(first)), "sos_batch_query_adjoint")
+    gsos = torch.empty((max(rows.value, 1), 6), dtype=torch.float64, device=x.device)
+    ws = int(lib().sos_batch_backward_workspace_size(batch.handle))
+    wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=x.device)
+    _check(lib().sos_filt_backward_batched(batch.handle, ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(gx.data_ptr()),
+                                           ctypes.c_void_p(gsos.data_ptr()), ctypes.c_void_p(wsb.data_ptr()),
+                                           _stream_ptr(stream)), "sos_filt_backward_batched")
+    return gx, gsos[:rows.value], first
