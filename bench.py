@@ -224,6 +224,51 @@ def bench_grad(S, W, torch, dev, args):
     return out
 
 
+def bench_stream(S, W, torch, dev, args):
+    """A ragged stream of requests: each request filters 1-64 channels of
+    lengths log-uniform in [2^10, 2^18], each channel with one of 64 cached
+    cascades (K ~ U{1..16}, r in [0.5, 0.95]).  Per request: the batch
+    schedule (host, plus its small upload), one batched launch, and a
+    synchronisation, as a serving loop would do.  Reports requests/s,
+    samples/s and the median and 99th-percentile request latency."""
+    rng = np.random.default_rng(9)
+    pool = [S.Plan(W.make_sos(int(rng.integers(1, 17)), 0.5, 0.95, 500 + i), io_dtype="f32",
+                   compute_dtype="f64", N=16) for i in range(64)]
+    reqs = []
+    for _ in range(200):
+        C = int(rng.integers(1, 65))
+        lengths = np.floor(2.0 ** rng.uniform(10, 18, size=C)).astype(np.int64)
+        chans = rng.integers(0, 64, size=C)
+        reqs.append((lengths, chans))
+    cap = int(max(r[0].sum() for r in reqs))
+    xb = torch.from_numpy(W.make_signal(cap, 7, np.float32)).to(dev)
+    yb = torch.empty_like(xb)
+    torch.cuda.synchronize()
+
+    def serve(lengths, chans):
+        b = S.Batch([pool[c] for c in chans], lengths)
+        S.filt_batched(b, xb, yb)
+        torch.cuda.synchronize()
+
+    for r in reqs[:10]:
+        serve(*r)
+    lat = []
+    t_all = time.time()
+    for r in reqs:
+        t = time.time()
+        serve(*r)
+        lat.append(time.time() - t)
+    wall = time.time() - t_all
+    samples = int(sum(r[0].sum() for r in reqs))
+    lat = np.array(lat)
+    out = {"requests": len(reqs), "samples": samples, "req_per_s": len(reqs) / wall,
+           "GSps": samples / wall / 1e9, "latency_ms_median": float(np.median(lat) * 1e3),
+           "latency_ms_p99": float(np.percentile(lat, 99) * 1e3)}
+    log("stream: %d requests, %.0f req/s, %.2f GS/s, latency median %.3f ms p99 %.3f ms"
+        % (len(reqs), out["req_per_s"], out["GSps"], out["latency_ms_median"], out["latency_ms_p99"]))
+    return out
+
+
 def bench_grad_long(S, W, torch, dev, args):
     """The adjoint on one long channel: 2^26 float32 samples, K = 8,
     r in [0.5, 0.95]; one sos_filt_backward per step."""
@@ -321,6 +366,8 @@ def main():
                     help="also time the batched ragged workload (4096 channels), autotuned, graph-replayed")
     ap.add_argument("--grad", action="store_true",
                     help="also time the adjoint workload (64 channels x 2^18, forward + backward)")
+    ap.add_argument("--stream", action="store_true",
+                    help="also time a ragged stream of 1-64-channel requests")
     ap.add_argument("--grad-long", action="store_true",
                     help="also time the adjoint on one long channel (2^26 samples)")
     ap.add_argument("--precision", action="store_true",
@@ -406,7 +453,7 @@ def main():
                 % (solver, NN, cd, p2.tile(n), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
         extra["sweep"] = rows
 
-    if args.batch or args.grad or args.precision or args.grad_long:
+    if args.batch or args.grad or args.precision or args.grad_long or args.stream:
         del x, y
         torch.cuda.empty_cache()
     if args.batch:
@@ -415,6 +462,8 @@ def main():
         extra["grad"] = bench_grad(S, W, torch, dev, args)
     if args.grad_long:
         extra["grad_long"] = bench_grad_long(S, W, torch, dev, args)
+    if args.stream:
+        extra["stream"] = bench_stream(S, W, torch, dev, args)
     if args.precision:
         extra["precision"] = bench_precision(S, W, torch, dev, args)
 
