@@ -228,8 +228,9 @@ def bench_stream(S, W, torch, dev, args):
     """A ragged stream of requests: each request filters 1-64 channels of
     lengths log-uniform in [2^10, 2^18], each channel with one of 64 cached
     cascades (K ~ U{1..16}, r in [0.5, 0.95]).  Per request: the batch
-    schedule (host, plus its small upload), one batched launch, and a
-    synchronisation, as a serving loop would do.  Reports requests/s,
+    schedule, one batched launch and a synchronisation, as a serving loop
+    would do, either with a new batch per request or by replanning one
+    reserved batch (no allocation, asynchronous upload).  Reports requests/s,
     samples/s and the median and 99th-percentile request latency."""
     rng = np.random.default_rng(9)
     pool = [S.Plan(W.make_sos(int(rng.integers(1, 17)), 0.5, 0.95, 500 + i), io_dtype="f32",
@@ -243,29 +244,38 @@ def bench_stream(S, W, torch, dev, args):
     cap = int(max(r[0].sum() for r in reqs))
     xb = torch.from_numpy(W.make_signal(cap, 7, np.float32)).to(dev)
     yb = torch.empty_like(xb)
+    stream = torch.cuda.Stream()
     torch.cuda.synchronize()
+    reuse = S.Batch([pool[0]], [1], max_channels=64, max_samples=cap)
 
-    def serve(lengths, chans):
+    def serve_new(lengths, chans):
         b = S.Batch([pool[c] for c in chans], lengths)
-        S.filt_batched(b, xb, yb)
-        torch.cuda.synchronize()
+        S.filt_batched(b, xb, yb, stream=stream)
+        stream.synchronize()
 
-    for r in reqs[:10]:
-        serve(*r)
-    lat = []
-    t_all = time.time()
-    for r in reqs:
-        t = time.time()
-        serve(*r)
-        lat.append(time.time() - t)
-    wall = time.time() - t_all
-    samples = int(sum(r[0].sum() for r in reqs))
-    lat = np.array(lat)
-    out = {"requests": len(reqs), "samples": samples, "req_per_s": len(reqs) / wall,
-           "GSps": samples / wall / 1e9, "latency_ms_median": float(np.median(lat) * 1e3),
-           "latency_ms_p99": float(np.percentile(lat, 99) * 1e3)}
-    log("stream: %d requests, %.0f req/s, %.2f GS/s, latency median %.3f ms p99 %.3f ms"
-        % (len(reqs), out["req_per_s"], out["GSps"], out["latency_ms_median"], out["latency_ms_p99"]))
+    def serve_replan(lengths, chans):
+        reuse.replan([pool[c] for c in chans], lengths, stream=stream)
+        S.filt_batched(reuse, xb, yb, stream=stream)
+        stream.synchronize()
+
+    out = {"requests": len(reqs), "samples": int(sum(r[0].sum() for r in reqs))}
+    for name, serve in (("new_batch", serve_new), ("replan", serve_replan)):
+        for r in reqs[:10]:
+            serve(*r)
+        lat = []
+        t_all = time.time()
+        for r in reqs:
+            t = time.time()
+            serve(*r)
+            lat.append(time.time() - t)
+        wall = time.time() - t_all
+        lat = np.array(lat)
+        row = {"req_per_s": len(reqs) / wall, "GSps": out["samples"] / wall / 1e9,
+               "latency_ms_median": float(np.median(lat) * 1e3),
+               "latency_ms_p99": float(np.percentile(lat, 99) * 1e3)}
+        out[name] = row
+        log("stream (%s): %d requests, %.0f req/s, %.2f GS/s, latency median %.3f ms p99 %.3f ms"
+            % (name, len(reqs), row["req_per_s"], row["GSps"], row["latency_ms_median"], row["latency_ms_p99"]))
     return out
 
 

@@ -213,7 +213,9 @@ sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
  * opts     host, may be NULL: tile_groups > 0 caps the groups per tile
  *          (0 = chosen from the total length); flags SOS_FLAG_HOST_ONLY
  *          builds the schedule without device memory (queries only, and
- *          host-only plans are then accepted).
+ *          host-only plans are then accepted); max_channels and
+ *          max_samples reserve room for later sos_batch_replan calls of up
+ *          to that many channels and samples in all (0 = this set's size).
  * out      host, receives the batch handle (unchanged on error).
  */
 typedef struct sos_batch_s *sos_batch_t;   /* opaque, owned by the caller */
@@ -221,6 +223,9 @@ typedef struct sos_batch_s *sos_batch_t;   /* opaque, owned by the caller */
 typedef struct {
     int32_t tile_groups;
     uint32_t flags;
+    int32_t max_channels;
+    int32_t reserved;      /* 0 */
+    int64_t max_samples;
 } sos_batch_opts;
 
 sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
@@ -228,6 +233,21 @@ sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
 
 /* Release the batch and its device schedule.  NULL is accepted. */
 sos_status sos_batch_destroy(sos_batch_t batch);
+
+/*
+ * sos_batch_replan -- give an existing batch a new channel set (a serving
+ * loop's next request) without allocating: the schedule is rebuilt on the
+ * host and copied, asynchronously on `stream`, into the batch's device
+ * descriptors through its pinned staging buffer.  Arguments as for
+ * sos_batch_plan; the plans must share the batch's N, io_dtype and
+ * compute_dtype (SOS_E_UNSUPPORTED).  SOS_E_NOMEM if the new schedule does
+ * not fit the room reserved at creation; on any error the batch keeps its
+ * previous channel set.  Later launches with the batch must be on `stream`
+ * (or ordered after it).  The call waits only for the previous replan's
+ * copy, so it never waits for a kernel.
+ */
+sos_status sos_batch_replan(sos_batch_t batch, const sos_plan_t *plans, int32_t C, const int64_t *n,
+                            const int64_t *offsets, sos_stream_t stream);
 
 /*
  * sos_batch_query -- the schedule, for inspection and tests.  Every output

@@ -12,6 +12,7 @@
 struct sos_batch_s {
   int C = 0, N = 0, io_dtype = SOS_F32, compute_dtype = SOS_F64;
   int kmax = 0, mix = SOS_PH;
+  int32_t tile_groups = 0;
   bool b0one = true, host_only = false;
   int device = -1;
   int64_t total = 0, items = 0;
@@ -26,12 +27,23 @@ struct sos_batch_s {
   int64_t adj_items = 0, adj_rows = 0;    // wave items; rows of gsos (sum of K)
   size_t adj_ws = 0;                      // workspace bytes
   std::vector<int64_t> adj_gsos_row;      // per channel (caller order): first gsos row
+  std::vector<sosf::AdjChan> adj_chans;   // in launch order
+  std::vector<int32_t> adj_item_chan;     // item -> index into adj_chans
+  std::vector<int32_t> adj_red;           // gsos row -> index into adj_chans
   sosf::AdjChan *d_adj = nullptr;
-  int32_t *d_adj_item = nullptr;          // item -> index into the adjoint channels
-  int32_t *d_adj_red = nullptr;           // gsos row -> index into the adjoint channels
+  int32_t *d_adj_item = nullptr;
+  int32_t *d_adj_red = nullptr;
+  // every device descriptor lives in one allocation (and its pinned host
+  // staging copy, for sos_batch_replan)
+  unsigned char *d_blob = nullptr, *h_blob = nullptr;
+  size_t blob_cap = 0;
+  hipEvent_t copied = nullptr;            // the last staging upload has been read
 };
 
+// the descriptor pointers lie inside the device buffer (sosfilt_batch.hip)
+bool batch_descriptors_valid(const sos_batch_s &b);
+
 namespace sosf {
-// builds and uploads the adjoint schedule (sosfilt_backward.hip)
-sos_status build_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups);
+// the adjoint schedule, host side (sosfilt_backward.hip)
+sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups);
 }

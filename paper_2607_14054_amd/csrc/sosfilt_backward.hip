@@ -155,11 +155,12 @@ sos_status launch_adjoint_batched(const sos_batch_s &b, const void *x, const voi
 
 namespace sosf {
 
-// The batched adjoint's schedule: per channel its adjoint sub-plan, tiles in
-// groups of the sub-plan (reversed time, n rounded up to the vector width),
-// and its regions of the workspace (saved outputs, per-tile sums) and of
-// gsos.  Channels go in the forward batch's launch order.
-sos_status build_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups) {
+// The batched adjoint's schedule (host side): per channel its adjoint
+// sub-plan, tiles in groups of the sub-plan (reversed time, n rounded up to
+// the vector width), and its regions of the workspace (saved outputs,
+// per-tile sums) and of gsos.  Channels go in the forward batch's launch
+// order.
+sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups) {
   b.adj = false;
   for (int c = 0; c < b.C; ++c)
     if (!plans[c]->bwd || !plans[c]->d_bwd_rows) return SOS_OK;   // no adjoint for this batch
@@ -224,26 +225,9 @@ sos_status build_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t 
   }
   b.adj_items = items;
   b.adj_ws = (size_t)std::max<int64_t>(ws, 32) * sizeof(double);
-  if (hipGetDevice(&b.device) != hipSuccess) return SOS_E_DEVICE;
-  if (hipMalloc(&b.d_adj, chans.size() * sizeof(AdjChan)) != hipSuccess) {
-    b.d_adj = nullptr;
-    return SOS_E_NOMEM;
-  }
-  if (hipMalloc(&b.d_adj_item, std::max<size_t>(item_chan.size(), 1) * sizeof(int32_t)) != hipSuccess) {
-    b.d_adj_item = nullptr;
-    return SOS_E_NOMEM;
-  }
-  if (hipMalloc(&b.d_adj_red, std::max<size_t>(red.size(), 1) * sizeof(int32_t)) != hipSuccess) {
-    b.d_adj_red = nullptr;
-    return SOS_E_NOMEM;
-  }
-  if (hipMemcpy(b.d_adj, chans.data(), chans.size() * sizeof(AdjChan), hipMemcpyHostToDevice) != hipSuccess ||
-      (item_chan.size() &&
-       hipMemcpy(b.d_adj_item, item_chan.data(), item_chan.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-           hipSuccess) ||
-      (red.size() && hipMemcpy(b.d_adj_red, red.data(), red.size() * sizeof(int32_t), hipMemcpyHostToDevice) !=
-                         hipSuccess))
-    return SOS_E_DEVICE;
+  b.adj_chans = std::move(chans);
+  b.adj_item_chan = std::move(item_chan);
+  b.adj_red = std::move(red);
   b.adj = true;
   return SOS_OK;
 }
@@ -265,6 +249,7 @@ sos_status sos_batch_query_adjoint(sos_batch_t b, int64_t *gsos_rows, int64_t *f
 sos_status sos_filt_backward_batched(sos_batch_t b, const void *x, const void *gy, void *gx, double *gsos,
                                      void *workspace, sos_stream_t stream) {
   if (!b || !b->adj || !gsos || !workspace) return SOS_E_ARG;
+  if (!batch_descriptors_valid(*b)) return SOS_E_ARG;
   if (b->adj_items > 0) {
     if (!x || !gy || !gx) return SOS_E_ARG;
     const size_t esz = b->io_dtype == SOS_F64 ? 8 : 4;

@@ -52,34 +52,21 @@ struct ResidencyBatched {
 };
 
 void free_device(sos_batch_s *b) {
-  void **ptrs[] = {reinterpret_cast<void **>(&b->d_chans), reinterpret_cast<void **>(&b->d_item_chan),
-                   reinterpret_cast<void **>(&b->d_adj), reinterpret_cast<void **>(&b->d_adj_item),
-                   reinterpret_cast<void **>(&b->d_adj_red)};
-  bool any = false;
-  for (void **q : ptrs) any = any || *q;
-  if (!any) return;
+  if (!b->d_blob && !b->h_blob && !b->copied) return;
   int cur = -1;
   hipGetDevice(&cur);
   if (b->device >= 0 && cur != b->device) hipSetDevice(b->device);
-  for (void **q : ptrs)
-    if (*q) {
-      hipFree(*q);
-      *q = nullptr;
-    }
+  if (b->copied) hipEventSynchronize(b->copied);
+  if (b->d_blob) hipFree(b->d_blob);
+  if (b->h_blob) hipHostFree(b->h_blob);
+  if (b->copied) hipEventDestroy(b->copied);
   if (b->device >= 0 && cur >= 0 && cur != b->device) hipSetDevice(cur);
+  b->d_blob = b->h_blob = nullptr;
+  b->copied = nullptr;
 }
 
-}  // namespace
-
-extern "C" {
-
-sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
-                          const int64_t *offsets, const sos_batch_opts *opts, sos_batch_t *out) {
-  if (!plans || !n || !out || C < 1) return SOS_E_ARG;
-  sos_batch_opts o{0, 0};
-  if (opts) o = *opts;
-  if (o.tile_groups < 0) return SOS_E_ARG;
-  const bool host_only = (o.flags & SOS_FLAG_HOST_ONLY) != 0;
+sos_status validate(const sos_plan_t *plans, int32_t C, const int64_t *n, bool host_only) {
+  if (!plans || !n || C < 1) return SOS_E_ARG;
   for (int c = 0; c < C; ++c) {
     const sos_plan_s *p = plans[c];
     if (!p || n[c] < 0) return SOS_E_ARG;
@@ -90,15 +77,24 @@ sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
         p->compute_dtype != plans[0]->compute_dtype)
       return SOS_E_UNSUPPORTED;
   }
-  sos_batch_s *b = new (std::nothrow) sos_batch_s;
-  if (!b) return SOS_E_NOMEM;
-  b->C = C;
-  b->N = plans[0]->N;
-  b->io_dtype = plans[0]->io_dtype;
-  b->compute_dtype = plans[0]->compute_dtype;
-  b->host_only = host_only;
-  b->n.assign(n, n + C);
-  b->off.resize(C);
+  return SOS_OK;
+}
+
+// The host schedule of a channel set: offsets, per-channel tiles and work
+// items (costliest first), and for device batches the adjoint's schedule.
+sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const int64_t *n,
+                    const int64_t *offsets, int32_t tile_groups) {
+  b.C = C;
+  b.N = plans[0]->N;
+  b.io_dtype = plans[0]->io_dtype;
+  b.compute_dtype = plans[0]->compute_dtype;
+  b.n.assign(n, n + C);
+  b.off.assign(C, 0);
+  b.total = 0;
+  b.items = 0;
+  b.kmax = 0;
+  b.b0one = true;
+  b.item_chan.clear();
   // offsets: given (channels must not overlap), or dense packing
   if (offsets) {
     std::vector<int32_t> by_off(C);
@@ -108,112 +104,245 @@ sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
     int64_t end = 0;
     for (int i = 0; i < C; ++i) {
       const int32_t c = by_off[i];
-      if (offsets[c] < 0 || (n[c] > 0 && offsets[c] < end)) {
-        delete b;
-        return SOS_E_ARG;
-      }
+      if (offsets[c] < 0 || (n[c] > 0 && offsets[c] < end)) return SOS_E_ARG;
       if (n[c] > 0) end = offsets[c] + n[c];
     }
-    for (int c = 0; c < C; ++c) b->off[c] = offsets[c];
+    for (int c = 0; c < C; ++c) b.off[c] = offsets[c];
   } else {
     int64_t acc = 0;
     for (int c = 0; c < C; ++c) {
-      b->off[c] = acc;
+      b.off[c] = acc;
       acc += n[c];
     }
   }
-  const size_t esz = b->io_dtype == SOS_F64 ? 8 : 4;
-  const int64_t G = (int64_t)b->N * kL;
+  const size_t esz = b.io_dtype == SOS_F64 ? 8 : 4;
+  const int64_t G = (int64_t)b.N * kL;
   int64_t total_groups = 0;
   for (int c = 0; c < C; ++c) {
     total_groups += (n[c] + G - 1) / G;
-    b->total = std::max(b->total, b->off[c] + n[c]);
+    b.total = std::max(b.total, b.off[c] + n[c]);
   }
-  b->mix = plans[0]->solver[0];
+  b.mix = plans[0]->solver[0];
   for (int c = 0; c < C; ++c) {
     const sos_plan_s *p = plans[c];
-    b->kmax = std::max(b->kmax, p->K);
-    b->b0one = b->b0one && p->b0_factored;
+    b.kmax = std::max(b.kmax, p->K);
+    b.b0one = b.b0one && p->b0_factored;
     for (int k = 0; k < p->K; ++k)
-      if (p->solver[k] != b->mix) b->mix = SOS_AUTO;
+      if (p->solver[k] != b.mix) b.mix = SOS_AUTO;
   }
   Residency res;
-  if (!host_only)
-    dispatch_rows<ResidencyBatched>(b->N, b->io_dtype, b->compute_dtype, b->b0one, b->mix, b->kmax, &res);
+  if (!b.host_only)
+    dispatch_rows<ResidencyBatched>(b.N, b.io_dtype, b.compute_dtype, b.b0one, b.mix, b.kmax, &res);
   const int64_t resident_rows = (int64_t)4 * res.simds * res.waves_per_simd;
   // per-channel tiles: quads of four row tiles, as even as the length allows
-  b->tile.assign(C, 0);
+  b.tile.assign(C, 0);
   std::vector<int64_t> quads(C, 0);
   std::vector<double> cost(C, 0.0);
   for (int c = 0; c < C; ++c) {
     const sos_plan_s *p = plans[c];
     const int64_t groups = (n[c] + G - 1) / G;
-    const int64_t tg = batch_tile_groups(p->warm / G, total_groups, resident_rows, o.tile_groups);
+    const int64_t tg = batch_tile_groups(p->warm / G, total_groups, resident_rows, tile_groups);
     if (groups == 0) {
-      b->tile[c] = G;
+      b.tile[c] = G;
       continue;
     }
     quads[c] = (groups + 4 * tg - 1) / (4 * tg);
     const int64_t tgc = (groups + 4 * quads[c] - 1) / (4 * quads[c]);
-    b->tile[c] = tgc * G;
+    b.tile[c] = tgc * G;
     const int64_t warm = std::min<int64_t>(p->warm, (groups - 1) / tgc * tgc * G);
-    cost[c] = (double)p->K * (double)(warm + b->tile[c]);
+    cost[c] = (double)p->K * (double)(warm + b.tile[c]);
   }
   // launch order: costliest items first (the dispatcher then fills the
   // tail of the launch with the cheap ones)
-  b->order.resize(C);
-  std::iota(b->order.begin(), b->order.end(), 0);
-  std::stable_sort(b->order.begin(), b->order.end(),
-                   [&](int32_t a, int32_t c) { return cost[a] > cost[c]; });
-  b->chans.resize(C);
+  b.order.resize(C);
+  std::iota(b.order.begin(), b.order.end(), 0);
+  std::stable_sort(b.order.begin(), b.order.end(), [&](int32_t a, int32_t c) { return cost[a] > cost[c]; });
+  b.chans.assign(C, BatchChan{});
   for (int i = 0; i < C; ++i) {
-    const int32_t c = b->order[i];
+    const int32_t c = b.order[i];
     const sos_plan_s *p = plans[c];
-    BatchChan &ch = b->chans[i];
+    BatchChan &ch = b.chans[i];
     ch.tab = p->d_table;
     ch.solver = static_cast<const int32_t *>(p->d_solver);
-    ch.off = b->off[c];
+    ch.off = b.off[c];
     ch.n = n[c];
-    ch.tile = b->tile[c];
+    ch.tile = b.tile[c];
     ch.warm = p->warm;
-    ch.first_item = b->items;
+    ch.first_item = b.items;
     ch.K = p->K;
     ch.stride = p->stride;
     ch.gain = p->gain;
-    ch.aligned = ((b->off[c] * (int64_t)esz) % 16) == 0;
+    ch.aligned = ((b.off[c] * (int64_t)esz) % 16) == 0;
     ch.pad = 0;
-    for (int64_t q = 0; q < quads[c]; ++q) b->item_chan.push_back(i);
-    b->items += quads[c];
+    for (int64_t q = 0; q < quads[c]; ++q) b.item_chan.push_back(i);
+    b.items += quads[c];
+  }
+  b.adj = false;
+  if (!b.host_only) return schedule_batch_adjoint(b, plans, tile_groups);
+  return SOS_OK;
+}
+
+// The device descriptors of a schedule, packed into one blob: forward
+// channels, forward items, adjoint channels, adjoint items, gsos rows.
+struct BlobLayout {
+  size_t chans, items, adj, adj_items, red, bytes;
+};
+
+size_t up16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+BlobLayout blob_layout(size_t C, size_t items, size_t adj_items, size_t rows) {
+  BlobLayout l;
+  l.chans = 0;
+  l.items = up16(l.chans + C * sizeof(BatchChan));
+  l.adj = up16(l.items + items * sizeof(int32_t));
+  l.adj_items = up16(l.adj + C * sizeof(AdjChan));
+  l.red = up16(l.adj_items + adj_items * sizeof(int32_t));
+  l.bytes = up16(l.red + rows * sizeof(int32_t));
+  return l;
+}
+
+BlobLayout blob_layout(const sos_batch_s &b) {
+  return blob_layout(b.C, b.item_chan.size(), b.adj ? b.adj_item_chan.size() : 0, b.adj ? b.adj_red.size() : 0);
+}
+
+void pack(const sos_batch_s &b, const BlobLayout &l, unsigned char *dst) {
+  std::memcpy(dst + l.chans, b.chans.data(), b.chans.size() * sizeof(BatchChan));
+  std::memcpy(dst + l.items, b.item_chan.data(), b.item_chan.size() * sizeof(int32_t));
+  if (b.adj) {
+    std::memcpy(dst + l.adj, b.adj_chans.data(), b.adj_chans.size() * sizeof(AdjChan));
+    std::memcpy(dst + l.adj_items, b.adj_item_chan.data(), b.adj_item_chan.size() * sizeof(int32_t));
+    std::memcpy(dst + l.red, b.adj_red.data(), b.adj_red.size() * sizeof(int32_t));
+  }
+}
+
+void point(sos_batch_s &b, const BlobLayout &l) {
+  if (!b.d_blob) {
+    b.d_chans = nullptr;
+    b.d_item_chan = nullptr;
+    b.d_adj = nullptr;
+    b.d_adj_item = nullptr;
+    b.d_adj_red = nullptr;
+    return;
+  }
+  b.d_chans = reinterpret_cast<BatchChan *>(b.d_blob + l.chans);
+  b.d_item_chan = reinterpret_cast<int32_t *>(b.d_blob + l.items);
+  b.d_adj = reinterpret_cast<AdjChan *>(b.d_blob + l.adj);
+  b.d_adj_item = reinterpret_cast<int32_t *>(b.d_blob + l.adj_items);
+  b.d_adj_red = reinterpret_cast<int32_t *>(b.d_blob + l.red);
+}
+
+// Capacity for channel sets of up to C channels and `samples` samples in
+// all: tiles of at least one group give at most total / (4 G) + 2 C items.
+size_t capacity_bytes(const sos_batch_s &b, int64_t C, int64_t samples) {
+  const int64_t G = (int64_t)b.N * kL, Gb = (int64_t)kBwdN * kL;
+  const int64_t items = samples / (4 * G) + 2 * C + 1, adj_items = (samples + 3 * C) / (4 * Gb) + 2 * C + 1;
+  return blob_layout((size_t)C, (size_t)items, (size_t)adj_items, (size_t)C * SOS_MAX_SECTIONS).bytes;
+}
+
+}  // namespace
+
+// The descriptor pointers of a device batch lie inside its buffer (a launch
+// with any other value would read outside it).
+bool batch_descriptors_valid(const sos_batch_s &b) {
+  if (!b.d_blob) return false;
+  auto inside = [&](const void *p) {
+    const unsigned char *q = static_cast<const unsigned char *>(p);
+    return q >= b.d_blob && q < b.d_blob + b.blob_cap;
+  };
+  return inside(b.d_chans) && inside(b.d_item_chan) && inside(b.d_adj) && inside(b.d_adj_item) &&
+         inside(b.d_adj_red);
+}
+
+extern "C" {
+
+sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
+                          const int64_t *offsets, const sos_batch_opts *opts, sos_batch_t *out) {
+  if (!out) return SOS_E_ARG;
+  sos_batch_opts o{0, 0, 0, 0, 0};
+  if (opts) o = *opts;
+  if (o.tile_groups < 0 || o.max_channels < 0 || o.max_samples < 0) return SOS_E_ARG;
+  const bool host_only = (o.flags & SOS_FLAG_HOST_ONLY) != 0;
+  sos_status st = validate(plans, C, n, host_only);
+  if (st != SOS_OK) return st;
+  sos_batch_s *b = new (std::nothrow) sos_batch_s;
+  if (!b) return SOS_E_NOMEM;
+  b->host_only = host_only;
+  b->tile_groups = o.tile_groups;
+  st = schedule(*b, plans, C, n, offsets, o.tile_groups);
+  if (st != SOS_OK) {
+    delete b;
+    return st;
   }
   if (!host_only) {
-    const sos_status sa = build_batch_adjoint(*b, plans, o.tile_groups);
-    if (sa != SOS_OK) {
-      free_device(b);
-      delete b;
-      return sa;
-    }
-  }
-  if (!host_only && b->items > 0) {
+    const BlobLayout l = blob_layout(*b);
+    b->blob_cap = std::max(l.bytes, capacity_bytes(*b, std::max<int64_t>(o.max_channels, C),
+                                                    std::max<int64_t>(o.max_samples, b->total)));
     if (hipGetDevice(&b->device) != hipSuccess) {
       delete b;
       return SOS_E_DEVICE;
     }
-    if (hipMalloc(&b->d_chans, (size_t)C * sizeof(BatchChan)) != hipSuccess ||
-        hipMalloc(&b->d_item_chan, (size_t)b->items * sizeof(int32_t)) != hipSuccess) {
+    if (hipMalloc(&b->d_blob, b->blob_cap) != hipSuccess) {
+      b->d_blob = nullptr;
+      delete b;
+      return SOS_E_NOMEM;
+    }
+    if (hipHostMalloc(&b->h_blob, b->blob_cap, hipHostMallocDefault) != hipSuccess) {
+      b->h_blob = nullptr;
       free_device(b);
       delete b;
       return SOS_E_NOMEM;
     }
-    if (hipMemcpy(b->d_chans, b->chans.data(), (size_t)C * sizeof(BatchChan), hipMemcpyHostToDevice) !=
-            hipSuccess ||
-        hipMemcpy(b->d_item_chan, b->item_chan.data(), (size_t)b->items * sizeof(int32_t),
-                  hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipEventCreateWithFlags(&b->copied, hipEventDisableTiming) != hipSuccess) {
+      b->copied = nullptr;
       free_device(b);
       delete b;
       return SOS_E_DEVICE;
     }
+    pack(*b, l, b->h_blob);
+    if (hipMemcpy(b->d_blob, b->h_blob, l.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+      free_device(b);
+      delete b;
+      return SOS_E_DEVICE;
+    }
+    point(*b, l);
   }
   *out = b;
+  return SOS_OK;
+}
+
+sos_status sos_batch_replan(sos_batch_t b, const sos_plan_t *plans, int32_t C, const int64_t *n,
+                            const int64_t *offsets, sos_stream_t stream) {
+  if (!b) return SOS_E_ARG;
+  sos_status st = validate(plans, C, n, b->host_only);
+  if (st != SOS_OK) return st;
+  if (plans[0]->N != b->N || plans[0]->io_dtype != b->io_dtype || plans[0]->compute_dtype != b->compute_dtype)
+    return SOS_E_UNSUPPORTED;
+  // schedule into a copy, so that an invalid request leaves the batch as it was
+  sos_batch_s t;
+  t.host_only = b->host_only;
+  t.tile_groups = b->tile_groups;
+  st = schedule(t, plans, C, n, offsets, b->tile_groups);
+  if (st != SOS_OK) return st;
+  // t keeps the device resources of b (the descriptor pointers of t are
+  // then derived from b's buffer below; a host-only batch has none)
+  t.device = b->device;
+  t.d_blob = b->d_blob;
+  t.h_blob = b->h_blob;
+  t.blob_cap = b->blob_cap;
+  t.copied = b->copied;
+  if (!b->host_only) {
+    const BlobLayout l = blob_layout(t);
+    if (l.bytes > b->blob_cap) return SOS_E_NOMEM;
+    // the staging copy is free once the previous upload has been read
+    if (hipEventSynchronize(b->copied) != hipSuccess) return SOS_E_DEVICE;
+    pack(t, l, b->h_blob);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(b->d_blob, b->h_blob, l.bytes, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipEventRecord(b->copied, s) != hipSuccess)
+      return SOS_E_DEVICE;
+    point(t, l);
+  }
+  *b = std::move(t);
   return SOS_OK;
 }
 
@@ -241,7 +370,7 @@ sos_status sos_filt_batched(sos_batch_t b, const void *x, void *y, void *workspa
                             sos_stream_t stream) {
   (void)workspace;
   if (!b) return SOS_E_ARG;
-  if (b->host_only) return SOS_E_ARG;
+  if (b->host_only || !batch_descriptors_valid(*b)) return SOS_E_ARG;
   if (b->items == 0) return SOS_OK;
   if (!x || !y) return SOS_E_ARG;
   const size_t esz = b->io_dtype == SOS_F64 ? 8 : 4;

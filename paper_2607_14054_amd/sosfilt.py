@@ -26,7 +26,7 @@ SOS_FLAG_HOST_ONLY = 0x1
 
 EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_plan_tile",
             "sos_workspace_size", "sos_filt", "sos_batch_plan", "sos_batch_destroy",
-            "sos_batch_query", "sos_filt_batched", "sos_batch_tune", "sos_backward_workspace_size",
+            "sos_batch_query", "sos_batch_replan", "sos_filt_batched", "sos_batch_tune", "sos_backward_workspace_size",
             "sos_filt_backward", "sos_batch_backward_workspace_size", "sos_batch_query_adjoint",
             "sos_filt_backward_batched", "sos_status_string"]
 
@@ -58,7 +58,9 @@ class _Info(ctypes.Structure):
 
 
 class _BatchOpts(ctypes.Structure):
-    _fields_ = [("tile_groups", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+    _fields_ = [("tile_groups", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("max_channels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_samples", ctypes.c_int64)]
 
 
 class _TuneResult(ctypes.Structure):
@@ -91,6 +93,7 @@ def lib():
         L.sos_batch_plan.argtypes = [ctypes.POINTER(vp), i32, p64, p64, ctypes.POINTER(_BatchOpts),
                                      ctypes.POINTER(vp)]
         L.sos_batch_destroy.argtypes = [vp]
+        L.sos_batch_replan.argtypes = [vp, ctypes.POINTER(vp), i32, p64, p64, vp]
         L.sos_batch_query.argtypes = [vp, p64, p64, p64, p64, ctypes.POINTER(ctypes.c_int32)]
         L.sos_filt_batched.argtypes = [vp, vp, vp, vp, vp]
         pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -105,7 +108,8 @@ def lib():
         L.sos_batch_query_adjoint.argtypes = [vp, p64, p64]
         L.sos_filt_backward_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt",
-                  "sos_batch_plan", "sos_batch_destroy", "sos_batch_query", "sos_filt_batched",
+                  "sos_batch_plan", "sos_batch_destroy", "sos_batch_query", "sos_batch_replan",
+                  "sos_filt_batched",
                   "sos_batch_tune", "sos_filt_backward", "sos_batch_query_adjoint",
                   "sos_filt_backward_batched"):
             getattr(L, f).restype = ctypes.c_int
@@ -153,6 +157,8 @@ class Plan:
                               ctypes.byref(o), ctypes.byref(h)), "sos_plan")
         self._h = h
         self.K = s.shape[0]
+        self.host_only = bool(host_only)
+        self._sos = s
         self.io_dtype = io_dtype if isinstance(io_dtype, str) else ("f32" if io_dtype == np.float32 else "f64")
 
     @property
@@ -231,9 +237,23 @@ class Batch:
     """Owns a sos_batch_t: channel c (length lengths[c]) filtered with
     plans[c], at offsets[c] of the concatenated buffers (None: dense)."""
 
-    def __init__(self, plans, lengths, offsets=None, tile_groups=0, host_only=False):
-        self.plans = list(plans)        # the batch refers to their device tables
-        C = len(self.plans)
+    def __init__(self, plans, lengths, offsets=None, tile_groups=0, host_only=False,
+                 max_channels=0, max_samples=0):
+        plans, n, off = self._args(plans, lengths, offsets)
+        C = len(plans)
+        hs = (ctypes.c_void_p * C)(*[p.handle.value for p in plans])
+        o = _BatchOpts(int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0, int(max_channels), 0,
+                       int(max_samples))
+        h = ctypes.c_void_p()
+        _check(lib().sos_batch_plan(hs, C, _i64p(n), _i64p(off) if off is not None else None,
+                                    ctypes.byref(o), ctypes.byref(h)), "sos_batch_plan")
+        self._h = h
+        self._adopt(plans, n)
+
+    @staticmethod
+    def _args(plans, lengths, offsets):
+        plans = list(plans)
+        C = len(plans)
         n = np.ascontiguousarray(np.asarray(lengths, dtype=np.int64))
         if n.shape != (C,):
             raise ValueError("one length per plan")
@@ -242,18 +262,30 @@ class Batch:
             off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
             if off.shape != (C,):
                 raise ValueError("one offset per plan")
-        hs = (ctypes.c_void_p * C)(*[p.handle.value for p in self.plans])
-        o = _BatchOpts(int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0)
-        h = ctypes.c_void_p()
-        _check(lib().sos_batch_plan(hs, C, _i64p(n), _i64p(off) if off is not None else None,
-                                    ctypes.byref(o), ctypes.byref(h)), "sos_batch_plan")
-        self._h = h
-        self.C = C
+        return plans, n, off
+
+    def _adopt(self, plans, n):
+        self.plans = plans              # the batch refers to their device tables
+        self.C = len(plans)
         self.lengths = n
-        self.io_dtype = self.plans[0].io_dtype
+        self.io_dtype = plans[0].io_dtype
         q = self.query()
         self.total = q["total"]
         self.offsets = q["offsets"]
+
+    def replan(self, plans, lengths, offsets=None, stream=None):
+        """sos_batch_replan: a new channel set in this batch's room; later
+        launches must run on `stream` (default: the current stream)."""
+        plans, n, off = self._args(plans, lengths, offsets)
+        C = len(plans)
+        hs = (ctypes.c_void_p * C)(*[p.handle.value for p in plans])
+        sp = _stream_ptr(stream) if not self._host_only() else None
+        _check(lib().sos_batch_replan(self._h, hs, C, _i64p(n), _i64p(off) if off is not None else None, sp),
+               "sos_batch_replan")
+        self._adopt(plans, n)
+
+    def _host_only(self):
+        return any(getattr(p, "host_only", False) for p in self.plans)
 
     @property
     def handle(self):

@@ -184,3 +184,40 @@ def test_batched_config_full_size_sampled():
         ref = oracle.sosfilt(x, W.make_sos(int(Ks[c]), cfg.r_lo, cfg.r_hi, cfg.seed + c))
         err = oracle.rel_rms(yb[o:o + n].cpu().numpy(), ref)
         assert err < 1e-6, (c, n, int(Ks[c]), err)
+
+
+def test_replan_serves_requests_without_reallocating():
+    """One batch with room for 64 channels and 2^20 samples serves a stream
+    of requests through sos_batch_replan on one stream; every request is
+    checked against the oracle, and a request beyond the room is refused
+    without disturbing the batch."""
+    rng = np.random.default_rng(700)
+    pool = [S.Plan(W.make_sos(int(rng.integers(1, 17)), 0.5, 0.95, 800 + i), io_dtype="f32",
+                   compute_dtype="f64", N=16) for i in range(16)]
+    first = [pool[0], pool[1]]
+    b = S.Batch(first, [1000, 2000], max_channels=64, max_samples=2 ** 20)
+    stream = torch.cuda.Stream()
+    xb = torch.from_numpy(W.make_signal(2 ** 20, 701, np.float32)).to(DEV)
+    yb = torch.zeros_like(xb)
+    for req in range(5):
+        C = int(rng.integers(1, 65))
+        lengths = np.floor(2.0 ** rng.uniform(6, 14, size=C)).astype(np.int64)
+        chans = rng.integers(0, 16, size=C)
+        with torch.cuda.stream(stream):
+            b.replan([pool[c] for c in chans], lengths, stream=stream)
+            S.filt_batched(b, xb, yb, stream=stream)
+        stream.synchronize()
+        x = xb.cpu().numpy()
+        y = yb.cpu().numpy()
+        for i, c in enumerate(chans):
+            o, n = int(b.offsets[i]), int(lengths[i])
+            ref = oracle.sosfilt(x[o:o + n], pool[c]._sos)
+            assert oracle.rel_rms(y[o:o + n], ref) < 1e-6, (req, i)
+    # the room is in bytes of descriptors: 300 channels do not fit the room
+    # reserved for 64
+    prev_C, prev_total = b.C, b.total
+    with pytest.raises(S.SosError) as e:
+        b.replan([pool[0]] * 300, [10] * 300, stream=stream)
+    assert e.value.code == S.SOS_E_NOMEM
+    q = b.query()
+    assert q["total"] == prev_total and len(q["offsets"]) == prev_C

@@ -338,3 +338,20 @@ def test_batch_rejections():
     b = S.Batch(_host_plans([2]), [10], host_only=True)
     assert S.lib().sos_filt_batched(b.handle, None, None, None, None) == S.SOS_E_ARG
     assert S.lib().sos_batch_plan(None, 1, None, None, None, None) == S.SOS_E_ARG
+
+
+def test_batch_replan_host_only():
+    b = S.Batch(_host_plans([2, 3, 4]), [100, 2000, 50], host_only=True)
+    assert b.query()["total"] == 2150
+    b.replan(_host_plans([5, 1, 8, 2, 16]), [10, 0, 70000, 3, 12345])
+    q = b.query()
+    assert b.C == 5 and q["total"] == 10 + 70000 + 3 + 12345
+    assert sorted(q["order"].tolist()) == list(range(5))
+    # an invalid request leaves the batch as it was
+    with pytest.raises(S.SosError) as e:
+        b.replan(_host_plans([2], N=16) + _host_plans([2], N=32), [10, 10])
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    with pytest.raises(S.SosError) as e:
+        b.replan(_host_plans([2, 2]), [10, 10], offsets=[0, 5])
+    assert e.value.code == S.SOS_E_ARG
+    assert b.query()["total"] == q["total"]
