@@ -203,3 +203,48 @@ def test_single_signal_graph_replays_match_eager():
         eager = S.filt(p, fresh)
         torch.cuda.synchronize()
         assert torch.equal(got, eager), rep
+
+
+@pytest.mark.parametrize("solver,io", [("ph", "f64"), ("cr", "f64"), ("cr", "f32")])
+def test_sixty_four_sections_at_lds_limit(solver, io):
+    """K = 64 (the plan limit) at N = 64: with FP64 I/O the staging buffers
+    and boundary values fill about 152 KB of the 160 KB LDS."""
+    sos = W.make_sos(64, 0.5, 0.9, 95)
+    dt = np.float64 if io == "f64" else np.float32
+    x = W.make_signal(3 * 2 ** 16 + 5, 96, dt)
+    if io == "f32":
+        # this cascade attenuates white input to RMS ~2e-48, below the FP32
+        # range; scale the input (exactly, by a power of two) into it
+        x = x * dt(2.0 ** 100)
+    y, p = run(sos, x, compute_dtype="f64", solver=solver, N=64)
+    assert p.info().K == 64
+    ld = oracle.sosfilt_ld(x.astype(np.float64), sos)
+    err, own = oracle.rel_rms(y, ld), oracle.rel_rms(oracle.sosfilt(x, sos), ld)
+    print("K=64 %s %s rel_rms=%.2e (oracle %.2e)" % (solver, io, err, own))
+    assert err <= max(1e-12 if io == "f64" else 1e-6, 4 * own)
+
+
+@pytest.mark.slow
+def test_signal_longer_than_2_pow_31():
+    """2^31 + 2^20 + 3 float32 samples (64-bit indexing everywhere).  The
+    outputs in windows around 2^31 depend, to the run-in bound, only on the
+    preceding W samples, so the oracle runs on a suffix that starts far
+    enough before each window."""
+    n = 2 ** 31 + 2 ** 20 + 3
+    sos = W.make_sos(8, 0.8, 0.98, 97)
+    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=64)
+    W_run = p.info().warm_samples
+    g = torch.Generator(device=dev())
+    g.manual_seed(98)
+    x = torch.randn(n, dtype=torch.float32, device=dev(), generator=g)
+    y = S.filt(p, x)
+    torch.cuda.synchronize()
+    for start in (2 ** 31 - 5000, 2 ** 31 + 123, n - 4000):
+        lo = start - 4 * W_run
+        hi = min(start + 3000, n)
+        xs = x[lo:hi].cpu().numpy()
+        ref = oracle.sosfilt(xs, sos)[start - lo:]
+        got = y[start:hi].cpu().numpy()
+        err = oracle.rel_rms(got, ref)
+        print("window at %d: rel_rms %.2e" % (start, err))
+        assert err < 1e-6, start
