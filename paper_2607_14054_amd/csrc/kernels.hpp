@@ -11,8 +11,8 @@
 // group is loaded, one de-permutation when it is stored.
 //
 // The four rows of a wavefront work on four different tiles of the signal,
-// so nothing couples them; groups inside a tile are chained through each
-// section's boundary values (x[-2], x[-1], y[-2], y[-1]), kept per row in LDS.
+// so nothing couples them; groups inside a tile are chained through the
+// sections' boundary values (Section V), kept per row in LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>

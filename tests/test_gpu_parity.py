@@ -80,9 +80,13 @@ def test_f32_arithmetic_near_fp32_floor(solver):
 def test_ragged_lengths(n):
     sos = W.make_sos(4, 0.5, 0.95, 9)
     x = W.make_signal(n, 3, np.float64)
-    for solver, N in (("ph", 8), ("cr", 8), ("phd", 16)):
+    for solver, N in (("ph", 8), ("cr", 8), ("phd", 16), ("auto", 64)):
         y, _ = run(sos, x, compute_dtype="f64", solver=solver, N=N, tile_groups=2)
         assert oracle.rel_rms(y, oracle.sosfilt(x, sos)) < 1e-12, (n, solver)
+    # the headline plan: FP32 I/O (vector path only where 16-byte aligned), N = 64
+    x32 = x.astype(np.float32)
+    y, _ = run(sos, x32, compute_dtype="f64", solver="auto", N=64)
+    assert oracle.rel_rms(y, oracle.sosfilt(x32, sos)) < 1e-6, n
 
 
 def test_zero_length_is_noop():
