@@ -122,14 +122,22 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
     total_groups += (n[c] + G - 1) / G;
     b.total = std::max(b.total, b.off[c] + n[c]);
   }
-  b.mix = plans[0]->solver[0];
+  // each channel's solver class: SOS_CR or SOS_PH when all its sections use
+  // that solver, SOS_AUTO otherwise; the batch takes a specialised kernel
+  // when every channel has the same class, else the kernel that branches
+  // once per wavefront on the channel's class
+  std::vector<int32_t> cls(C);
   for (int c = 0; c < C; ++c) {
     const sos_plan_s *p = plans[c];
     b.kmax = std::max(b.kmax, p->K);
     b.b0one = b.b0one && p->b0_factored;
-    for (int k = 0; k < p->K; ++k)
-      if (p->solver[k] != b.mix) b.mix = SOS_AUTO;
+    cls[c] = p->solver[0];
+    for (int k = 1; k < p->K; ++k)
+      if (p->solver[k] != cls[c]) cls[c] = SOS_AUTO;
   }
+  b.mix = cls[0];
+  for (int c = 1; c < C; ++c)
+    if (cls[c] != b.mix) b.mix = SOS_AUTO;
   Residency res;
   if (!b.host_only)
     dispatch_rows<ResidencyBatched>(b.N, b.io_dtype, b.compute_dtype, b.b0one, b.mix, b.kmax, &res);
@@ -138,9 +146,15 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   b.tile.assign(C, 0);
   std::vector<int64_t> quads(C, 0);
   std::vector<double> cost(C, 0.0);
+  // a channel whose first sample is off a 16-byte boundary is filtered over
+  // [-shift, n): the shift samples before it read as zeros (zero state stays
+  // zero) and are not stored, and every group then starts on a boundary
+  const int64_t V = 16 / (int64_t)esz;
+  std::vector<int32_t> shift(C, 0);
   for (int c = 0; c < C; ++c) {
     const sos_plan_s *p = plans[c];
-    const int64_t groups = (n[c] + G - 1) / G;
+    shift[c] = (int32_t)(b.off[c] % V);
+    const int64_t groups = n[c] == 0 ? 0 : (n[c] + shift[c] + G - 1) / G;
     const int64_t tg = batch_tile_groups(p->warm / G, total_groups, resident_rows, tile_groups);
     if (groups == 0) {
       b.tile[c] = G;
@@ -172,8 +186,8 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
     ch.K = p->K;
     ch.stride = p->stride;
     ch.gain = p->gain;
-    ch.aligned = ((b.off[c] * (int64_t)esz) % 16) == 0;
-    ch.pad = 0;
+    ch.shift = shift[c];
+    ch.mix = cls[c];
     for (int64_t q = 0; q < quads[c]; ++q) b.item_chan.push_back(i);
     b.items += quads[c];
   }

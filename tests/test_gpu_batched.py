@@ -64,7 +64,8 @@ def test_batched_ragged_f64(solver, N):
 
 def test_batched_f32_dense_unaligned():
     """Dense packing of odd lengths puts channel starts off 16-byte
-    boundaries: those channels take the element-wise load/store path."""
+    boundaries: those channels are filtered over a span that starts up to
+    three samples early, so that their groups are 16-byte aligned."""
     lengths = [3, 1001, 777, 65537, 12345, 200003]
     Ks = [8, 3, 16, 8, 1, 5]
     sos, xs = channel_inputs(lengths, Ks, np.float32, seed=200)
@@ -74,6 +75,35 @@ def test_batched_f32_dense_unaligned():
         o = b.offsets[c]
         err = oracle.rel_rms(y[o:o + len(x)], oracle.sosfilt(x, s))
         assert err < 1e-6, (c, err)
+
+
+@pytest.mark.parametrize("io,N", [("f32", 16), ("f64", 8), ("f32", 64)])
+def test_batched_shifted_starts_keep_neighbours(io, N):
+    """Channels starting 1..V-1 samples past a 16-byte boundary (V samples
+    per 16 bytes), with lengths around whole groups once shifted: outputs
+    match the oracle, and the samples just before and after each channel
+    (gaps of 1..3 samples) keep their value."""
+    dtype = np.float64 if io == "f64" else np.float32
+    V = 16 // np.dtype(dtype).itemsize
+    G = 16 * N
+    lengths, offsets, pos = [], [], 0
+    for i, n in enumerate([1, 2, 3, G - 3, G - 2, G - 1, G, G + 1, 2 * G - 1, 3 * G + 5, 5 * G - 2, 40 * G + 3]):
+        s = 1 + i % (V - 1) if V > 2 else 1
+        pos = (pos + V - 1) // V * V + s           # start s samples past a boundary
+        offsets.append(pos)
+        lengths.append(n)
+        pos += n + 1 + i % 3                        # leave a gap of 1..3 samples
+    Ks = [1 + (3 * c) % 12 for c in range(len(lengths))]
+    sos, xs = channel_inputs(lengths, Ks, dtype, seed=350)
+    y, b = run_batch(sos, xs, io, N, solver="auto", offsets=offsets, tile_groups=2, fill=-3.0)
+    mask = np.ones(b.total, bool)
+    for c, (s_, x) in enumerate(zip(sos, xs)):
+        o = offsets[c]
+        mask[o:o + len(x)] = False
+        tol = 1e-12 if io == "f64" else 1e-6
+        err = oracle.rel_rms(y[o:o + len(x)], oracle.sosfilt(x, s_))
+        assert err < tol, (c, len(x), o % V, err)
+    assert np.all(y[:b.total][mask] == -3.0)
 
 
 def test_batched_gaps_untouched_and_order():

@@ -286,11 +286,14 @@ def test_batch_schedule_covers_every_channel(cap):
         assert t > 0 and t % G == 0
         if cap:
             assert t <= cap * G
-        ntiles = -(-int(lengths[c]) // t)
+        # the tiles cover [-shift, n): shift = samples past the last 16-byte
+        # boundary before the channel start (4 float32 samples per 16 bytes)
+        span = int(lengths[c]) + int(q["offsets"][c]) % 4 if lengths[c] else 0
+        ntiles = -(-span // t)
         quads = -(-ntiles // 4)
         # tiles as even as the length allows: the quads could not be fewer
         if ntiles:
-            assert (quads - 1) * 4 * t < lengths[c] + 4 * t
+            assert (quads - 1) * 4 * t < span + 4 * t
         items += quads
     assert q["items"] == items
 
