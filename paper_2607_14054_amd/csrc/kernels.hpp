@@ -391,41 +391,7 @@ __host__ __device__ constexpr int lds_bytes(int K) {
 //
 // SOLVER: SOS_PH or SOS_CR when every section uses that solver (no branch
 // in the section loop), SOS_AUTO for a per-section choice.
-//
-// PREFETCH: while a section runs, one dword of every 64-byte line that the
-// next section reads from its table is loaded and held until the section
-// ends.  The section's own table reads then hit the scalar cache instead
-// of waiting on L2 one line group at a time.  This matters when wavefronts
-// of several channels share a compute unit and evict each other's tables;
-// a single signal's table stays cached without it.  Only CR sections do
-// it: they read 5-6 lines, while PH's u1 and u2 would need more scalar
-// registers than the kernel has to spare.
-template <int N, typename T, int SOLVER>
-struct SectionLines {
-  static constexpr int kMax = 12;   // lines held at once (scalar registers)
-  int n = 0;
-  int line[kMax] = {};
-  constexpr void add(int e0, int e1) {   // elements [e0, e1) of a section's row
-    for (int b = e0 * (int)sizeof(T) / 64; b <= (e1 * (int)sizeof(T) - 1) / 64; ++b) {
-      bool seen = false;
-      for (int i = 0; i < n; ++i) seen = seen || line[i] == b;
-      if (!seen && n < kMax) line[n++] = b;
-    }
-  }
-  constexpr SectionLines() {
-    add(OFF_B0, OFF_A2 + 1);
-    if (SOLVER != SOS_PH) {
-      add(OFF_CR_POW, OFF_CR_POW + 4 * kLogL);
-      add(OFF_CR_LVL, OFF_CR_LVL + 4 * __builtin_ctz(N));
-    }
-    if (SOLVER != SOS_CR) {
-      add(OFF_PH_POW, OFF_PH_POW + 4 * kLogL);
-      add(OFF_U1, OFF_U1 + 2 * N);
-    }
-  }
-};
-
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER, bool PREFETCH = false>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
 __device__ __forceinline__ void filter_rows(const TI *__restrict__ x, TI *__restrict__ y,
                                             ctab<T> tab, const int32_t *__restrict__ solver,
                                             int64_t n, int K,
@@ -444,26 +410,10 @@ __device__ __forceinline__ void filter_rows(const TI *__restrict__ x, TI *__rest
     st[1] = last_of_row(X[N - 1]);
     for (int k = 0; k < K; ++k) {
       const ctab<T> c = tab + (int64_t)k * stride;
-      constexpr SectionLines<N, T, SOLVER> lines;
-      constexpr bool touch = PREFETCH && SOLVER == SOS_CR;
-      uint32_t hold[touch ? lines.n : 1];
-      if (touch) {
-        // the next section's lines (section 0's for the next group); every
-        // address lies inside this table's K rows
-        const ctab<uint32_t> nx = (ctab<uint32_t>)(tab + (int64_t)(k + 1 < K ? k + 1 : 0) * stride);
-#pragma unroll
-        for (int i = 0; i < lines.n; ++i) hold[i] = nx[16 * lines.line[i]];
-      }
       if (SOLVER == SOS_CR || (SOLVER == SOS_AUTO && solver[k] == SOS_CR))
         cr_section<N, T, B0ONE>(X, c, xs2, xs1, st + 2 + 2 * k);
       else
         ph_section<N, T, B0ONE>(X, c, xs2, xs1, st + 2 + 2 * k);
-      if (touch) {
-        // consume the held dwords here, after the section's arithmetic, so
-        // that their wait falls where the loads have long completed
-#pragma unroll
-        for (int i = 0; i < lines.n; ++i) asm volatile("" ::"s"(hold[i]));
-      }
     }
     if (it >= warm_groups) store_group<N, TI, T>(X, y, g, n, full, gain, buf);
   }
@@ -540,8 +490,8 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_batched_kernel(
   TI *buf = stage + (w * kRows + row) * Stage<N, TI>::ROWBUF;
   const ctab<T> tab = as_ctab(static_cast<const T *>(ch.tab));
 #define SOSF_BATCH_ROWS(S)                                                                       \
-  filter_rows<N, TI, T, B0ONE, S, true>(x + ch.off, y + ch.off, tab, ch.solver, ch.n, ch.K, ch.stride, t0, \
-                                        warm, ch.tile, true, (T)ch.gain, st, buf)
+  filter_rows<N, TI, T, B0ONE, S>(x + ch.off, y + ch.off, tab, ch.solver, ch.n, ch.K, ch.stride, t0, warm, \
+                                  ch.tile, true, (T)ch.gain, st, buf)
   if (SOLVER != SOS_AUTO) {
     SOSF_BATCH_ROWS(SOLVER);
   } else {
