@@ -10,6 +10,7 @@ namespace sosf {
 // kernels see it.
 struct AdjView {
   int64_t n, np, tile, warm, ntiles, sstride;
+  int64_t shift;            // forward tiles cover [-shift, n); saved arrays start shift elements in
   int32_t K, stride;
 };
 
@@ -25,7 +26,7 @@ struct AdjChan {
   int64_t partial_off;      // doubles into the workspace (ntiles x 5K)
   int64_t sstride;
   int32_t K, stride;
-  int32_t aligned;          // the channel's signals start 16-byte aligned
+  int32_t shift;            // off mod samples per 16 bytes (see AdjView)
   int32_t gsos_row;         // first row of the channel in gsos
 };
 

@@ -146,7 +146,11 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
   double *dbuf = reinterpret_cast<double *>(rowbuf);
   for (int i = 0; i < state_elems(v.K); ++i) st[i] = T(0);
   const int64_t G = (int64_t)N * kL;
-  const int64_t t0 = tile_index * v.tile;
+  // tiles over [-shift, n): groups start where x + g is 16-byte aligned (the
+  // samples before 0 read as zeros); the saved arrays start shift elements
+  // in, so that their groups are aligned too
+  const int64_t t0 = tile_index * v.tile - v.shift;
+  saved += v.shift;
   const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
   T X[N];
   for (int64_t it = 0; it < steps; ++it) {
@@ -182,6 +186,7 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   double *dbuf = reinterpret_cast<double *>(rowbuf);
   T *acc = st + 2 * v.K;
   for (int i = 0; i < 7 * v.K; ++i) st[i] = T(0);
+  saved += v.shift;   // the saved arrays' origin, as written by save_rows
   const int64_t G = (int64_t)N * kL;
   const int64_t t0 = tile_index * v.tile;
   const int64_t pad = v.np - v.n;
@@ -256,6 +261,7 @@ __device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
   v.warm = a.warm;
   v.ntiles = a.ntiles;
   v.sstride = a.sstride;
+  v.shift = 0;
   v.K = a.K;
   v.stride = a.stride;
   return v;
@@ -306,6 +312,7 @@ __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
   v.warm = c.warm;
   v.ntiles = c.ntiles;
   v.sstride = c.sstride;
+  v.shift = c.shift;
   v.K = c.K;
   v.stride = c.stride;
   return v;
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_batched_ker
                (int64_t)(w * kRows + row) * state_elems(kmax);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
   save_rows<N, TI, B0ONE>(x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd), adj_view(c),
-                          tile_index, c.aligned != 0, st, rowbuf);
+                          tile_index, true, st, rowbuf);
 }
 
 template <int N, typename TI>
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_batched_
                (int64_t)(w * kRows + row) * (7 * kmax);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
   adjoint_rows<N, TI>(gy + c.off, gx + c.off, x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd),
-                      ws + c.partial_off + tile_index * 5 * c.K, adj_view(c), tile_index, c.aligned != 0, st,
+                      ws + c.partial_off + tile_index * 5 * c.K, adj_view(c), tile_index, true, st,
                       rowbuf);
 }
 

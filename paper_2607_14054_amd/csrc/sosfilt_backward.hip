@@ -166,12 +166,20 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
     if (!plans[c]->bwd || !plans[c]->d_bwd_rows) return SOS_OK;   // no adjoint for this batch
   const int64_t G = (int64_t)kBwdN * kL;
   const int64_t V = b.io_dtype == SOS_F64 ? 2 : 4;
-  std::vector<int64_t> np(b.C);
+  // Channel c starts shift = off mod V samples past a 16-byte boundary.  The
+  // forward-time tiles cover [-shift, n); reversed time reads
+  // r[t] = s[np - 1 - t] with off + np a multiple of V.  Both put every
+  // group of x, gy, gx and of the saved arrays (origin shifted by shift) on
+  // a 16-byte boundary.  span: the samples the tiles must cover.
+  std::vector<int64_t> np(b.C), shift(b.C), span(b.C);
   int64_t total_groups = 0;
   b.adj_b0one = true;
   for (int c = 0; c < b.C; ++c) {
-    np[c] = (b.n[c] + V - 1) / V * V;
-    total_groups += (np[c] + G - 1) / G;
+    const int64_t n = b.n[c];
+    shift[c] = b.off[c] % V;
+    np[c] = n ? (b.off[c] + n + V - 1) / V * V - b.off[c] : 0;
+    span[c] = n ? std::max(n + shift[c], np[c]) : 0;
+    total_groups += (span[c] + G - 1) / G;
     b.adj_b0one = b.adj_b0one && plans[c]->bwd->b0_factored;
   }
   const Residency r = residency_of(b.io_dtype == SOS_F64 ? adjoint_batched_kernel_ptr<double>()
@@ -188,12 +196,11 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
   std::vector<AdjChan> chans(b.C);
   std::vector<int32_t> item_chan, red(rows, 0);
   int64_t ws = 0, items = 0;
-  const size_t esz = b.io_dtype == SOS_F64 ? 8 : 4;
   for (int i = 0; i < b.C; ++i) {
     const int32_t c = b.order[i];
     const sos_plan_s *sub = plans[c]->bwd;
     AdjChan &a = chans[i];
-    const int64_t groups = (np[c] + G - 1) / G;
+    const int64_t groups = (span[c] + G - 1) / G;
     int64_t tg = tile_groups > 0 ? tile_groups : std::max<int64_t>(16 * (sub->warm / G), 8);
     if (tile_groups <= 0) {
       const int64_t tg_par = std::max<int64_t>(total_groups / std::max<int64_t>(resident_rows, 1), 1);
@@ -208,16 +215,16 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
     a.np = np[c];
     a.tile = tgc * G;
     a.warm = sub->warm;
-    a.ntiles = groups ? (np[c] + a.tile - 1) / a.tile : 0;
+    a.ntiles = groups ? (span[c] + a.tile - 1) / a.tile : 0;
     a.first_item = items;
-    a.sstride = (b.n[c] + 63) / 64 * 64;
+    a.sstride = (b.n[c] + shift[c] + 63) / 64 * 64;
     a.saved_off = ws;
     ws += (int64_t)plans[c]->K * a.sstride;
     a.partial_off = ws;
     ws += (a.ntiles * 5 * plans[c]->K + 31) / 32 * 32;
     a.K = plans[c]->K;
     a.stride = sub->stride;
-    a.aligned = ((b.off[c] * (int64_t)esz) % 16) == 0;
+    a.shift = (int32_t)shift[c];
     a.gsos_row = (int32_t)b.adj_gsos_row[c];
     for (int64_t q = 0; q < quads; ++q) item_chan.push_back(i);
     items += quads;

@@ -200,6 +200,54 @@ def test_batched_adjoint_matches_oracle(io):
             assert row_err(g_c, rs) < 1e-9, c
 
 
+@pytest.mark.parametrize("io", ["f32", "f64"])
+def test_batched_adjoint_shifted_starts_keep_neighbours(io):
+    """Channels starting 1..V-1 samples past a 16-byte boundary (V samples
+    per 16 bytes) with gaps of 1..3 samples between them, lengths around
+    whole groups of the adjoint tiles: dL/dx and dL/dsos match the oracle
+    and the gap samples of gx keep their value."""
+    dt = np.float64 if io == "f64" else np.float32
+    V = 16 // np.dtype(dt).itemsize
+    G = 256                                       # adjoint group: N = 16, 16 lanes
+    lengths, offsets, pos = [], [], 0
+    for i, n in enumerate([1, 2, 3, G - 3, G - 2, G - 1, G, G + 1, 2 * G - 1, 3 * G + 5, 5000, 70001]):
+        s_ = 1 + i % (V - 1) if V > 2 else 1
+        pos = (pos + V - 1) // V * V + s_
+        offsets.append(pos)
+        lengths.append(n)
+        pos += n + 1 + i % 3
+    Ks = [1 + (5 * c) % 9 for c in range(len(lengths))]
+    sos = [W.make_sos(k, 0.5, 0.95, 170 + c) for c, k in enumerate(Ks)]
+    plans = [S.Plan(s_, io_dtype=io, compute_dtype="f64", N=32) for s_ in sos]
+    b = S.Batch(plans, lengths, offsets=offsets)
+    xs = [W.make_signal(n, 171 + c, dt) for c, n in enumerate(lengths)]
+    gs = [W.grad_seed_signal(n, 171 + c, dt) for c, n in enumerate(lengths)]
+    xb = np.zeros(b.total, dt)
+    gb = np.zeros(b.total, dt)
+    for c, o in enumerate(offsets):
+        xb[o:o + lengths[c]] = xs[c]
+        gb[o:o + lengths[c]] = gs[c]
+    gx0 = torch.full((b.total,), -3.0, dtype=torch.float32 if io == "f32" else torch.float64, device=DEV)
+    gx, gsos, first = S.filt_backward_batched(b, torch.from_numpy(xb).to(DEV), torch.from_numpy(gb).to(DEV),
+                                              gx=gx0)
+    torch.cuda.synchronize()
+    gx = gx.cpu().numpy()
+    gsos = gsos.cpu().numpy()
+    mask = np.ones(b.total, bool)
+    for c, o in enumerate(offsets):
+        n, K = lengths[c], Ks[c]
+        mask[o:o + n] = False
+        g_c = gsos[first[c]:first[c] + K]
+        x64, g64 = xs[c].astype(np.float64), gs[c].astype(np.float64)
+        if io == "f64":
+            check_f64(x64, sos[c], g64, gx[o:o + n], g_c, "shifted c=%d" % c)
+        else:
+            rx, rs = oracle.sosfilt_backward(x64, sos[c], g64)
+            assert oracle.rel_rms(gx[o:o + n], rx) < 1e-6, (c, n, o % V)
+            assert row_err(g_c, rs) < 1e-9, (c, n, o % V)
+    assert np.all(gx[mask] == -3.0)
+
+
 def test_batched_adjoint_equals_single_channel_adjoint():
     """Each channel of the batched adjoint equals sos_filt_backward on that
     channel alone to rounding (the tiles differ)."""
