@@ -64,16 +64,32 @@ __device__ __forceinline__ double dpp(double v) {
 template <int D, typename T>
 __device__ __forceinline__ T shr(T v) { return dpp<0x110 + D, true>(v); }
 
-// R with a fill value for lane 0 of the row.
-template <typename T>
-__device__ __forceinline__ T shift_r(T v, T fill) {
-  const T s = shr<1>(v);
-  return row_lane() == 0 ? fill : s;
+// R with a fill value for lane 0 of the row: without bound_ctrl the DPP
+// move leaves a lane whose source is outside the row (lane 0 for row_shr:1)
+// at its old value, which is the fill.
+__device__ __forceinline__ float shift_r(float v, float fill) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x111, 0xf, 0xf,
+                                                    false));
+}
+__device__ __forceinline__ double shift_r(double v, double fill) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v), f = (uint64_t)__double_as_longlong(fill);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)f, (int)(uint32_t)b, 0x111, 0xf, 0xf, false);
+  const uint32_t hi =
+      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(f >> 32), (int)(uint32_t)(b >> 32), 0x111, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Lane 15 of the row in every lane of the row.
+// Lane 15 of the row in every lane of the row (a 64-bit value moves in one
+// row_newbcast).
+__device__ __forceinline__ float last_of_row(float v) { return dpp<0x15f, false>(v); }
+__device__ __forceinline__ double last_of_row(double v) {
+  return __longlong_as_double(__builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x15f, 0xf, 0xf, false));
+}
+
+// 1 in lane 0 of the row, 0 elsewhere: multiplies the previous group's
+// boundary values into the first lane only.
 template <typename T>
-__device__ __forceinline__ T last_of_row(T v) { return dpp<0x15f, false>(v); }
+__device__ __forceinline__ T lane0_mask() { return row_lane() == 0 ? T(1) : T(0); }
 
 // Log-depth solve along the row of z_l = A z_{l-1} + z_l (z_{-1} = 0) for
 // 2-vectors z = (p, q): round j adds A^(2^j) times the value 2^j lanes below
@@ -159,8 +175,8 @@ __device__ __forceinline__ void ph_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
   // over its own N samples.  On lane 0 of the row the recurrence starts from
   // the previous group's outputs, which is the same arithmetic as the state
   // correction of v_0[0] and v_1[0].
-  const bool l0 = row_lane() == 0;
-  particular_pass<N, T>(X, a1, a2, l0 ? ys1 : T(0), l0 ? ys2 : T(0));
+  const T m0 = lane0_mask<T>();
+  particular_pass<N, T>(X, a1, a2, m0 * ys1, m0 * ys2);
   // step 2, eq. recursive_doubling_equation: y_e[l] = w_e[l] - C y_e[l-1]
   // along the row, with y_e[l] = (y[(l+1)N-2], y[(l+1)N-1])
   T p = X[N - 2], q = X[N - 1];
@@ -193,9 +209,9 @@ __device__ __forceinline__ void cr_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
   fir_pass<N, T, B0ONE>(X, c, shift_r(X[N - 1], xs1), shift_r(X[N - 2], xs2));
   __builtin_amdgcn_sched_barrier(0);
   // the previous group's outputs enter the first element of blocks 0 and 1
-  const bool l0 = row_lane() == 0;
-  X[0] -= l0 ? fma_(a1, ys1, a2 * ys2) : T(0);
-  X[1] -= l0 ? a2 * ys1 : T(0);
+  const T m0 = lane0_mask<T>(), z1 = m0 * ys1, z2 = m0 * ys2;
+  X[0] = fma_(-a1, z1, fma_(-a2, z2, X[0]));
+  X[1] = fma_(-a2, z1, X[1]);
   // reduction, eq. cr_coeff_update coefficients per level
 #pragma unroll
   for (int i = 0; i < LG; ++i) {
