@@ -62,7 +62,8 @@ typedef enum {
 } sos_dtype;
 
 typedef enum {
-    SOS_AUTO = 0,        /* cyclic reduction, with PH for sections the CR guard rejects */
+    SOS_AUTO = 0,        /* PH for every section: the faster of the two on MI355X at
+                            every N from 8 to 64, and free of the CR guard */
     SOS_PH = 1,          /* PH factorisation (Section VI-B) for every section */
     SOS_CR = 2,          /* cyclic reduction (Section VI-C), guard still applies */
     SOS_PH_DEFERRED = 3, /* PH with the homogeneous correction (eq. PH_forward) of all

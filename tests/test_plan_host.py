@@ -147,8 +147,15 @@ def test_cr_guard_falls_back_to_ph(theta, N):
     r = 0.9
     sec = np.array([[1.0, 0.0, 0.0, 1.0, -2 * r * math.cos(theta), r * r]])
     assert plan(sec, N=N, solver="cr").info().solver == ["ph"]
-    # auto: FP32 arithmetic (no deferred form) takes cyclic reduction with the guard
+    # auto takes PH whatever the guard says
     assert plan(sec, N=N, solver="auto", compute_dtype="f32").info().solver == ["ph"]
+
+
+def test_auto_takes_ph():
+    sos = W.make_sos(8, 0.8, 0.98, 0)
+    for N in (8, 16, 32, 64):
+        assert plan(sos, N=N).info().solver == ["ph"] * 8
+        assert plan(sos, N=N, solver="cr").info().solver == ["cr"] * 8
 
 
 def test_cr_flush_of_negligible_levels():
