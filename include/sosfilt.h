@@ -347,7 +347,8 @@ sos_status sos_filt_backward_batched(sos_batch_t batch, const void *x, const voi
  * Ns, nN     host: candidate N values; tiles, nt: candidate tile_groups
  *            (0 = the library's choice).
  * x, y       device buffers laid out as the batch (y is overwritten).
- * reps       timed launches per candidate (after one untimed launch).
+ * reps       timed launches per candidate, after untimed launches for at
+ *            least 30 ms (code load, clocks after the host-side planning).
  * results    host [nN * nt] or NULL: every candidate's seconds per launch,
  *            N-major.
  * best       host: the fastest candidate.

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -425,7 +426,13 @@ sos_status sos_batch_tune(const double *const *sos, const int32_t *K, int32_t C,
       st = sos_batch_plan(plans.data(), C, n, offsets, &bo, &b);
       if (st != SOS_OK) break;
       float ms = 0.f;
-      st = sos_filt_batched(b, x, y, nullptr, stream);   // warm-up (code load, clocks)
+      // warm-up: load the code and bring the clocks back up after the host
+      // built this configuration's plans (launch until 30 ms have passed)
+      const auto t0 = std::chrono::steady_clock::now();
+      do {
+        st = sos_filt_batched(b, x, y, nullptr, stream);
+        if (st == SOS_OK && hipStreamSynchronize(s) != hipSuccess) st = SOS_E_DEVICE;
+      } while (st == SOS_OK && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(30));
       if (st == SOS_OK && hipEventRecord(e0, s) != hipSuccess) st = SOS_E_DEVICE;
       for (int r = 0; r < reps && st == SOS_OK; ++r) st = sos_filt_batched(b, x, y, nullptr, stream);
       if (st == SOS_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
