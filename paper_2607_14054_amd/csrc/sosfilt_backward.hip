@@ -201,10 +201,15 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
     const sos_plan_s *sub = plans[c]->bwd;
     AdjChan &a = chans[i];
     const int64_t groups = (span[c] + G - 1) / G;
+    // Tiles as long as 16 run-ins where the batch fills the GPU with them;
+    // otherwise as short as fills it, down to 2 run-ins.  The adjoint pass
+    // waits on memory and on its reductions more than the forward does, so
+    // a second wavefront per SIMD pays for more run-in than it does there
+    // (4 run-ins).
     int64_t tg = tile_groups > 0 ? tile_groups : std::max<int64_t>(16 * (sub->warm / G), 8);
     if (tile_groups <= 0) {
       const int64_t tg_par = std::max<int64_t>(total_groups / std::max<int64_t>(resident_rows, 1), 1);
-      if (tg_par < tg) tg = std::max<int64_t>(tg_par, std::max<int64_t>(4 * (sub->warm / G), 4));
+      if (tg_par < tg) tg = std::max<int64_t>(tg_par, std::max<int64_t>(2 * (sub->warm / G), 2));
     }
     const int64_t quads = groups ? (groups + 4 * tg - 1) / (4 * tg) : 0;
     const int64_t tgc = quads ? (groups + 4 * quads - 1) / (4 * quads) : 1;
