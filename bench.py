@@ -303,6 +303,33 @@ def bench_grad_long(S, W, torch, dev, args):
     return {"samples": n, "ms": sec * 1e3, "GSps": n / sec / 1e9}
 
 
+def bench_draws(S, W, torch, dev, args):
+    """The headline cascade shape over 16 coefficient draws (seeds 0..15,
+    K = 8, r in [0.8, 0.98]) on 2^24 float32 samples each: the kernel's
+    relative RMS against the FP64 oracle, and the FP32 floor (a plain
+    sequential FP32 cascade) on the same draw."""
+    import oracle
+    n = 1 << 24
+    x_np = W.make_signal(n, 0, np.float32)
+    xt = torch.from_numpy(x_np).to(dev)
+    rows = []
+    for seed in range(16):
+        sos = W.make_sos(8, 0.8, 0.98, seed)
+        plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=args.solver, N=args.N or 64)
+        y = S.filt(plan, xt).cpu().numpy()
+        ref = oracle.sosfilt(x_np, sos)
+        rows.append({"seed": seed, "rel_rms": oracle.rel_rms(y, ref), "max_rel": oracle.max_rel(y, ref),
+                     "fp32_floor_rel_rms": oracle.rel_rms(oracle.sosfilt_f32arith(x_np, sos), ref)})
+    k = np.array([r["rel_rms"] for r in rows])
+    f = np.array([r["fp32_floor_rel_rms"] for r in rows])
+    out = {"n": n, "draws": rows, "rel_rms_median": float(np.median(k)), "rel_rms_max": float(k.max()),
+           "fp32_floor_median": float(np.median(f)), "fp32_floor_max": float(f.max())}
+    log("draws: 16 coefficient draws, 2^24 samples: kernel rel_rms median %.2e max %.2e; "
+        "FP32 floor median %.2e max %.2e" % (out["rel_rms_median"], out["rel_rms_max"],
+                                              out["fp32_floor_median"], out["fp32_floor_max"]))
+    return out
+
+
 def bench_precision(S, W, torch, dev, args):
     """The precision workload: 256 channels x 2^20 float32 samples, K = 8,
     pole radius U[0.9, 0.999], channel c drawn with seed c.  One batched
@@ -384,6 +411,8 @@ def main():
                     help="also report the error per arithmetic type on the precision workload")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy of the signal (counter calibration)")
+    ap.add_argument("--draws", action="store_true",
+                    help="also the kernel's and the FP32 floor's error over 16 coefficient draws")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
@@ -476,8 +505,11 @@ def main():
         extra["stream"] = bench_stream(S, W, torch, dev, args)
     if args.precision:
         extra["precision"] = bench_precision(S, W, torch, dev, args)
+    if args.draws:
+        extra["draws"] = bench_draws(S, W, torch, dev, args)
 
     cpu = None
+    comparator = None
     accuracy = {}
     if not args.no_cpu:
         import oracle
@@ -489,9 +521,25 @@ def main():
                "sample": "the full 2^28-sample signal, FP64 direct form I, one thread"}
         accuracy["rel_rms"] = oracle.rel_rms(y_np, ref)
         accuracy["max_rel"] = oracle.max_rel(y_np, ref)
-        log("oracle: %.2f s (%.1f MS/s); rel_rms=%.3e max_rel=%.3e"
-            % (tc, n / tc / 1e6, accuracy["rel_rms"], accuracy["max_rel"]))
+        # the FP32 floor: a plain sequential FP32 cascade on the same draw
+        accuracy["fp32_floor_rel_rms"] = oracle.rel_rms(oracle.sosfilt_f32arith(x_np, sos), ref)
+        log("oracle: %.2f s (%.1f MS/s); rel_rms=%.3e max_rel=%.3e; FP32 floor %.3e"
+            % (tc, n / tc / 1e6, accuracy["rel_rms"], accuracy["max_rel"], accuracy["fp32_floor_rel_rms"]))
         del ref
+        # the paper's CPU comparator, scipy.signal.sosfilt in FP64 on one
+        # thread, timed on the first 2^26 samples
+        try:
+            import scipy.signal as ss
+            m = min(n, 1 << 26)
+            x64 = x_np[:m].astype(np.float64)
+            t = time.time()
+            ss.sosfilt(np.asarray(sos, dtype=np.float64), x64)
+            tc = time.time() - t
+            comparator = {"kind": "scipy.signal.sosfilt", "value": m / tc / 1e9, "unit": "GS/s", "cores": 1,
+                          "sample": "the first 2^%d samples as FP64" % (m.bit_length() - 1)}
+            log("scipy.signal.sosfilt: %.2f s for %d samples (%.1f MS/s)" % (tc, m, m / tc / 1e6))
+        except ImportError:
+            comparator = None
 
     line = {
         "metric": "GS/s filtered (K=8, FP32) + % HBM roofline; forms vs plain at <=1e-4 rel RMS",
@@ -513,6 +561,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(N, args.solver, info.solver, n)},
         "cpu_baseline": cpu,
+        "cpu_comparator": comparator,
         "accuracy": accuracy,
     }
     print(json.dumps(line), flush=True)
