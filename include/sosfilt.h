@@ -209,8 +209,10 @@ sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
  * offsets  host [C] or NULL: first sample of channel c in the concatenated
  *          x and y buffers.  NULL packs the channels densely in order
  *          (offset[c] = n[0] + ... + n[c-1]).  Channels must not overlap.
- *          A channel whose offset is not a multiple of 16 bytes is still
- *          exact but loads and stores element by element.
+ *          Any offset is accepted at full speed: a channel starting off
+ *          a 16-byte boundary is filtered over a span that begins up to
+ *          three samples (FP64: one) earlier, read as zeros and never
+ *          stored, so that its groups move as 16-byte vectors.
  * opts     host, may be NULL: tile_groups > 0 caps the groups per tile
  *          (0 = chosen from the total length); flags SOS_FLAG_HOST_ONLY
  *          builds the schedule without device memory (queries only, and
