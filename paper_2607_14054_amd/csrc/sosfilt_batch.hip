@@ -19,16 +19,46 @@ using namespace sosf;
 
 namespace {
 
-// Groups per tile for a channel: as for one signal, long enough that the
-// run-in costs little, short enough that the whole batch keeps every
-// resident row of the device busy.
-int64_t batch_tile_groups(int64_t warm_groups, int64_t total_groups, int64_t resident_rows,
-                          int32_t cap) {
-  if (cap > 0) return cap;
-  int64_t tg = std::max<int64_t>(16 * warm_groups, 8);
-  const int64_t tg_par = std::max<int64_t>(total_groups / std::max<int64_t>(resident_rows, 1), 1);
-  if (tg_par < tg) tg = std::max<int64_t>(tg_par, std::max<int64_t>(4 * warm_groups, 4));
-  return tg;
+// One channel's share of the schedule, in groups: its span, its run-in
+// and its sections.
+struct ChanWork {
+  int64_t groups, warm_groups;
+  int32_t K;
+};
+
+// Groups per tile (the cap every channel's tile stays under), from a
+// makespan model.  Each candidate cap gives every channel's work items
+// (quads of four equal row tiles, each preceded by its run-in, clamped at
+// the channel start) and their cost in group-sections, K (tile + run-in).
+// The launch then takes about
+//   total / simds + (longest item) * waves_per_simd
+// in SIMD time: the list-scheduling bound for items of one wavefront each,
+// with waves_per_simd of them sharing a SIMD.  Long tiles waste little on
+// run-ins; short tiles give more items and a shorter tail.  A channel with
+// a long run-in (poles near the unit circle) needs the short tiles for
+// parallelism even at the cost of run-in many times its tile.
+int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t waves_per_simd) {
+  int64_t best_tg = 8;
+  double best = -1.0;
+  for (int e = 0; e <= 12; ++e) {
+    const int64_t tg = int64_t(1) << e;
+    double total = 0.0, longest = 0.0;
+    for (const ChanWork &c : w) {
+      if (c.groups == 0) continue;
+      const int64_t quads = (c.groups + 4 * tg - 1) / (4 * tg);
+      const int64_t tgc = (c.groups + 4 * quads - 1) / (4 * quads);
+      const int64_t wc = std::min<int64_t>(c.warm_groups, (c.groups - 1) / tgc * tgc);
+      const double item = (double)c.K * (double)(tgc + wc);
+      total += (double)quads * item;
+      longest = std::max(longest, item);
+    }
+    const double cost = total / (double)std::max<int64_t>(simds, 1) + longest * (double)waves_per_simd;
+    if (best < 0.0 || cost < best * 0.999) {
+      best = cost;
+      best_tg = tg;
+    }
+  }
+  return best_tg;
 }
 
 template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
@@ -118,11 +148,7 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   }
   const size_t esz = b.io_dtype == SOS_F64 ? 8 : 4;
   const int64_t G = (int64_t)b.N * kL;
-  int64_t total_groups = 0;
-  for (int c = 0; c < C; ++c) {
-    total_groups += (n[c] + G - 1) / G;
-    b.total = std::max(b.total, b.off[c] + n[c]);
-  }
+  for (int c = 0; c < C; ++c) b.total = std::max(b.total, b.off[c] + n[c]);
   // each channel's solver class: SOS_CR or SOS_PH when all its sections use
   // that solver, SOS_AUTO otherwise; the batch takes a specialised kernel
   // when every channel has the same class, else the kernel that branches
@@ -142,21 +168,25 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   Residency res;
   if (!b.host_only)
     dispatch_rows<ResidencyBatched>(b.N, b.io_dtype, b.compute_dtype, b.b0one, b.mix, b.kmax, &res);
-  const int64_t resident_rows = (int64_t)4 * res.simds * res.waves_per_simd;
-  // per-channel tiles: quads of four row tiles, as even as the length allows
-  b.tile.assign(C, 0);
-  std::vector<int64_t> quads(C, 0);
-  std::vector<double> cost(C, 0.0);
   // a channel whose first sample is off a 16-byte boundary is filtered over
   // [-shift, n): the shift samples before it read as zeros (zero state stays
   // zero) and are not stored, and every group then starts on a boundary
   const int64_t V = 16 / (int64_t)esz;
   std::vector<int32_t> shift(C, 0);
+  std::vector<ChanWork> work(C);
+  for (int c = 0; c < C; ++c) {
+    shift[c] = (int32_t)(b.off[c] % V);
+    work[c] = ChanWork{n[c] == 0 ? 0 : (n[c] + shift[c] + G - 1) / G, plans[c]->warm / G, plans[c]->K};
+  }
+  const int64_t tg = tile_groups > 0 ? tile_groups : batch_tile_groups(work, res.simds, res.waves_per_simd);
+  // per-channel tiles: quads of four row tiles under the cap, as even as
+  // the length allows
+  b.tile.assign(C, 0);
+  std::vector<int64_t> quads(C, 0);
+  std::vector<double> cost(C, 0.0);
   for (int c = 0; c < C; ++c) {
     const sos_plan_s *p = plans[c];
-    shift[c] = (int32_t)(b.off[c] % V);
-    const int64_t groups = n[c] == 0 ? 0 : (n[c] + shift[c] + G - 1) / G;
-    const int64_t tg = batch_tile_groups(p->warm / G, total_groups, resident_rows, tile_groups);
+    const int64_t groups = work[c].groups;
     if (groups == 0) {
       b.tile[c] = G;
       continue;
