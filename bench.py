@@ -330,6 +330,64 @@ def bench_draws(S, W, torch, dev, args):
     return out
 
 
+def bench_carry(S, W, torch, dev, args):
+    """Single signals whose run-in is long against the tile the device needs
+    (K = 8, pole radius U[0.9, 0.999], seed 3, float32 I/O, FP64 arithmetic,
+    N = 64): the run-in carry against the exact scan carry, at 2^20, 2^24
+    and 2^28 samples.  Both are checked against each other."""
+    sos = W.make_sos(8, 0.9, 0.999, 3)
+    out = {"rows": []}
+    for log2n in (20, 24, 28):
+        n = 1 << log2n
+        xt = torch.from_numpy(W.make_signal(n, 3, np.float32)).to(dev)
+        ys = {}
+        for carry in ("runin", "scan"):
+            plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=args.solver, N=64, carry=carry)
+            ws = plan.workspace_size(n)
+            wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=dev)
+            y = torch.empty_like(xt)
+
+            def once():
+                _check_call(S, plan, xt, y, wsb if ws else None)
+            sec = timed(torch, once, max(3, args.steps // 4))
+            ys[carry] = y
+            row = {"log2n": log2n, "carry": carry, "GSps": n / sec / 1e9, "ms": sec * 1e3,
+                   "warm_samples": plan.info().warm_samples, "tile": plan.tile(n), "workspace": ws}
+            out["rows"].append(row)
+            log("carry %-5s 2^%d: %.3f ms %.1f GS/s (run-in %d samples)" % (carry, log2n, sec * 1e3, n / sec / 1e9,
+                                                                             row["warm_samples"]))
+        d = (ys["runin"] - ys["scan"]).double()
+        out["rows"][-1]["rel_rms_scan_vs_runin"] = float(d.norm() / ys["runin"].double().norm())
+        del xt, ys
+        torch.cuda.empty_cache()
+    return out
+
+
+def _check_call(S, plan, x, y, wsb):
+    import ctypes
+    rc = S.lib().sos_filt(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
+                          ctypes.c_void_p(wsb.data_ptr()) if wsb is not None else None, None)
+    if rc != 0:
+        raise RuntimeError("sos_filt: status %d" % rc)
+
+
+def timed(torch, once, steps):
+    """Seconds per call: a 0.3 s clock warm-up, then `steps` calls between
+    events on the current stream."""
+    t_end = time.time() + 0.3
+    while time.time() < t_end:
+        once()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        once()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
 def bench_precision(S, W, torch, dev, args):
     """The precision workload: 256 channels x 2^20 float32 samples, K = 8,
     pole radius U[0.9, 0.999], channel c drawn with seed c.  One batched
@@ -411,6 +469,8 @@ def main():
                     help="also report the error per arithmetic type on the precision workload")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy of the signal (counter calibration)")
+    ap.add_argument("--carry", action="store_true",
+                    help="also the run-in against the exact scan carry on long-run-in single signals")
     ap.add_argument("--draws", action="store_true",
                     help="also the kernel's and the FP32 floor's error over 16 coefficient draws")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -507,6 +567,8 @@ def main():
         extra["precision"] = bench_precision(S, W, torch, dev, args)
     if args.draws:
         extra["draws"] = bench_draws(S, W, torch, dev, args)
+    if args.carry:
+        extra["carry"] = bench_carry(S, W, torch, dev, args)
 
     cpu = None
     comparator = None

@@ -84,6 +84,11 @@ typedef enum {
 /* Plan flags. */
 #define SOS_FLAG_HOST_ONLY 0x1u   /* build the FP64 host tables only; the plan
                                      can be queried but not used to filter */
+#define SOS_FLAG_CARRY_SCAN 0x2u  /* carry between tiles by the exact scan
+                                     whenever the plan supports it (see
+                                     sos_workspace_size) */
+#define SOS_FLAG_CARRY_RUNIN 0x4u /* always carry by the run-in (not with
+                                     SOS_FLAG_CARRY_SCAN) */
 
 typedef struct {
     int32_t io_dtype;       /* sos_dtype of x and y (default SOS_F32) */
@@ -173,7 +178,17 @@ typedef enum {
 sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
                           double *out, int32_t count, int32_t *size);
 
-/* Device workspace bytes sos_filt needs for n samples (0 at present). */
+/*
+ * Device workspace bytes sos_filt uses for n samples: 0 when it carries the
+ * state between tiles by the run-in, else the size of the exact carry's
+ * buffers.  The exact carry (FP64 arithmetic, solvers AUTO, PH or CR,
+ * K <= 16) runs every tile twice, once from zero section states to get its
+ * end state c_t and once from the scanned true state, with a log-depth scan
+ * S_t = c_t + Phi^T S_{t-1} in between (Phi the cascade's one-step state
+ * transition).  sos_filt takes it when the run-in would be longer than 1.2
+ * tiles (a signal short against its run-in, poles near the unit circle), or
+ * always with SOS_FLAG_CARRY_SCAN; never with SOS_FLAG_CARRY_RUNIN.
+ */
 size_t sos_workspace_size(sos_plan_t plan, int64_t n);
 
 /*
@@ -183,8 +198,12 @@ size_t sos_workspace_size(sos_plan_t plan, int64_t n);
  *            (SOS_E_ARG): tiles re-read input that precedes them.
  * n          >= 0; n == 0 is a no-op.  Any n is accepted: the last group is
  *            zero-padded and only n outputs are written.
- * workspace  device, sos_workspace_size bytes (may be NULL when that is 0).
+ * workspace  device, at least sos_workspace_size(plan, n) bytes, 16-byte
+ *            aligned, contents on entry irrelevant; may be NULL, which keeps
+ *            the run-in carry (SOS_E_ARG if the plan has SOS_FLAG_CARRY_SCAN
+ *            and the size is not 0).
  * stream     HIP stream the kernels are enqueued on.
+ * No allocation and no synchronisation in either carry.
  */
 sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
                     void *workspace, sos_stream_t stream);

@@ -74,6 +74,8 @@ struct sos_plan_s {
   std::vector<unsigned char> block_aop;
   void *d_block = nullptr;
   void *d_aop = nullptr;
+  // exact inter-tile carry: the one-step state transition phi on the device
+  void *d_phi = nullptr;
 };
 
 namespace sosf {
@@ -86,6 +88,19 @@ sos_status build_block_plan(sos_plan_s &p);
 sos_status upload_block_plan(sos_plan_s &p);
 int64_t block_tile(const sos_plan_s &p, int64_t n);
 sos_status launch_block(const sos_plan_s &p, const void *x, void *y, int64_t n, hipStream_t s);
+// exact inter-tile carry (sosfilt_carry.hip): whether a plan can use it, the
+// tiles, scan rounds and workspace for n samples (use = false: run-in), and
+// the launches
+struct CarryLayout {
+  bool use = false;
+  int64_t tile = 0, ntiles = 0;
+  int rounds = 0;
+  size_t aggs_off = 0, buf_off = 0, pow_off = 0, bytes = 0;
+};
+bool carry_supported(const sos_plan_s &p);
+CarryLayout carry_layout(const sos_plan_s &p, int64_t n, int64_t runin_tile);
+sos_status launch_carry(const sos_plan_s &p, const CarryLayout &l, const void *x, void *y, int64_t n, void *ws,
+                        hipStream_t s);
 }
 sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
                        sos_plan_t *out);

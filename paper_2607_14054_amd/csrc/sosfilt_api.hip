@@ -235,7 +235,9 @@ const char *sos_status_string(sos_status s) {
 }
 
 sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan_t *out) {
-  if (opts && (opts->flags & ~SOS_FLAG_HOST_ONLY)) return SOS_E_ARG;
+  constexpr uint32_t known = SOS_FLAG_HOST_ONLY | SOS_FLAG_CARRY_SCAN | SOS_FLAG_CARRY_RUNIN;
+  if (opts && (opts->flags & ~known)) return SOS_E_ARG;
+  if (opts && (opts->flags & SOS_FLAG_CARRY_SCAN) && (opts->flags & SOS_FLAG_CARRY_RUNIN)) return SOS_E_ARG;
   return create_plan(sos, K, opts, true, out);
 }
 
@@ -290,6 +292,16 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   }
   if (st == SOS_OK && !(o.flags & SOS_FLAG_HOST_ONLY)) {
     st = upload(*p);
+    if (st == SOS_OK && carry_supported(*p)) {
+      // the transition the exact inter-tile carry raises to the tile length
+      const size_t bytes = p->phi.size() * sizeof(double);
+      if (hipMalloc(&p->d_phi, bytes) != hipSuccess) {
+        p->d_phi = nullptr;
+        st = SOS_E_NOMEM;
+      } else if (hipMemcpy(p->d_phi, p->phi.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        st = SOS_E_DEVICE;
+      }
+    }
     Residency r;
     if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED)
       r = p->io_dtype == SOS_F32 ? deferred_residency<float>(p->N, p->K, p->b0_factored)
@@ -330,6 +342,7 @@ sos_status sos_plan_destroy(sos_plan_t p) {
     if (p->d_bwd_rows) hipFree(p->d_bwd_rows);
     if (p->d_block) hipFree(p->d_block);
     if (p->d_aop) hipFree(p->d_aop);
+    if (p->d_phi) hipFree(p->d_phi);
     if (p->device >= 0 && cur >= 0 && cur != p->device) hipSetDevice(cur);
   }
   if (p->bwd) sos_plan_destroy(p->bwd);
@@ -400,14 +413,12 @@ int64_t sos_plan_tile(sos_plan_t p, int64_t n) {
 }
 
 size_t sos_workspace_size(sos_plan_t p, int64_t n) {
-  (void)p;
-  (void)n;
-  return 0;
+  if (!p || n <= 0) return 0;
+  return carry_layout(*p, n, choose_tile(*p, n)).bytes;
 }
 
 sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *workspace,
                     sos_stream_t stream) {
-  (void)workspace;
   if (!p || n < 0) return SOS_E_ARG;
   if (n == 0) return SOS_OK;
   if (!x || !y) return SOS_E_ARG;
@@ -432,6 +443,13 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
   if (p->solver_opt == SOS_PH_DEFERRED) {
     if (p->io_dtype == SOS_F32) return launch_deferred<float>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);
     return launch_deferred<double>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);
+  }
+  // the exact inter-tile carry where the run-in would cost more than the
+  // carry's second pass (it needs the caller's workspace)
+  const CarryLayout cl = carry_layout(*p, n, a.tile);
+  if (cl.use) {
+    if (workspace && ((uintptr_t)workspace & 15) == 0) return launch_carry(*p, cl, x, y, n, workspace, s);
+    if (p->flags & SOS_FLAG_CARRY_SCAN) return SOS_E_ARG;   // asked for, but no workspace
   }
   // one solver for every section lets the kernel drop the per-section branch
   return dispatch_rows<LaunchRows>(p->N, p->io_dtype, p->compute_dtype, b0one, solver_mix(*p), q, a, s);

@@ -20,6 +20,9 @@ SOS_OK, SOS_E_ARG, SOS_E_COEF, SOS_E_UNSTABLE, SOS_E_UNSUPPORTED, SOS_E_DEVICE, 
 SOS_F32, SOS_F64, SOS_F16, SOS_BF16 = 0, 1, 2, 3
 SOS_AUTO, SOS_PH, SOS_CR, SOS_PH_DEFERRED, SOS_SCALAR, SOS_BLOCK = 0, 1, 2, 3, 4, 5
 SOS_FLAG_HOST_ONLY = 0x1
+SOS_FLAG_CARRY_SCAN = 0x2
+SOS_FLAG_CARRY_RUNIN = 0x4
+_CARRY = {"auto": 0, "scan": SOS_FLAG_CARRY_SCAN, "runin": SOS_FLAG_CARRY_RUNIN}
 (SOS_TABLE_ROWS, SOS_TABLE_U1, SOS_TABLE_U2, SOS_TABLE_C, SOS_TABLE_PH_POWERS,
  SOS_TABLE_CR_LEVELS, SOS_TABLE_CR_TERMINAL, SOS_TABLE_CR_POWERS, SOS_TABLE_TRANSITION,
  SOS_TABLE_THETA, SOS_TABLE_COUPLING) = range(11)
@@ -143,15 +146,17 @@ class PlanInfo:
 
 
 class Plan:
-    """Owns a sos_plan_t.  sos: [K, 6] rows (b0, b1, b2, a0, a1, a2)."""
+    """Owns a sos_plan_t.  sos: [K, 6] rows (b0, b1, b2, a0, a1, a2).
+    carry: "auto" (the library picks the run-in or the exact scan per call),
+    "scan" or "runin"."""
 
     def __init__(self, sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=0,
-                 tile_groups=0, host_only=False):
+                 tile_groups=0, host_only=False, carry="auto"):
         s = np.ascontiguousarray(np.asarray(sos, dtype=np.float64))
         if s.ndim != 2 or s.shape[1] != 6:
             raise ValueError("sos must be [K, 6]")
         o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), 16,
-                  int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0)
+                  int(tile_groups), (SOS_FLAG_HOST_ONLY if host_only else 0) | _CARRY[carry])
         h = ctypes.c_void_p()
         _check(lib().sos_plan(s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), s.shape[0],
                               ctypes.byref(o), ctypes.byref(h)), "sos_plan")

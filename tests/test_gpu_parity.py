@@ -157,7 +157,7 @@ def test_slow_pole_long_run_in(solver, N, tol):
     r, th = 0.9995, 0.01
     sec = np.array([[1.0, 0.0, 0.0, 1.0, -2 * r * math.cos(th), r * r]])
     x = W.make_signal(2 ** 19, 7, np.float64)
-    y, p = run(sec, x, compute_dtype="f64", solver=solver, N=N, tile_groups=4)
+    y, p = run(sec, x, compute_dtype="f64", solver=solver, N=N, tile_groups=4, carry="runin")
     assert p.info().warm_samples > 4 * 8 * 64
     err = oracle.rel_rms(y, oracle.sosfilt(x, sec))
     print("slow pole %s N=%d rel_rms=%.3e" % (solver, N, err))

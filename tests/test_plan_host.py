@@ -365,3 +365,26 @@ def test_batch_replan_host_only():
         b.replan(_host_plans([2, 2]), [10, 10], offsets=[0, 5])
     assert e.value.code == S.SOS_E_ARG
     assert b.query()["total"] == q["total"]
+
+
+def test_carry_flags():
+    """The carry flags: either one is accepted, both together or an unknown
+    flag is SOS_E_ARG; a host-only plan has no exact carry (no workspace)."""
+    import ctypes
+    sos = np.ascontiguousarray(W.make_sos(2, 0.5, 0.9, 1))
+    ptr = sos.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def rc(flags):
+        h = ctypes.c_void_p()
+        o = S._Opts(S.SOS_F32, S.SOS_F64, S.SOS_AUTO, 32, 16, 0, S.SOS_FLAG_HOST_ONLY | flags)
+        r = S.lib().sos_plan(ptr, 2, ctypes.byref(o), ctypes.byref(h))
+        if r == S.SOS_OK:
+            S.lib().sos_plan_destroy(h)
+        return r
+
+    assert rc(S.SOS_FLAG_CARRY_SCAN) == S.SOS_OK
+    assert rc(S.SOS_FLAG_CARRY_RUNIN) == S.SOS_OK
+    assert rc(S.SOS_FLAG_CARRY_SCAN | S.SOS_FLAG_CARRY_RUNIN) == S.SOS_E_ARG
+    assert rc(0x40) == S.SOS_E_ARG
+    p = S.Plan(W.make_sos(4, 0.9, 0.999, 1), host_only=True, carry="scan")
+    assert p.workspace_size(1 << 20) == 0
