@@ -30,17 +30,18 @@ struct ChanWork {
 // makespan model.  Each candidate cap gives every channel's work items
 // (quads of four equal row tiles, each preceded by its run-in, clamped at
 // the channel start) and their cost in group-sections, K (tile + run-in).
-// The launch then takes about
-//   total / simds + (longest item) * waves_per_simd
-// in SIMD time: the list-scheduling bound for items of one wavefront each,
-// with waves_per_simd of them sharing a SIMD.  Long tiles waste little on
+// In SIMD time, with a = total / simds and b = (longest item) *
+// waves_per_simd, the launch takes between max(a, b) and a + b (the
+// list-scheduling bound for one-wavefront items, waves_per_simd of them
+// sharing a SIMD); the model takes the midpoint.  Long tiles waste little on
 // run-ins; short tiles give more items and a shorter tail.  A channel with
 // a long run-in (poles near the unit circle) needs the short tiles for
-// parallelism even at the cost of run-in many times its tile.
+// parallelism even at the cost of run-in many times its tile.  Ties go to
+// the longer tile.
 int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t waves_per_simd) {
   int64_t best_tg = 8;
   double best = -1.0;
-  for (int e = 0; e <= 12; ++e) {
+  for (int e = 12; e >= 0; --e) {
     const int64_t tg = int64_t(1) << e;
     double total = 0.0, longest = 0.0;
     for (const ChanWork &c : w) {
@@ -52,7 +53,8 @@ int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t
       total += (double)quads * item;
       longest = std::max(longest, item);
     }
-    const double cost = total / (double)std::max<int64_t>(simds, 1) + longest * (double)waves_per_simd;
+    const double a = total / (double)std::max<int64_t>(simds, 1), b = longest * (double)waves_per_simd;
+    const double cost = 0.5 * (std::max(a, b) + a + b);
     if (best < 0.0 || cost < best * 0.999) {
       best = cost;
       best_tg = tg;
