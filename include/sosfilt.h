@@ -148,10 +148,11 @@ typedef struct {
  * solver      host [K] or NULL: per section SOS_PH or SOS_CR as run. */
 sos_status sos_plan_query(sos_plan_t plan, sos_plan_info *info, int32_t *solver);
 
-/* Samples per tile that sos_filt uses for n samples: the plan's tile_groups,
- * or the launch-shape model: the shortest tile that gives every SIMD at most
- * m wavefronts (four tiles each), m the largest power of two of resident
- * wavefronts per SIMD for the plan's kernel. */
+/* Samples per tile that sos_filt's run-in carry uses for n samples: the
+ * plan's tile_groups, or the launch-shape model: the shortest tile that
+ * gives every SIMD at most m wavefronts (four tiles each), m the largest
+ * power of two of resident wavefronts per SIMD for the plan's kernel.  The
+ * exact carry (see sos_workspace_size) uses the same model with no run-in. */
 int64_t sos_plan_tile(sos_plan_t plan, int64_t n);
 
 /* Host FP64 tables, for inspection and tests.  Copies min(count, size) values
@@ -233,7 +234,9 @@ sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
  *          three samples (FP64: one) earlier, read as zeros and never
  *          stored, so that its groups move as 16-byte vectors.
  * opts     host, may be NULL: tile_groups > 0 caps the groups per tile
- *          (0 = chosen from the total length); flags SOS_FLAG_HOST_ONLY
+ *          (0 = chosen by a makespan model over candidate caps from every
+ *          channel's length, run-in and K, and the kernel's residency);
+ *          flags SOS_FLAG_HOST_ONLY
  *          builds the schedule without device memory (queries only, and
  *          host-only plans are then accepted); max_channels and
  *          max_samples reserve room for later sos_batch_replan calls of up
