@@ -330,6 +330,47 @@ def bench_draws(S, W, torch, dev, args):
     return out
 
 
+def bench_tiny(S, W, torch, dev, args):
+    """The small workload (2^16 float64 samples, K = 8, r in [0.5, 0.95],
+    seed 0): cache-resident, so a latency.  Per plan, the median of 50
+    single calls each between its own events (launch included), the rate of
+    50 back-to-back calls, and the relative RMS against the oracle."""
+    c = W.CONFIGS["tiny"]
+    sos = W.make_sos(c.K, c.r_lo, c.r_hi, c.seed)
+    x_np = W.make_signal(c.n, c.seed, np.float64)
+    xt = torch.from_numpy(x_np).to(dev)
+    y = torch.empty_like(xt)
+    ref = None
+    if not args.no_cpu:
+        import oracle
+        ref = oracle.sosfilt(x_np, sos)
+    out = {"n": c.n, "rows": []}
+    for solver, N in (("ph", 8), ("cr", 8), ("ph", 16), ("ph", 32), ("cr", 32)):
+        plan = S.Plan(sos, io_dtype="f64", compute_dtype="f64", solver=solver, N=N)
+        S.filt(plan, xt, y)
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(50):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            S.filt(plan, xt, y)
+            e1.record()
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1) * 1e3)
+        sec = timed(torch, lambda: S.filt(plan, xt, y), 50)
+        row = {"solver": solver, "N": N, "latency_us_median": float(np.median(lat)),
+               "back_to_back_us": sec * 1e6, "GSps": c.n / sec / 1e9}
+        if ref is not None:
+            import oracle
+            row["rel_rms"] = oracle.rel_rms(y.cpu().numpy(), ref)
+        out["rows"].append(row)
+        log("tiny %s N=%2d: latency median %.1f us, back-to-back %.1f us (%.1f GS/s)%s"
+            % (solver, N, row["latency_us_median"], row["back_to_back_us"], row["GSps"],
+               ", rel_rms %.2e" % row["rel_rms"] if "rel_rms" in row else ""))
+    return out
+
+
 def bench_carry(S, W, torch, dev, args):
     """Single signals whose run-in is long against the tile the device needs
     (K = 8, pole radius U[0.9, 0.999], seed 3, float32 I/O, FP64 arithmetic,
@@ -469,6 +510,8 @@ def main():
                     help="also report the error per arithmetic type on the precision workload")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the plain copy of the signal (counter calibration)")
+    ap.add_argument("--tiny", action="store_true",
+                    help="also the small FP64 workload's latency")
     ap.add_argument("--carry", action="store_true",
                     help="also the run-in against the exact scan carry on long-run-in single signals")
     ap.add_argument("--draws", action="store_true",
@@ -569,6 +612,8 @@ def main():
         extra["draws"] = bench_draws(S, W, torch, dev, args)
     if args.carry:
         extra["carry"] = bench_carry(S, W, torch, dev, args)
+    if args.tiny:
+        extra["tiny"] = bench_tiny(S, W, torch, dev, args)
 
     cpu = None
     comparator = None
