@@ -1,0 +1,65 @@
+"""Seeded random sweep over the configuration space of sos_filt: K, N, I/O
+dtype, solver, carry (run-in or exact scan), length and pole range, each
+case against the FP64 oracle (FP64 I/O: against the extended-precision
+oracle, within 1e-12 or four times the FP64 oracle's own error; FP32 I/O:
+1e-6), and the same cases through a one-channel batch where the plan allows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_14054_amd import sosfilt as S
+from paper_2607_14054_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+RNG = np.random.default_rng(2024)
+CASES = []
+for i in range(40):
+    K = int(RNG.integers(1, 17))
+    N = int(RNG.choice([8, 16, 32, 64]))
+    io = str(RNG.choice(["f32", "f64"]))
+    solver = str(RNG.choice(["auto", "ph", "cr"]))
+    carry = str(RNG.choice(["auto", "runin", "scan"]))
+    n = int(np.floor(2.0 ** RNG.uniform(0, 17)))
+    r_hi = float(RNG.choice([0.9, 0.98, 0.995]))
+    CASES.append((i, K, N, io, solver, carry, n, r_hi))
+
+
+def check(y, x, sos, io, tag):
+    if io == "f32":
+        err = oracle.rel_rms(y, oracle.sosfilt(x, sos))
+        assert err < 1e-6, (tag, err)
+        return
+    ld = oracle.sosfilt_ld(x, sos)
+    err, own = oracle.rel_rms(y, ld), oracle.rel_rms(oracle.sosfilt(x, sos), ld)
+    assert err <= max(1e-12, 4 * own), (tag, err, own)
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "c%02d-K%d-N%d-%s-%s-%s-n%d-r%g" % c)
+def test_random_config(case):
+    i, K, N, io, solver, carry, n, r_hi = case
+    sos = W.make_sos(K, 0.5, r_hi, 5000 + i)
+    dt = np.float64 if io == "f64" else np.float32
+    x = W.make_signal(n, 6000 + i, dt)
+    p = S.Plan(sos, io_dtype=io, compute_dtype="f64", solver=solver, N=N, carry=carry)
+    y = S.filt(p, torch.from_numpy(x).to(DEV))
+    torch.cuda.synchronize()
+    check(y.cpu().numpy(), x, sos, io, "single")
+    # the same channel, at an odd offset, in a batch with a short neighbour
+    # (batches carry by the run-in whatever the plan's carry flag)
+    q = S.Plan(W.make_sos(2, 0.5, 0.9, 7000 + i), io_dtype=io, compute_dtype="f64", solver=solver, N=N)
+    x2 = W.make_signal(37, 7100 + i, dt)
+    b = S.Batch([q, p], [37, n])
+    xb = np.zeros(b.total, dt)
+    xb[b.offsets[0]:b.offsets[0] + 37] = x2
+    xb[b.offsets[1]:b.offsets[1] + n] = x
+    yb = S.filt_batched(b, torch.from_numpy(xb).to(DEV))
+    torch.cuda.synchronize()
+    yb = yb.cpu().numpy()
+    check(yb[b.offsets[1]:b.offsets[1] + n], x, sos, io, "batched")
+    check(yb[b.offsets[0]:b.offsets[0] + 37], x2, W.make_sos(2, 0.5, 0.9, 7000 + i), io, "neighbour")
