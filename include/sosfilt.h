@@ -187,8 +187,10 @@ sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
  * end state c_t and once from the scanned true state, with a log-depth scan
  * S_t = c_t + Phi^T S_{t-1} in between (Phi the cascade's one-step state
  * transition).  sos_filt takes it when the run-in would be longer than 1.2
- * tiles (a signal short against its run-in, poles near the unit circle), or
- * always with SOS_FLAG_CARRY_SCAN; never with SOS_FLAG_CARRY_RUNIN.
+ * tiles (a signal short against its run-in, poles near the unit circle) and
+ * the run-in it saves, K (W - tile) section-samples, is at least 8192 (below
+ * that the scan's extra launches cost more), or always with
+ * SOS_FLAG_CARRY_SCAN; never with SOS_FLAG_CARRY_RUNIN.
  */
 size_t sos_workspace_size(sos_plan_t plan, int64_t n);
 

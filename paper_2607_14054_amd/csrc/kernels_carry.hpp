@@ -135,4 +135,73 @@ __global__ __launch_bounds__(256) void carry_scan_kernel(const double *__restric
   out[idx] = v;
 }
 
+// The powers and every scan round in one workgroup, when all tile states
+// fit in LDS (ntiles * D <= kCarryOneBlock): the states and the powers live
+// in LDS; each round reads all it needs before any thread writes.  The
+// powers are kept transposed, so that the lanes of a round, which hold
+// consecutive rows of a state, read consecutive words of a power's column.
+// Dynamic LDS: (ntiles * D + 2 D^2) doubles.
+constexpr int kCarryOneBlock = 8192;
+
+__global__ __launch_bounds__(1024) void carry_scan_one_block_kernel(const double *__restrict__ phi, int D,
+                                                                    int64_t T, int rounds, int ntiles,
+                                                                    const double *__restrict__ in,
+                                                                    double *__restrict__ out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  double *S = reinterpret_cast<double *>(smem);
+  const int E = ntiles * D;
+  double *baseT = S + E, *accT = baseT + D * D;   // transposes of Phi^(2^b) and of the running power
+  const int tid = threadIdx.x;
+  const bool on = tid < D * D;
+  const int i = on ? tid / D : 0, j = on ? tid % D : 0;
+  for (int e = tid; e < E; e += 1024) S[e] = in[e];
+  if (on) {
+    baseT[tid] = phi[j * D + i];
+    accT[tid] = i == j ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // dst = a b, every thread reading before any writes
+  auto mul_into = [&](double *dst, const double *a, const double *b) {
+    double v = 0.0;
+    if (on)
+      for (int l = 0; l < D; ++l) v = __builtin_fma(a[i * D + l], b[l * D + j], v);
+    __syncthreads();
+    if (on) dst[tid] = v;
+    __syncthreads();
+  };
+  // (acc base)^T = base^T acc^T, (base base)^T = base^T base^T
+  for (int64_t e = T; e > 0; e >>= 1) {
+    if (e & 1) mul_into(accT, baseT, accT);
+    if (e > 1) mul_into(baseT, baseT, baseT);
+  }
+  constexpr int kPer = kCarryOneBlock / 1024;   // states per thread
+  for (int r = 0; r < rounds; ++r) {
+    const int off = 1 << r;
+    double v[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * 1024;
+      v[k] = 0.0;
+      if (e < E) {
+        const int t = e / D, row = e - t * D;
+        double a = S[e];
+        if (t >= off) {
+          const double *src = S + (t - off) * D;
+          for (int l = 0; l < D; ++l) a = __builtin_fma(accT[l * D + row], src[l], a);
+        }
+        v[k] = a;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = tid + k * 1024;
+      if (e < E) S[e] = v[k];
+    }
+    __syncthreads();
+    if (r + 1 < rounds) mul_into(accT, accT, accT);
+  }
+  for (int e = tid; e < E; e += 1024) out[e] = S[e];
+}
+
 }  // namespace sosf

@@ -50,6 +50,8 @@ int mix_of(const sos_plan_s &p) {
 
 namespace sosf {
 
+constexpr int64_t kCarryMinSaving = 8192;   // section-samples of run-in per row
+
 bool carry_supported(const sos_plan_s &p) {
   return p.compute_dtype == SOS_F64 &&
          (p.solver_opt == SOS_AUTO || p.solver_opt == SOS_PH || p.solver_opt == SOS_CR) &&
@@ -60,8 +62,13 @@ CarryLayout carry_layout(const sos_plan_s &p, int64_t n, int64_t runin_tile) {
   CarryLayout l;
   if (n <= 0 || !p.d_phi || !carry_supported(p) || (p.flags & SOS_FLAG_CARRY_RUNIN)) return l;
   // automatic choice: the scan when the run-in would more than double the
-  // work of the tiles the run-in launch uses (two passes plus the scan)
-  if (!(p.flags & SOS_FLAG_CARRY_SCAN) && 5 * p.warm <= 6 * runin_tile) return l;
+  // work of the tiles the run-in launch uses (two passes plus the scan),
+  // and the run-in it saves, K (W - T) section-samples, outweighs the
+  // scan's extra launches (measured: about 8192 section-samples of a
+  // row's serial work)
+  if (!(p.flags & SOS_FLAG_CARRY_SCAN) &&
+      (5 * p.warm <= 6 * runin_tile || (int64_t)p.K * (p.warm - runin_tile) < kCarryMinSaving))
+    return l;
   const int64_t G = (int64_t)p.N * kL;
   Residency r;
   r.simds = p.simds;
@@ -105,7 +112,14 @@ sos_status launch_carry(const sos_plan_s &p, const CarryLayout &l, const void *x
   if (st != SOS_OK) return st;
   // 2. S_t = c_t + Phi^T S_{t-1}, in log-depth rounds
   double *in = aggs, *out = buf;
-  if (l.rounds > 0) {
+  if (l.rounds > 0 && l.ntiles * D <= kCarryOneBlock) {
+    // every state in one workgroup's LDS: powers and rounds in one launch
+    const size_t lds = ((size_t)l.ntiles * D + 2 * (size_t)D * D) * sizeof(double);
+    hipLaunchKernelGGL(carry_scan_one_block_kernel, dim3(1), dim3(1024), lds, s,
+                       static_cast<const double *>(p.d_phi), D, l.tile, l.rounds, (int)l.ntiles, in, out);
+    if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
+    std::swap(in, out);
+  } else if (l.rounds > 0) {
     hipLaunchKernelGGL(carry_powers_kernel, dim3(1), dim3(1024), 0, s, static_cast<const double *>(p.d_phi), D,
                        l.tile, l.rounds, P);
     if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;

@@ -51,8 +51,10 @@ def test_scan_carry_long_run_in(io, N, K):
     n = 3 * 2 ** 17 + 77
     x = W.make_signal(n, 301, dt)
     p = S.Plan(sos, io_dtype=io, compute_dtype="f64", N=N)
-    # the automatic choice: the scan where the run-in exceeds 1.2 tiles
-    assert (p.workspace_size(n) > 0) == (5 * p.info().warm_samples > 6 * p.tile(n))
+    # the automatic choice: the scan where the run-in exceeds 1.2 tiles and
+    # saves at least 8192 section-samples
+    w, t = p.info().warm_samples, p.tile(n)
+    assert (p.workspace_size(n) > 0) == (5 * w > 6 * t and K * (w - t) >= 8192)
     check(filt(p, x), x, sos, io)
     ps = S.Plan(sos, io_dtype=io, compute_dtype="f64", N=N, carry="scan")
     assert ps.workspace_size(n) > 0
@@ -134,7 +136,7 @@ def test_scan_carry_without_workspace():
     """NULL workspace: the automatic choice falls back to the run-in (same
     result to rounding); a plan that asks for the scan gets SOS_E_ARG."""
     lib = S.lib()
-    sos = W.make_sos(4, 0.9, 0.999, 307)
+    sos = W.make_sos(8, 0.95, 0.999, 307)
     n = 2 ** 18
     x_np = W.make_signal(n, 308, np.float64)
     x = torch.from_numpy(x_np).to(DEV)
@@ -157,7 +159,7 @@ def test_scan_carry_graph_replays_match_eager():
     lib = S.lib()
     sos = W.make_sos(6, 0.9, 0.999, 309)
     n = 2 ** 18 + 33
-    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", N=32)
+    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", N=32, carry="scan")
     ws = p.workspace_size(n)
     assert ws > 0
     wsb = torch.empty(ws, dtype=torch.uint8, device=DEV)
