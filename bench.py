@@ -172,55 +172,69 @@ def bench_grad(S, W, torch, dev, args):
     """The adjoint workload: 64 channels x 2^18 float32 samples, K = 8,
     r in [0.5, 0.95], loss sum(y * g) with g ~ N(0, 1) (seed + 2); channel c
     drawn with seed c.  One step is the batched forward (sos_filt_batched)
-    and the batched adjoint (sos_filt_backward_batched) of all channels.  A
-    sample of channels is checked against the oracle adjoint."""
+    and the batched adjoint (sos_filt_backward_batched) of all channels, in
+    the automatic adjoint mode (recompute from group checkpoints at K = 8)
+    and, for comparison, with every section output saved.  A sample of
+    channels is checked against the oracle adjoint."""
     cfg = W.CONFIGS["grad"]
     C, n = cfg.channels, cfg.n
     sos = [W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed + c) for c in range(C)]
-    plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver="auto", N=64) for s_ in sos]
-    b = S.Batch(plans, [n] * C)
-    xb = torch.empty(b.total, dtype=torch.float32, device=dev)
+    xb = torch.empty(C * n, dtype=torch.float32, device=dev)
     gb = torch.empty_like(xb)
     for c in range(C):
         xb[c * n:(c + 1) * n] = torch.from_numpy(W.make_signal(n, cfg.seed + c, np.float32)).to(dev)
         gb[c * n:(c + 1) * n] = torch.from_numpy(W.grad_seed_signal(n, cfg.seed + c, np.float32)).to(dev)
     yb = torch.empty_like(xb)
     gx = torch.empty_like(xb)
-
-    def one_pass():
-        S.filt_batched(b, xb, yb)
-        return S.filt_backward_batched(b, xb, gb, gx)
-
-    _, gsos, first = one_pass()
-    torch.cuda.synchronize()
-    steps = max(3, args.steps // 2)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        one_pass()
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / steps
     total = C * n
-    out = {"channels": C, "samples": total, "K": cfg.K, "ms": sec * 1e3, "GSps": total / sec / 1e9}
-    log("grad: %d x %d batched forward+backward %.3f ms  %.1f GS/s" % (C, n, sec * 1e3, total / sec / 1e9))
-    if not args.no_cpu:
-        import oracle
-        _, gsos, first = one_pass()
+    out = {"channels": C, "samples": total, "K": cfg.K}
+    for mode in ("auto", "save"):
+        plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver="auto", N=64, adjoint=mode)
+                 for s_ in sos]
+        b = S.Batch(plans, [n] * C)
+        assert b.total == total
+
+        def one_pass():
+            S.filt_batched(b, xb, yb)
+            return S.filt_backward_batched(b, xb, gb, gx)
+
+        one_pass()
         torch.cuda.synchronize()
-        g_all = gsos.cpu().numpy()
-        worst_x, worst_s = 0.0, 0.0
-        for c in (0, C // 2, C - 1):
-            x64 = xb[c * n:(c + 1) * n].cpu().numpy().astype(np.float64)
-            g64 = gb[c * n:(c + 1) * n].cpu().numpy().astype(np.float64)
-            rx, rs = oracle.sosfilt_backward(x64, sos[c], g64)
-            worst_x = max(worst_x, oracle.rel_rms(gx[c * n:(c + 1) * n].cpu().numpy(), rx))
-            g = g_all[first[c]:first[c] + cfg.K]
-            worst_s = max(worst_s, float(np.max(np.abs(g - rs) / np.max(np.abs(rs), axis=1, keepdims=True))))
-        out["gx_rel_rms_max"] = worst_x
-        out["gsos_row_err_max"] = worst_s
-        log("grad: sampled channels gx rel_rms %.2e, gsos row err %.2e" % (worst_x, worst_s))
+        steps = max(3, args.steps // 2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            one_pass()
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / steps
+        row = {"ms": sec * 1e3, "GSps": total / sec / 1e9}
+        log("grad (%s): %d x %d batched forward+backward %.3f ms  %.1f GS/s"
+            % (mode, C, n, sec * 1e3, total / sec / 1e9))
+        if not args.no_cpu:
+            import oracle
+            _, gsos, first = one_pass()
+            torch.cuda.synchronize()
+            g_all = gsos.cpu().numpy()
+            worst_x, worst_s = 0.0, 0.0
+            for c in (0, C // 2, C - 1):
+                x64 = xb[c * n:(c + 1) * n].cpu().numpy().astype(np.float64)
+                g64 = gb[c * n:(c + 1) * n].cpu().numpy().astype(np.float64)
+                rx, rs = oracle.sosfilt_backward(x64, sos[c], g64)
+                worst_x = max(worst_x, oracle.rel_rms(gx[c * n:(c + 1) * n].cpu().numpy(), rx))
+                g = g_all[first[c]:first[c] + cfg.K]
+                worst_s = max(worst_s, float(np.max(np.abs(g - rs) / np.max(np.abs(rs), axis=1, keepdims=True))))
+            row["gx_rel_rms_max"] = worst_x
+            row["gsos_row_err_max"] = worst_s
+            log("grad (%s): sampled channels gx rel_rms %.2e, gsos row err %.2e" % (mode, worst_x, worst_s))
+        if mode == "auto":
+            out.update(row)
+        else:
+            out["saved_outputs"] = row
+        b.close()
+        for p_ in plans:
+            p_.close()
     return out
 
 
@@ -281,26 +295,35 @@ def bench_stream(S, W, torch, dev, args):
 
 def bench_grad_long(S, W, torch, dev, args):
     """The adjoint on one long channel: 2^26 float32 samples, K = 8,
-    r in [0.5, 0.95]; one sos_filt_backward per step."""
+    r in [0.5, 0.95]; one sos_filt_backward per step, in the automatic mode
+    (recompute) and with saved outputs."""
     n = 1 << 26
     sos = W.make_sos(8, 0.5, 0.95, 0)
     x = torch.from_numpy(W.make_signal(n, 0, np.float32)).to(dev)
     g = torch.from_numpy(W.grad_seed_signal(n, 0, np.float32)).to(dev)
-    plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=64)
     gx = torch.empty_like(x)
-    S.filt_backward(plan, x, g, gx)
-    torch.cuda.synchronize()
-    steps = max(3, args.steps // 4)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
+    out = {"samples": n}
+    for mode in ("auto", "save"):
+        plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=64, adjoint=mode)
         S.filt_backward(plan, x, g, gx)
-    e1.record()
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3 / steps
-    log("grad-long: 2^26 backward %.3f ms  %.1f GS/s" % (sec * 1e3, n / sec / 1e9))
-    return {"samples": n, "ms": sec * 1e3, "GSps": n / sec / 1e9}
+        torch.cuda.synchronize()
+        steps = max(3, args.steps // 4)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            S.filt_backward(plan, x, g, gx)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / steps
+        log("grad-long (%s): 2^26 backward %.3f ms  %.1f GS/s" % (mode, sec * 1e3, n / sec / 1e9))
+        row = {"ms": sec * 1e3, "GSps": n / sec / 1e9}
+        if mode == "auto":
+            out.update(row)
+        else:
+            out["saved_outputs"] = row
+        plan.close()
+    return out
 
 
 def bench_draws(S, W, torch, dev, args):

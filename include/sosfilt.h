@@ -89,6 +89,11 @@ typedef enum {
                                      sos_workspace_size) */
 #define SOS_FLAG_CARRY_RUNIN 0x4u /* always carry by the run-in (not with
                                      SOS_FLAG_CARRY_SCAN) */
+#define SOS_FLAG_ADJ_SAVE 0x8u    /* adjoint: keep every section's output (see
+                                     sos_backward_workspace_size) */
+#define SOS_FLAG_ADJ_RECOMPUTE 0x10u /* adjoint: checkpoint the cascade state
+                                     per group and recompute section inputs
+                                     (not with SOS_FLAG_ADJ_SAVE) */
 
 typedef struct {
     int32_t io_dtype;       /* sos_dtype of x and y (default SOS_F32) */
@@ -314,9 +319,22 @@ sos_status sos_filt_batched(sos_batch_t batch, const void *x, void *y, void *wor
  * transposed filters run backwards in time, so the kernels take the groups
  * in reversed time and reuse the PH solve of Section VI-B for A^{-T}.
  *
+ * Two modes, fixed by the plan (SOS_FLAG_ADJ_SAVE, SOS_FLAG_ADJ_RECOMPUTE, or
+ * by cost when neither is set):
+ *  - saved outputs: the forward pass stores every section's output (FP64,
+ *    K n samples) and the adjoint reads them back;
+ *  - recompute: the forward pass stores the cascade state (2K + 2 values)
+ *    at every group of 256 samples, and the adjoint recomputes section k's
+ *    input from the group's state (K(K-1)/2 + 1 forward section passes per
+ *    group).
+ * Measured costs per sample on MI355X are 3.74 + 4.00 K ps (saved) and
+ * 4.48 + 1.36 K + 0.38 (K(K-1)/2 + 1) ps (recompute), so without a flag a
+ * plan recomputes for K <= 14.
+ *
  * sos_backward_workspace_size -- device bytes sos_filt_backward needs for n
- * samples: every section's output (FP64, K n samples, padded) and the
- * per-tile partial sums.  0 for a host-only plan.
+ * samples: the saved outputs (K n doubles, padded) or the group states
+ * ((2K + 2) doubles per 256 samples), and the per-tile partial sums.  0 for
+ * a host-only plan.
  */
 size_t sos_backward_workspace_size(sos_plan_t plan, int64_t n);
 
@@ -333,8 +351,8 @@ size_t sos_backward_workspace_size(sos_plan_t plan, int64_t n);
  *            aligned; its contents on entry do not matter.
  * The adjoint always runs PH with FP64 arithmetic at N = 16, whatever the
  * plan's solver, N and compute dtype (the same cascade, exact to rounding).
- * It first re-runs the forward pass to save every section's output, so the
- * caller's forward result is not needed.  Sums over the signal are formed
+ * It first re-runs the forward pass (saving section outputs or group
+ * states, as above), so the caller's forward result is not needed.  Sums over the signal are formed
  * per tile and added in a fixed order: results are deterministic.
  */
 sos_status sos_filt_backward(sos_plan_t plan, const void *x, const void *gy, void *gx,
@@ -342,8 +360,11 @@ sos_status sos_filt_backward(sos_plan_t plan, const void *x, const void *gy, voi
 
 /*
  * Batched adjoint: sos_filt_backward for every channel of a device batch in
- * three launches (the forward pass that saves the section outputs, the
- * reversed-time adjoint, the reduction of the coefficient sums).
+ * three launches (the forward pass that saves the section outputs or the
+ * group states, the reversed-time adjoint, the reduction of the coefficient
+ * sums).  One mode for the whole batch: saved outputs if any channel's plan
+ * has SOS_FLAG_ADJ_SAVE, else recompute if any has SOS_FLAG_ADJ_RECOMPUTE,
+ * else the cheaper by the costs above summed over the channels' samples.
  *
  * sos_batch_backward_workspace_size -- device bytes of the workspace (0 if
  * the batch has no adjoint: host-only batches).

@@ -12,9 +12,18 @@
 // B_k.  The sums become sum_t mu_r[t - j] u_r[t], lags of mu that the FIR
 // already reads, so they are fused into it.
 //
-// Two kernels: a forward PH pass that writes every section's output w_k
-// (true scale) to the workspace, and the reversed-time adjoint pass that
-// reads them back one section at a time.
+// Two kernels, in one of two modes:
+//  * saved outputs: a forward PH pass writes every section's output w_k
+//    (true scale, FP64) to the workspace, and the reversed-time adjoint pass
+//    reads them back one section at a time (about 16K bytes per sample
+//    written and read back);
+//  * recompute: the forward pass writes only the cascade state at every
+//    group boundary (2K + 2 values per group, aligned with the adjoint's
+//    reversed-time groups), and the adjoint pass recomputes the section
+//    inputs of each group from its checkpoint, in registers: section k's
+//    input takes k forward sections, so a group costs K(K-1)/2 + 1 forward
+//    section passes on top of the adjoint's own work, and no per-section
+//    traffic.
 #pragma once
 
 #include "kernels.hpp"
@@ -99,6 +108,16 @@ __device__ __forceinline__ void store_group_rev(const T (&X)[N], TI *__restrict_
   __builtin_amdgcn_wave_barrier();
 }
 
+// A forward-time group in registers (lane l holds samples lN .. lN + N - 1
+// of the row's group) into the reversed-time layout of the same samples,
+// out of place: lane 15 - l's run, in reverse order (DPP row_mirror moves
+// lane 15 - l's value into lane l).
+template <int N>
+__device__ __forceinline__ void to_reversed(double (&R)[N], const double (&F)[N]) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) R[m] = dpp<0x140, false>(F[N - 1 - m]);
+}
+
 // All-pole part of a section by PH (Section VI-B with b = (1, 0, 0)): X := (1/A) X
 // on the group, ys = (y[-2], y[-1]) of the output, replaced by the group's
 // last two outputs.
@@ -130,13 +149,20 @@ struct BwdArgs {
   int64_t n, np;            // samples; n rounded up to the vector width
   int64_t tile, warm, ntiles;
   int64_t sstride;          // elements between saved section outputs
+  int64_t shift;            // forward tiles cover [-shift, n)
+  int64_t nck;              // recompute mode: group checkpoints
   int32_t K, stride;
 };
 
-// Forward pass of one row's tile that saves w_k (true scale, FP64) of every
-// section k to saved + k * sstride.  PH, FP64 arithmetic, tiles as in
-// filter_rows.  st: 2 + 2K boundary values; rowbuf: one FP64 group.
-template <int N, typename TI, bool B0ONE>
+// Forward pass of one row's tile.  Saved-output mode: writes w_k (true
+// scale, FP64) of every section k to saved + k * sstride.  Recompute mode
+// (RC): writes, before each of its groups, the row's boundary values (the
+// state the cascade enters the group with) as checkpoint j = (np - g)/G - 1,
+// the reversed-time group that covers the same samples; the tiles start
+// where the groups line up with the reversed-time ones (shift = -np mod G).
+// PH, FP64 arithmetic, tiles as in filter_rows.  st: 2 + 2K boundary values;
+// rowbuf: one FP64 group.
+template <int N, typename TI, bool B0ONE, bool RC>
 __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__restrict__ saved,
                                           ctab<double> ct, ctab<double> cb, const AdjView &v,
                                           int64_t tile_index, bool aligned, double *st,
@@ -144,27 +170,34 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
   typedef double T;
   TI *buf = reinterpret_cast<TI *>(rowbuf);
   double *dbuf = reinterpret_cast<double *>(rowbuf);
-  for (int i = 0; i < state_elems(v.K); ++i) st[i] = T(0);
+  const int SE = state_elems(v.K);
+  for (int i = 0; i < SE; ++i) st[i] = T(0);
   const int64_t G = (int64_t)N * kL;
   // tiles over [-shift, n): groups start where x + g is 16-byte aligned (the
   // samples before 0 read as zeros); the saved arrays start shift elements
   // in, so that their groups are aligned too
   const int64_t t0 = tile_index * v.tile - v.shift;
-  saved += v.shift;
+  if (!RC) saved += v.shift;
   const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
   T X[N];
   for (int64_t it = 0; it < steps; ++it) {
     const int64_t g = t0 - v.warm + it * G;
     const bool full = aligned && __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= v.n)) == 0;
     const bool live = it >= warm_groups;
+    if (RC && live) {
+      const int64_t j = (v.np - g) / G - 1;   // g = np mod G: exact
+      if (j >= 0 && j < v.nck)
+        for (int i = row_lane(); i < SE; i += kL) saved[j * SE + i] = st[i];
+    }
     load_group<N, TI, T>(X, x, g, v.n, full, buf);
     T xs2 = st[0], xs1 = st[1];
     st[0] = last_of_row(X[N - 2]);
     st[1] = last_of_row(X[N - 1]);
     for (int k = 0; k < v.K; ++k) {
       ph_section<N, T, B0ONE>(X, ct + (int64_t)k * v.stride, xs2, xs1, st + 2 + 2 * k);
-      if (live) store_group<N, double, T>(X, saved + (int64_t)k * v.sstride, g, v.n, full,
-                                          cb[kBwdRow * k + BW_SCALE], dbuf);
+      if (!RC && live)
+        store_group<N, double, T>(X, saved + (int64_t)k * v.sstride, g, v.n, full, cb[kBwdRow * k + BW_SCALE],
+                                  dbuf);
     }
   }
 }
@@ -174,8 +207,15 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
 // section k, lambda = B_k mu; the group's final lambda is r(dL/dx).  The
 // tile's sums go to sums[k][0..4]: sum mu[t] u[t], mu[t-1] u[t],
 // mu[t-2] u[t], mu[t-1] w[t], mu[t-2] w[t] (reversed time, t over the tile).
-// st: 7K values (2K all-pole output states, then 5K running sums).
-template <int N, typename TI>
+// u = u_k and w = w_k come from the saved outputs, or (RC) from the group's
+// checkpoint: the group's input in forward time through sections 0 .. k-1
+// (and k, for w_{K-1}), then mirrored into reversed time; those values are
+// in the kernels' scaled domain, so the sums take the cumulative b0 scales
+// once per group.  Since w_k = u_{k+1}, two arrays take the roles of u and w
+// in turn (no copies between steps).
+// st: 7K values (2K all-pole output states, then 5K running sums); RC adds
+// the group's checkpoint and a working copy of it (2 + 2K each).
+template <int N, typename TI, bool B0ONE, bool RC>
 __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__restrict__ gx,
                                              const TI *__restrict__ x, const double *__restrict__ saved,
                                              ctab<double> ct, ctab<double> cb, double *__restrict__ sums,
@@ -185,66 +225,125 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   TI *buf = reinterpret_cast<TI *>(rowbuf);
   double *dbuf = reinterpret_cast<double *>(rowbuf);
   T *acc = st + 2 * v.K;
+  const int SE = state_elems(v.K);
+  T *ck = st + 7 * v.K, *cw = ck + SE;   // RC: checkpoint, working copy
   for (int i = 0; i < 7 * v.K; ++i) st[i] = T(0);
-  saved += v.shift;   // the saved arrays' origin, as written by save_rows
+  if (!RC) saved += v.shift;   // the saved arrays' origin, as written by save_rows
   const int64_t G = (int64_t)N * kL;
   const int64_t t0 = tile_index * v.tile;
   const int64_t pad = v.np - v.n;
   const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
-  T X[N], U[N], Wk[N];
-  for (int64_t it = 0; it < steps; ++it) {
-    const int64_t g = t0 - v.warm + it * G;
-    const bool full = aligned && __builtin_amdgcn_ballot_w64(!(g >= pad && g + G <= v.np)) == 0;
-    const bool live = it >= warm_groups;   // uniform per wave
-    load_group_rev<N, TI, T>(X, gy, g, v.n, v.np, full, buf);
-    if (live)
-      load_group_rev<N, double, T>(Wk, saved + (int64_t)(v.K - 1) * v.sstride, g, v.n, v.np, full, dbuf);
-    for (int k = v.K - 1; k >= 0; --k) {
-      const ctab<T> c = ct + (int64_t)k * v.stride;
-      const ctab<T> b = cb + kBwdRow * k;
-      T *ys = st + 2 * k;
-      const T old2 = ys[0], old1 = ys[1];
-      allpole_ph<N>(X, c, ys);                                 // X = mu_k
-      const T m1 = shift_r(X[N - 1], old1), m2 = shift_r(X[N - 2], old2);
-      const T b0 = b[BW_B0], b1 = b[BW_B1], b2 = b[BW_B2];
-      if (live) {
-        if (k == 0)
-          load_group_rev<N, TI, T>(U, x, g, v.n, v.np, full, buf);
-        else
-          load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * v.sstride, g, v.n, v.np, full, dbuf);
-        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0), s4 = T(0);
+  T X[N], A[N], B[N], F[N];
+  int64_t g = 0;
+  bool full = false, live = false;
+
+  // RC: F = the group's forward-time input through sections 0 .. upto-1
+  // (from the checkpoint); the chain's input state is left in xs2, xs1
+  T xs2 = T(0), xs1 = T(0);
+  auto forward = [&](int upto) {
+    stage_to_regs<N, TI, T>(F, buf);
+    for (int i = row_lane(); i < SE; i += kL) cw[i] = ck[i];
+    __builtin_amdgcn_wave_barrier();
+    xs2 = cw[0];
+    xs1 = cw[1];
+    for (int q = 0; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
+  };
+  // U = u_k in reversed time
+  auto input_of = [&](int k, T (&U)[N]) {
+    if (RC) {
+      forward(k);
+      to_reversed<N>(U, F);
+      __builtin_amdgcn_wave_barrier();
+    } else if (k == 0) {
+      load_group_rev<N, TI, T>(U, x, g, v.n, v.np, full, buf);
+    } else {
+      load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * v.sstride, g, v.n, v.np, full, dbuf);
+    }
+  };
+  // the adjoint of section k on X, with U = u_k, W = w_k
+  auto step = [&](int k, const T (&U)[N], const T (&W)[N]) {
+    const ctab<T> c = ct + (int64_t)k * v.stride;
+    const ctab<T> b = cb + kBwdRow * k;
+    T *ys = st + 2 * k;
+    const T old2 = ys[0], old1 = ys[1];
+    allpole_ph<N>(X, c, ys);                                 // X = mu_k
+    const T m1 = shift_r(X[N - 1], old1), m2 = shift_r(X[N - 2], old2);
+    const T b0 = b[BW_B0], b1 = b[BW_B1], b2 = b[BW_B2];
+    if (live) {
+      T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0), s4 = T(0);
 #pragma unroll
-        for (int m = N - 1; m >= 0; --m) {
-          const T p1 = m >= 1 ? X[m - 1] : m1;
-          const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? m1 : m2);
-          s0 = fma_(X[m], U[m], s0);
-          s1 = fma_(p1, U[m], s1);
-          s2 = fma_(p2, U[m], s2);
-          s3 = fma_(p1, Wk[m], s3);
-          s4 = fma_(p2, Wk[m], s4);
-          X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
-        }
-        s0 = row_sum(s0);
-        s1 = row_sum(s1);
-        s2 = row_sum(s2);
-        s3 = row_sum(s3);
-        s4 = row_sum(s4);
-        T *ak = acc + 5 * k;
-        ak[0] += s0;
-        ak[1] += s1;
-        ak[2] += s2;
-        ak[3] += s3;
-        ak[4] += s4;
-#pragma unroll
-        for (int m = 0; m < N; ++m) Wk[m] = U[m];
-      } else {
-#pragma unroll
-        for (int m = N - 1; m >= 0; --m) {
-          const T p1 = m >= 1 ? X[m - 1] : m1;
-          const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? m1 : m2);
-          X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
-        }
+      for (int m = N - 1; m >= 0; --m) {
+        const T p1 = m >= 1 ? X[m - 1] : m1;
+        const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? m1 : m2);
+        s0 = fma_(X[m], U[m], s0);
+        s1 = fma_(p1, U[m], s1);
+        s2 = fma_(p2, U[m], s2);
+        s3 = fma_(p1, W[m], s3);
+        s4 = fma_(p2, W[m], s4);
+        X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
       }
+      s0 = row_sum(s0);
+      s1 = row_sum(s1);
+      s2 = row_sum(s2);
+      s3 = row_sum(s3);
+      s4 = row_sum(s4);
+      if (RC) {
+        // u_k and w_k in the scaled domain: w_k = scale_k * W, u_k = scale_{k-1} * U
+        const T su = k > 0 ? cb[kBwdRow * (k - 1) + BW_SCALE] : T(1), sw = b[BW_SCALE];
+        s0 *= su;
+        s1 *= su;
+        s2 *= su;
+        s3 *= sw;
+        s4 *= sw;
+      }
+      T *ak = acc + 5 * k;
+      ak[0] += s0;
+      ak[1] += s1;
+      ak[2] += s2;
+      ak[3] += s3;
+      ak[4] += s4;
+    } else {
+#pragma unroll
+      for (int m = N - 1; m >= 0; --m) {
+        const T p1 = m >= 1 ? X[m - 1] : m1;
+        const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? m1 : m2);
+        X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
+      }
+    }
+  };
+
+  for (int64_t it = 0; it < steps; ++it) {
+    g = t0 - v.warm + it * G;
+    full = aligned && __builtin_amdgcn_ballot_w64(!(g >= pad && g + G <= v.np)) == 0;
+    live = it >= warm_groups;   // uniform per wave
+    load_group_rev<N, TI, T>(X, gy, g, v.n, v.np, full, buf);
+    if (live) {
+      // A = u_{K-1}, B = w_{K-1}
+      if (RC) {
+        // the group covers forward samples [np - g - G, np - g): its input in
+        // forward order (kept in the row's stage until the group's gx is
+        // stored) and the state the cascade enters it with
+        load_group<N, TI, T>(F, x, v.np - g - G, v.n, full, buf);
+        const int64_t j = g / G;
+        for (int i = row_lane(); i < SE; i += kL) ck[i] = j < v.nck ? saved[j * SE + i] : T(0);
+        __builtin_amdgcn_wave_barrier();
+        forward(v.K - 1);
+        to_reversed<N>(A, F);
+        ph_section<N, T, B0ONE>(F, ct + (int64_t)(v.K - 1) * v.stride, xs2, xs1, cw + 2 + 2 * (v.K - 1));
+        to_reversed<N>(B, F);
+        __builtin_amdgcn_wave_barrier();
+      } else {
+        input_of(v.K - 1, A);
+        load_group_rev<N, double, T>(B, saved + (int64_t)(v.K - 1) * v.sstride, g, v.n, v.np, full, dbuf);
+      }
+    }
+    for (int k = v.K - 1;;) {
+      step(k, A, B);
+      if (--k < 0) break;
+      if (live) input_of(k, B);   // w_k = u_{k+1} is in A
+      step(k, B, A);
+      if (--k < 0) break;
+      if (live) input_of(k, A);
     }
     if (live) store_group_rev<N, TI, T>(X, gx, g, v.n, v.np, full, buf);
   }
@@ -252,6 +351,10 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   if (row_lane() == 0 && tile_index < v.ntiles)
     for (int i = 0; i < 5 * v.K; ++i) sums[i] = acc[i];
 }
+
+// LDS doubles per row of the adjoint pass: all-pole states and sums, and
+// in recompute mode the group's checkpoint and its working copy.
+__host__ __device__ constexpr int adj_row_elems(int K, bool rc) { return 7 * K + (rc ? 2 * state_elems(K) : 0); }
 
 __device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
   AdjView v;
@@ -261,14 +364,15 @@ __device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
   v.warm = a.warm;
   v.ntiles = a.ntiles;
   v.sstride = a.sstride;
-  v.shift = 0;
+  v.shift = a.shift;
+  v.nck = a.nck;
   v.K = a.K;
   v.stride = a.stride;
   return v;
 }
 
 // Single signal: row r of wavefront w takes tile 4w + r.
-template <int N, typename TI, bool B0ONE>
+template <int N, typename TI, bool B0ONE, bool RC>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
     const TI *__restrict__ x, double *__restrict__ saved, const double *__restrict__ tab,
     const double *__restrict__ bwd, BwdArgs a) {
@@ -282,11 +386,11 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
   double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
                (int64_t)(w * kRows + row) * state_elems(a.K);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
-  save_rows<N, TI, B0ONE>(x, saved, as_ctab(tab), as_ctab(bwd), adj_view(a), wave * kRows + row, true,
-                          st, rowbuf);
+  save_rows<N, TI, B0ONE, RC>(x, saved, as_ctab(tab), as_ctab(bwd), adj_view(a), wave * kRows + row, true,
+                              st, rowbuf);
 }
 
-template <int N, typename TI>
+template <int N, typename TI, bool B0ONE, bool RC>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
     const TI *__restrict__ gy, TI *__restrict__ gx, const TI *__restrict__ x,
     const double *__restrict__ saved, const double *__restrict__ tab, const double *__restrict__ bwd,
@@ -298,10 +402,10 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
   const int row = lane_id() >> 4;
   const int64_t tile_index = wave * kRows + row;
   double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
-               (int64_t)(w * kRows + row) * (7 * a.K);
+               (int64_t)(w * kRows + row) * adj_row_elems(a.K, RC);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
-  adjoint_rows<N, TI>(gy, gx, x, saved, as_ctab(tab), as_ctab(bwd), partials + tile_index * 5 * a.K,
-                      adj_view(a), tile_index, true, st, rowbuf);
+  adjoint_rows<N, TI, B0ONE, RC>(gy, gx, x, saved, as_ctab(tab), as_ctab(bwd), partials + tile_index * 5 * a.K,
+                                 adj_view(a), tile_index, true, st, rowbuf);
 }
 
 __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
@@ -313,12 +417,13 @@ __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
   v.ntiles = c.ntiles;
   v.sstride = c.sstride;
   v.shift = c.shift;
+  v.nck = c.nck;
   v.K = c.K;
   v.stride = c.stride;
   return v;
 }
 
-template <int N, typename TI, bool B0ONE>
+template <int N, typename TI, bool B0ONE, bool RC>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_batched_kernel(
     const TI *__restrict__ x, double *__restrict__ ws, const AdjChan *__restrict__ chans,
     const int32_t *__restrict__ item_chan, int64_t items, int32_t kmax) {
@@ -332,11 +437,11 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_batched_ker
   double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
                (int64_t)(w * kRows + row) * state_elems(kmax);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
-  save_rows<N, TI, B0ONE>(x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd), adj_view(c),
-                          tile_index, true, st, rowbuf);
+  save_rows<N, TI, B0ONE, RC>(x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd), adj_view(c),
+                              tile_index, true, st, rowbuf);
 }
 
-template <int N, typename TI>
+template <int N, typename TI, bool B0ONE, bool RC>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_batched_kernel(
     const TI *__restrict__ gy, TI *__restrict__ gx, const TI *__restrict__ x, double *__restrict__ ws,
     const AdjChan *__restrict__ chans, const int32_t *__restrict__ item_chan, int64_t items,
@@ -349,11 +454,11 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_batched_
   const int row = lane_id() >> 4;
   const int64_t tile_index = (item - c.first_item) * kRows + row;
   double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
-               (int64_t)(w * kRows + row) * (7 * kmax);
+               (int64_t)(w * kRows + row) * adj_row_elems(kmax, RC);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
-  adjoint_rows<N, TI>(gy + c.off, gx + c.off, x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd),
-                      ws + c.partial_off + tile_index * 5 * c.K, adj_view(c), tile_index, true, st,
-                      rowbuf);
+  adjoint_rows<N, TI, B0ONE, RC>(gy + c.off, gx + c.off, x + c.off, ws + c.saved_off, as_ctab(c.tab),
+                                 as_ctab(c.bwd), ws + c.partial_off + tile_index * 5 * c.K, adj_view(c),
+                                 tile_index, true, st, rowbuf);
 }
 
 // dL/d(sos) from the per-tile sums of one section: the block sums

@@ -83,6 +83,9 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos);
 void build_deferred_tables(sos_plan_s &p);
 // the adjoint's sub-plan and rows (sosfilt_backward.hip)
 sos_status attach_adjoint(sos_plan_s &p, const double *sos);
+bool adjoint_recompute(const sos_plan_s &p);
+double adjoint_cost_saved(int K);
+double adjoint_cost_recompute(int K);
 // block filtering plans (sosfilt_block.hip)
 sos_status build_block_plan(sos_plan_s &p);
 sos_status upload_block_plan(sos_plan_s &p);

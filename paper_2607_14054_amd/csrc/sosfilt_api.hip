@@ -235,9 +235,11 @@ const char *sos_status_string(sos_status s) {
 }
 
 sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan_t *out) {
-  constexpr uint32_t known = SOS_FLAG_HOST_ONLY | SOS_FLAG_CARRY_SCAN | SOS_FLAG_CARRY_RUNIN;
+  constexpr uint32_t known = SOS_FLAG_HOST_ONLY | SOS_FLAG_CARRY_SCAN | SOS_FLAG_CARRY_RUNIN |
+                             SOS_FLAG_ADJ_SAVE | SOS_FLAG_ADJ_RECOMPUTE;
   if (opts && (opts->flags & ~known)) return SOS_E_ARG;
   if (opts && (opts->flags & SOS_FLAG_CARRY_SCAN) && (opts->flags & SOS_FLAG_CARRY_RUNIN)) return SOS_E_ARG;
+  if (opts && (opts->flags & SOS_FLAG_ADJ_SAVE) && (opts->flags & SOS_FLAG_ADJ_RECOMPUTE)) return SOS_E_ARG;
   return create_plan(sos, K, opts, true, out);
 }
 

@@ -43,34 +43,76 @@ sos_status attach_adjoint(sos_plan_s &p, const double *sos) {
   return SOS_OK;
 }
 
+// Recompute (group checkpoints) or saved outputs, by measured costs per
+// sample (MI355X, 2^24 float32 samples, ps): saved outputs move about 16K
+// bytes per sample, 3.74 + 4.00 K; recompute takes K(K-1)/2 + 1 forward
+// section passes per group besides the adjoint's own work,
+// 4.48 + 1.36 K + 0.38 (K(K-1)/2 + 1).  They cross between K = 14 and 15.
+double adjoint_cost_saved(int K) { return 3.74 + 4.00 * K; }
+double adjoint_cost_recompute(int K) { return 4.48 + 1.36 * K + 0.38 * (0.5 * K * (K - 1) + 1); }
+
+bool adjoint_recompute(const sos_plan_s &p) {
+  if (p.flags & SOS_FLAG_ADJ_RECOMPUTE) return true;
+  if (p.flags & SOS_FLAG_ADJ_SAVE) return false;
+  return adjoint_cost_recompute(p.K) < adjoint_cost_saved(p.K);
+}
+
 }  // namespace sosf
 
 namespace {
 
+template <typename TI, bool B0ONE, bool RC>
+void launch_single(const BwdArgs &f, const BwdArgs &a, int K, const void *x, const void *gy, void *gx,
+                   double *saved, const double *tab, const double *rows, double *partials, hipStream_t s) {
+  constexpr int N = kBwdN;
+  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
+  const unsigned lds_f = (unsigned)lds_bytes<N, double, double>(K);
+  const unsigned blocks_f = (unsigned)((f.ntiles + per_block - 1) / per_block);
+  hipLaunchKernelGGL((sos_rows_save_kernel<N, TI, B0ONE, RC>), dim3(blocks_f), dim3(kWavesPerBlock * 64), lds_f,
+                     s, static_cast<const TI *>(x), saved, tab, rows, f);
+  const unsigned lds_a = (unsigned)(stage_bytes<N, double>() + kWavesPerBlock * kRows * adj_row_elems(K, RC) * 8);
+  const unsigned blocks_a = (unsigned)((a.ntiles + per_block - 1) / per_block);
+  hipLaunchKernelGGL((sos_rows_adjoint_kernel<N, TI, B0ONE, RC>), dim3(blocks_a), dim3(kWavesPerBlock * 64),
+                     lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx), static_cast<const TI *>(x),
+                     saved, tab, rows, partials, a);
+}
+
 struct BwdLayout {
+  bool rc;                  // recompute mode
   int64_t np, tile, ntiles, sstride;
+  int64_t shift, nck;       // forward tiles over [-shift, n); checkpoints (recompute mode)
+  int64_t ftile, fntiles;   // the forward pass's tiles
   size_t saved_bytes, partial_bytes;
 };
 
 BwdLayout layout(const sos_plan_s &p, int64_t n) {
-  const sos_plan_s &b = *p.bwd;
   const size_t esz = p.io_dtype == SOS_F64 ? 8 : 4;
-  const int64_t V = 16 / (int64_t)esz;
+  const int64_t V = 16 / (int64_t)esz, G = (int64_t)kBwdN * kL;
   BwdLayout l;
+  l.rc = adjoint_recompute(p);
   l.np = (n + V - 1) / V * V;
   l.tile = sos_plan_tile(p.bwd, std::max<int64_t>(l.np, 1));
   l.ntiles = (l.np + l.tile - 1) / l.tile;
   l.sstride = (n + 63) / 64 * 64;
-  l.saved_bytes = (size_t)p.K * (size_t)l.sstride * sizeof(double);
+  if (l.rc) {
+    // forward groups start where the reversed-time groups of [0, np) do
+    l.shift = (G - l.np % G) % G;
+    l.nck = (l.np + l.shift) / G;
+    l.saved_bytes = (size_t)l.nck * state_elems(p.K) * sizeof(double);
+  } else {
+    l.shift = 0;
+    l.nck = 0;
+    l.saved_bytes = (size_t)p.K * (size_t)l.sstride * sizeof(double);
+  }
+  l.ftile = sos_plan_tile(p.bwd, std::max<int64_t>(n + l.shift, 1));
+  l.fntiles = (n + l.shift + l.ftile - 1) / l.ftile;
   l.partial_bytes = (size_t)std::max<int64_t>(l.ntiles, 1) * 5 * p.K * sizeof(double);
-  (void)b;
   return l;
 }
 
 template <typename TI>
 sos_status launch_adjoint(const sos_plan_s &p, const void *x, const void *gy, void *gx, double *gsos,
                           int64_t n, void *ws, hipStream_t s) {
-  constexpr int N = kBwdN;
   const sos_plan_s &b = *p.bwd;
   const BwdLayout l = layout(p, n);
   double *saved = static_cast<double *>(ws);
@@ -83,30 +125,29 @@ sos_status launch_adjoint(const sos_plan_s &p, const void *x, const void *gy, vo
   a.stride = b.stride;
   a.warm = b.warm;
   a.sstride = l.sstride;
+  a.shift = l.shift;
+  a.nck = l.nck;
   const double *tab = static_cast<const double *>(b.d_table);
   const double *rows = static_cast<const double *>(p.d_bwd_rows);
-  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
   if (n > 0) {
-    // forward pass saving every section's output (forward-time tiles)
-    a.tile = sos_plan_tile(p.bwd, n);
-    a.ntiles = (n + a.tile - 1) / a.tile;
-    const unsigned lds_f = (unsigned)lds_bytes<N, double, double>(p.K);
-    const unsigned blocks_f = (unsigned)((a.ntiles + per_block - 1) / per_block);
-    if (b.b0_factored)
-      hipLaunchKernelGGL((sos_rows_save_kernel<N, TI, true>), dim3(blocks_f), dim3(kWavesPerBlock * 64),
-                         lds_f, s, static_cast<const TI *>(x), saved, tab, rows, a);
-    else
-      hipLaunchKernelGGL((sos_rows_save_kernel<N, TI, false>), dim3(blocks_f), dim3(kWavesPerBlock * 64),
-                         lds_f, s, static_cast<const TI *>(x), saved, tab, rows, a);
-    if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
+    // forward-time tiles (saving outputs or checkpoints), then the
     // reversed-time adjoint
+    BwdArgs f = a;
+    f.tile = l.ftile;
+    f.ntiles = l.fntiles;
     a.tile = l.tile;
     a.ntiles = l.ntiles;
-    const unsigned lds_a = (unsigned)(stage_bytes<N, double>() + kWavesPerBlock * kRows * 7 * p.K * 8);
-    const unsigned blocks_a = (unsigned)((a.ntiles + per_block - 1) / per_block);
-    hipLaunchKernelGGL((sos_rows_adjoint_kernel<N, TI>), dim3(blocks_a), dim3(kWavesPerBlock * 64), lds_a,
-                       s, static_cast<const TI *>(gy), static_cast<TI *>(gx), static_cast<const TI *>(x),
-                       saved, tab, rows, partials, a);
+    if (l.rc) {
+      if (b.b0_factored)
+        launch_single<TI, true, true>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+      else
+        launch_single<TI, false, true>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+    } else {
+      if (b.b0_factored)
+        launch_single<TI, true, false>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+      else
+        launch_single<TI, false, false>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+    }
     if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
   }
   hipLaunchKernelGGL(sos_adjoint_reduce_kernel, dim3((unsigned)p.K), dim3(256), 0, s, partials,
@@ -115,35 +156,46 @@ sos_status launch_adjoint(const sos_plan_s &p, const void *x, const void *gy, vo
 }
 
 template <typename TI>
-const void *adjoint_batched_kernel_ptr() {
-  return reinterpret_cast<const void *>(&sos_rows_adjoint_batched_kernel<kBwdN, TI>);
+const void *adjoint_batched_kernel_ptr(bool rc) {
+  // both b0 variants use the same resources
+  return rc ? reinterpret_cast<const void *>(&sos_rows_adjoint_batched_kernel<kBwdN, TI, true, true>)
+            : reinterpret_cast<const void *>(&sos_rows_adjoint_batched_kernel<kBwdN, TI, true, false>);
 }
 
 size_t adj_lds_save(int kmax) { return (size_t)lds_bytes<kBwdN, double, double>(kmax); }
-size_t adj_lds_adjoint(int kmax) {
-  return (size_t)stage_bytes<kBwdN, double>() + (size_t)kWavesPerBlock * kRows * 7 * kmax * sizeof(double);
+size_t adj_lds_adjoint(int kmax, bool rc) {
+  return (size_t)stage_bytes<kBwdN, double>() + (size_t)kWavesPerBlock * kRows * adj_row_elems(kmax, rc) * sizeof(double);
+}
+
+template <typename TI, bool B0ONE, bool RC>
+void launch_batched(const sos_batch_s &b, const void *x, const void *gy, void *gx, double *w, hipStream_t s) {
+  constexpr int N = kBwdN;
+  const unsigned blocks = (unsigned)((b.adj_items + kWavesPerBlock - 1) / kWavesPerBlock);
+  const unsigned lds_f = (unsigned)adj_lds_save(b.kmax), lds_a = (unsigned)adj_lds_adjoint(b.kmax, RC);
+  hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, B0ONE, RC>), dim3(blocks), dim3(kWavesPerBlock * 64),
+                     lds_f, s, static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items,
+                     (int32_t)b.kmax);
+  hipLaunchKernelGGL((sos_rows_adjoint_batched_kernel<N, TI, B0ONE, RC>), dim3(blocks),
+                     dim3(kWavesPerBlock * 64), lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx),
+                     static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
 }
 
 template <typename TI>
 sos_status launch_adjoint_batched(const sos_batch_s &b, const void *x, const void *gy, void *gx, double *gsos,
                                   void *ws, hipStream_t s) {
-  constexpr int N = kBwdN;
   double *w = static_cast<double *>(ws);
   if (b.adj_items > 0) {
-    const unsigned blocks = (unsigned)((b.adj_items + kWavesPerBlock - 1) / kWavesPerBlock);
-    const unsigned lds_f = (unsigned)adj_lds_save(b.kmax), lds_a = (unsigned)adj_lds_adjoint(b.kmax);
-    if (b.adj_b0one)
-      hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, true>), dim3(blocks), dim3(kWavesPerBlock * 64),
-                         lds_f, s, static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items,
-                         (int32_t)b.kmax);
-    else
-      hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, false>), dim3(blocks), dim3(kWavesPerBlock * 64),
-                         lds_f, s, static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items,
-                         (int32_t)b.kmax);
-    if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
-    hipLaunchKernelGGL((sos_rows_adjoint_batched_kernel<N, TI>), dim3(blocks), dim3(kWavesPerBlock * 64), lds_a,
-                       s, static_cast<const TI *>(gy), static_cast<TI *>(gx), static_cast<const TI *>(x), w,
-                       b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+    if (b.adj_rc) {
+      if (b.adj_b0one)
+        launch_batched<TI, true, true>(b, x, gy, gx, w, s);
+      else
+        launch_batched<TI, false, true>(b, x, gy, gx, w, s);
+    } else {
+      if (b.adj_b0one)
+        launch_batched<TI, true, false>(b, x, gy, gx, w, s);
+      else
+        launch_batched<TI, false, false>(b, x, gy, gx, w, s);
+    }
     if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
   }
   hipLaunchKernelGGL(sos_adjoint_reduce_batched_kernel, dim3((unsigned)b.adj_rows), dim3(256), 0, s, w, b.d_adj,
@@ -157,8 +209,8 @@ namespace sosf {
 
 // The batched adjoint's schedule (host side): per channel its adjoint
 // sub-plan, tiles in groups of the sub-plan (reversed time, n rounded up to
-// the vector width), and its regions of the workspace (saved outputs,
-// per-tile sums) and of gsos.  Channels go in the forward batch's launch
+// the vector width), and its regions of the workspace (saved outputs or
+// group checkpoints, per-tile sums) and of gsos.  Channels go in the forward batch's launch
 // order.
 sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups) {
   b.adj = false;
@@ -171,20 +223,34 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
   // r[t] = s[np - 1 - t] with off + np a multiple of V.  Both put every
   // group of x, gy, gx and of the saved arrays (origin shifted by shift) on
   // a 16-byte boundary.  span: the samples the tiles must cover.
+  // In recompute mode the shift is -np mod G instead, which is also off
+  // mod V, so that the forward groups start where the reversed-time ones do
+  // (the checkpoints).  One mode per batch: saved outputs if a plan asks for
+  // them, else recompute if a plan asks for it, else the cheaper over the
+  // batch's samples.
+  bool any_save = false, any_rc = false;
+  double cost_rc = 0.0, cost_saved = 0.0;
+  for (int c = 0; c < b.C; ++c) {
+    any_save = any_save || (plans[c]->flags & SOS_FLAG_ADJ_SAVE);
+    any_rc = any_rc || (plans[c]->flags & SOS_FLAG_ADJ_RECOMPUTE);
+    cost_rc += (double)b.n[c] * adjoint_cost_recompute(plans[c]->K);
+    cost_saved += (double)b.n[c] * adjoint_cost_saved(plans[c]->K);
+  }
+  b.adj_rc = !any_save && (any_rc || cost_rc < cost_saved);
   std::vector<int64_t> np(b.C), shift(b.C), span(b.C);
   int64_t total_groups = 0;
   b.adj_b0one = true;
   for (int c = 0; c < b.C; ++c) {
     const int64_t n = b.n[c];
-    shift[c] = b.off[c] % V;
     np[c] = n ? (b.off[c] + n + V - 1) / V * V - b.off[c] : 0;
+    shift[c] = b.adj_rc ? (G - np[c] % G) % G : b.off[c] % V;
     span[c] = n ? std::max(n + shift[c], np[c]) : 0;
     total_groups += (span[c] + G - 1) / G;
     b.adj_b0one = b.adj_b0one && plans[c]->bwd->b0_factored;
   }
-  const Residency r = residency_of(b.io_dtype == SOS_F64 ? adjoint_batched_kernel_ptr<double>()
-                                                         : adjoint_batched_kernel_ptr<float>(),
-                                   adj_lds_adjoint(b.kmax), kWavesPerBlock * 64);
+  const Residency r = residency_of(b.io_dtype == SOS_F64 ? adjoint_batched_kernel_ptr<double>(b.adj_rc)
+                                                         : adjoint_batched_kernel_ptr<float>(b.adj_rc),
+                                   adj_lds_adjoint(b.kmax, b.adj_rc), kWavesPerBlock * 64);
   const int64_t resident_rows = (int64_t)4 * r.simds * r.waves_per_simd;
   b.adj_gsos_row.assign(b.C, 0);
   int64_t rows = 0;
@@ -223,8 +289,9 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
     a.ntiles = groups ? (span[c] + a.tile - 1) / a.tile : 0;
     a.first_item = items;
     a.sstride = (b.n[c] + shift[c] + 63) / 64 * 64;
+    a.nck = b.adj_rc && b.n[c] ? (np[c] + shift[c]) / G : 0;
     a.saved_off = ws;
-    ws += (int64_t)plans[c]->K * a.sstride;
+    ws += b.adj_rc ? (a.nck * state_elems(plans[c]->K) + 31) / 32 * 32 : (int64_t)plans[c]->K * a.sstride;
     a.partial_off = ws;
     ws += (a.ntiles * 5 * plans[c]->K + 31) / 32 * 32;
     a.K = plans[c]->K;

@@ -23,6 +23,9 @@ SOS_FLAG_HOST_ONLY = 0x1
 SOS_FLAG_CARRY_SCAN = 0x2
 SOS_FLAG_CARRY_RUNIN = 0x4
 _CARRY = {"auto": 0, "scan": SOS_FLAG_CARRY_SCAN, "runin": SOS_FLAG_CARRY_RUNIN}
+SOS_FLAG_ADJ_SAVE = 0x8
+SOS_FLAG_ADJ_RECOMPUTE = 0x10
+_ADJOINT = {"auto": 0, "save": SOS_FLAG_ADJ_SAVE, "recompute": SOS_FLAG_ADJ_RECOMPUTE}
 (SOS_TABLE_ROWS, SOS_TABLE_U1, SOS_TABLE_U2, SOS_TABLE_C, SOS_TABLE_PH_POWERS,
  SOS_TABLE_CR_LEVELS, SOS_TABLE_CR_TERMINAL, SOS_TABLE_CR_POWERS, SOS_TABLE_TRANSITION,
  SOS_TABLE_THETA, SOS_TABLE_COUPLING) = range(11)
@@ -148,15 +151,18 @@ class PlanInfo:
 class Plan:
     """Owns a sos_plan_t.  sos: [K, 6] rows (b0, b1, b2, a0, a1, a2).
     carry: "auto" (the library picks the run-in or the exact scan per call),
-    "scan" or "runin"."""
+    "scan" or "runin".  adjoint: "auto", "save" (every section's output kept
+    for the backward pass) or "recompute" (group checkpoints, section inputs
+    recomputed)."""
 
     def __init__(self, sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=0,
-                 tile_groups=0, host_only=False, carry="auto"):
+                 tile_groups=0, host_only=False, carry="auto", adjoint="auto"):
         s = np.ascontiguousarray(np.asarray(sos, dtype=np.float64))
         if s.ndim != 2 or s.shape[1] != 6:
             raise ValueError("sos must be [K, 6]")
         o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), 16,
-                  int(tile_groups), (SOS_FLAG_HOST_ONLY if host_only else 0) | _CARRY[carry])
+                  int(tile_groups),
+                  (SOS_FLAG_HOST_ONLY if host_only else 0) | _CARRY[carry] | _ADJOINT[adjoint])
         h = ctypes.c_void_p()
         _check(lib().sos_plan(s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), s.shape[0],
                               ctypes.byref(o), ctypes.byref(h)), "sos_plan")
@@ -206,6 +212,9 @@ class Plan:
 
     def workspace_size(self, n: int) -> int:
         return int(lib().sos_workspace_size(self._h, int(n)))
+
+    def backward_workspace_size(self, n: int) -> int:
+        return int(lib().sos_backward_workspace_size(self._h, int(n)))
 
 
 def _stream_ptr(stream):
@@ -306,6 +315,9 @@ class Batch:
                "sos_batch_query")
         return {"total": int(total.value), "items": int(items.value), "offsets": off, "tile": tile,
                 "order": order}
+
+    def backward_workspace_size(self) -> int:
+        return int(lib().sos_batch_backward_workspace_size(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -56,14 +56,55 @@ def run_backward(sos, x_np, g_np, **kw):
     return gx.cpu().numpy(), gs.cpu().numpy()
 
 
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
 @pytest.mark.parametrize("n", [1, 2, 17, 255, 256, 257, 5000, 70001, 2 ** 20 + 3])
 @pytest.mark.parametrize("K", [1, 3, 8])
-def test_backward_f64_matches_oracle_adjoint(n, K):
+def test_backward_f64_matches_oracle_adjoint(n, K, adjoint):
     sos = W.make_sos(K, 0.5, 0.95, 40 + K)
     x = W.make_signal(n, 41, np.float64)
     g = W.grad_seed_signal(n, 41, np.float64)
-    gx, gs = run_backward(sos, x, g)
-    check_f64(x, sos, g, gx, gs, "n=%d K=%d" % (n, K))
+    gx, gs = run_backward(sos, x, g, adjoint=adjoint)
+    check_f64(x, sos, g, gx, gs, "n=%d K=%d %s" % (n, K, adjoint))
+
+
+@pytest.mark.parametrize("io", ["f64", "f32"])
+@pytest.mark.parametrize("K", [2, 16])
+def test_backward_recompute_equals_saved_outputs(io, K):
+    """The two adjoint modes (every section output kept in FP64, or the
+    section inputs recomputed from group checkpoints) give the same
+    gradients to rounding, with poles up to r = 0.99, and the oracle's."""
+    dt = np.float64 if io == "f64" else np.float32
+    n = 3 * 2 ** 16 + 1001
+    sos = W.make_sos(K, 0.6, 0.99, 140 + K)
+    x = W.make_signal(n, 141, dt)
+    g = W.grad_seed_signal(n, 141, dt)
+    rx, rs = run_backward(sos, x, g, adjoint="recompute")
+    sx, ss = run_backward(sos, x, g, adjoint="save")
+    assert oracle.rel_rms(rx, sx) < (1e-12 if io == "f64" else 1e-6)
+    assert row_err(rs, ss) < 1e-10
+    if io == "f64":
+        check_f64(x, sos, g, rx, rs, "recompute K=%d" % K)
+
+
+def test_backward_mode_choice_and_workspace():
+    """Automatic mode: recompute up to K = 14 (checkpoints: 2K + 2 doubles
+    per 256-sample group), saved outputs above (K doubles per sample); both
+    flags together are rejected."""
+    n = 2 ** 20
+    for K, rc in ((1, True), (8, True), (14, True), (15, False), (40, False)):
+        sos = W.make_sos(K, 0.5, 0.95, 150 + K)
+        auto = S.Plan(sos, io_dtype="f32").backward_workspace_size(n)
+        save = S.Plan(sos, io_dtype="f32", adjoint="save").backward_workspace_size(n)
+        rec = S.Plan(sos, io_dtype="f32", adjoint="recompute").backward_workspace_size(n)
+        assert save >= K * n * 8
+        assert rec < (2 * K + 2) * 8 * (n // 256 + 2) + save - K * n * 8
+        assert auto == (rec if rc else save), K
+    import ctypes
+    s2 = np.ascontiguousarray(W.make_sos(2, 0.5, 0.9, 1))
+    o = S._Opts(S.SOS_F32, S.SOS_F64, S.SOS_AUTO, 0, 16, 0, S.SOS_FLAG_ADJ_SAVE | S.SOS_FLAG_ADJ_RECOMPUTE)
+    h = ctypes.c_void_p()
+    rc = S.lib().sos_plan(s2.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, ctypes.byref(o), ctypes.byref(h))
+    assert rc == S.SOS_E_ARG and not h.value
 
 
 def test_backward_f32_adjoint_config_channel():
@@ -163,15 +204,34 @@ def test_backward_bad_arguments():
     assert lib.sos_backward_workspace_size(host.handle, 100) == 0
 
 
+def test_batched_adjoint_mode_choice():
+    """One adjoint mode per batch: saved outputs if any plan asks for them,
+    else recompute if any asks for it, else the cheaper one over the batch's
+    samples (K = 2 and 4 channels recompute; a batch dominated by K = 32
+    keeps the outputs).  The workspace shows the mode."""
+    def ws(Ks, modes, lengths=(5000, 70001)):
+        plans = [S.Plan(W.make_sos(k, 0.5, 0.95, 190 + i), io_dtype="f32", adjoint=m)
+                 for i, (k, m) in enumerate(zip(Ks, modes))]
+        return S.Batch(plans, list(lengths)).backward_workspace_size()
+    saved_bytes = 8 * (2 * 5000 + 4 * 70001)
+    assert ws([2, 4], ["auto", "auto"]) < saved_bytes / 4
+    assert ws([2, 4], ["auto", "save"]) >= saved_bytes
+    assert ws([2, 4], ["recompute", "auto"]) < saved_bytes / 4
+    assert ws([2, 4], ["recompute", "save"]) >= saved_bytes
+    assert ws([2, 32], ["auto", "auto"]) >= 8 * (2 * 5000 + 32 * 70001)
+    assert ws([32, 2], ["auto", "auto"], (1000, 200000)) < 8 * (32 * 1000 + 2 * 200000) / 4
+
+
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
 @pytest.mark.parametrize("io", ["f64", "f32"])
-def test_batched_adjoint_matches_oracle(io):
+def test_batched_adjoint_matches_oracle(io, adjoint):
     """sos_filt_backward_batched on ragged channels (dense packing, so f32
     channels also start off 16-byte boundaries), K mixed."""
     dt = np.float64 if io == "f64" else np.float32
     lengths = [0, 1, 17, 255, 5000, 70001, 2 ** 18 + 5]
     Ks = [3, 8, 1, 16, 5, 8, 2]
     sos = [W.make_sos(k, 0.5, 0.95, 70 + c) for c, k in enumerate(Ks)]
-    plans = [S.Plan(s_, io_dtype=io, compute_dtype="f64", N=32) for s_ in sos]
+    plans = [S.Plan(s_, io_dtype=io, compute_dtype="f64", N=32, adjoint=adjoint) for s_ in sos]
     b = S.Batch(plans, lengths)
     xs = [W.make_signal(n, 71 + c, dt) for c, n in enumerate(lengths)]
     gs = [W.grad_seed_signal(n, 71 + c, dt) for c, n in enumerate(lengths)]
@@ -200,8 +260,9 @@ def test_batched_adjoint_matches_oracle(io):
             assert row_err(g_c, rs) < 1e-9, c
 
 
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
 @pytest.mark.parametrize("io", ["f32", "f64"])
-def test_batched_adjoint_shifted_starts_keep_neighbours(io):
+def test_batched_adjoint_shifted_starts_keep_neighbours(io, adjoint):
     """Channels starting 1..V-1 samples past a 16-byte boundary (V samples
     per 16 bytes) with gaps of 1..3 samples between them, lengths around
     whole groups of the adjoint tiles: dL/dx and dL/dsos match the oracle
@@ -218,7 +279,7 @@ def test_batched_adjoint_shifted_starts_keep_neighbours(io):
         pos += n + 1 + i % 3
     Ks = [1 + (5 * c) % 9 for c in range(len(lengths))]
     sos = [W.make_sos(k, 0.5, 0.95, 170 + c) for c, k in enumerate(Ks)]
-    plans = [S.Plan(s_, io_dtype=io, compute_dtype="f64", N=32) for s_ in sos]
+    plans = [S.Plan(s_, io_dtype=io, compute_dtype="f64", N=32, adjoint=adjoint) for s_ in sos]
     b = S.Batch(plans, lengths, offsets=offsets)
     xs = [W.make_signal(n, 171 + c, dt) for c, n in enumerate(lengths)]
     gs = [W.grad_seed_signal(n, 171 + c, dt) for c, n in enumerate(lengths)]
@@ -267,14 +328,15 @@ def test_batched_adjoint_equals_single_channel_adjoint():
         assert row_err(gsos[first[c]:first[c] + plans[c].K].cpu().numpy(), ss.cpu().numpy()) < 1e-12
 
 
-def test_adjoint_graph_replays_match_eager():
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
+def test_adjoint_graph_replays_match_eager(adjoint):
     """sos_filt_backward (three kernels, caller workspace) captured in a HIP
     graph: every replay equals the eager call bit for bit."""
     import ctypes
     lib = S.lib()
     sos = W.make_sos(6, 0.5, 0.95, 92)
     n = 200003
-    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", N=32)
+    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", N=32, adjoint=adjoint)
     x = torch.from_numpy(W.make_signal(n, 93, np.float32)).to(DEV)
     g = torch.from_numpy(W.grad_seed_signal(n, 93, np.float32)).to(DEV)
     gx = torch.empty_like(x)
