@@ -455,7 +455,7 @@ def timed(torch, once, steps):
 def bench_precision(S, W, torch, dev, args):
     """The precision workload: 256 channels x 2^20 float32 samples, K = 8,
     pole radius U[0.9, 0.999], channel c drawn with seed c.  One batched
-    launch per arithmetic type; the relative RMS and max error against the
+    launch per arithmetic type and solver (block filtering included); the relative RMS and max error against the
     FP64 oracle on a sample of channels, with the plain sequential FP32
     cascade's error on the same channels (the FP32 floor)."""
     cfg = W.CONFIGS["precision"]
@@ -476,16 +476,10 @@ def bench_precision(S, W, torch, dev, args):
                                ("f64", "block", 64), ("f16", "block", 64), ("bf16", "block", 64)):
         plans = [S.Plan(s_, io_dtype="f32", compute_dtype=compute, solver=solver, N=N) for s_ in sos]
         yb = torch.empty_like(xb)
-        if solver == "block":
-            # comparison solver, not batched: one launch per channel
-            def once():
-                for c in range(C):
-                    S.filt(plans[c], xb[c * n:(c + 1) * n], yb[c * n:(c + 1) * n])
-        else:
-            b = S.Batch(plans, [n] * C)
+        b = S.Batch(plans, [n] * C)
 
-            def once():
-                S.filt_batched(b, xb, yb)
+        def once():
+            S.filt_batched(b, xb, yb)
         once()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)

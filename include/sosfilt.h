@@ -228,9 +228,13 @@ sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
  *
  * plans    host [C]: channel c is filtered with plans[c] (the same plan may
  *          serve several channels).  All plans must share N, io_dtype and
- *          compute_dtype (else SOS_E_UNSUPPORTED), and all must use
- *          SOS_AUTO, SOS_PH or SOS_CR (else SOS_E_UNSUPPORTED).  The plans must outlive the
- *          batch: the batch refers to their device tables.
+ *          compute_dtype (else SOS_E_UNSUPPORTED), and either all use
+ *          SOS_AUTO, SOS_PH or SOS_CR, or all use SOS_BLOCK (block filtering,
+ *          one workgroup per four tiles of a channel, with that channel's
+ *          Toeplitz operands in LDS; its groups are 256 samples whatever
+ *          N).  SOS_PH_DEFERRED and SOS_SCALAR give SOS_E_UNSUPPORTED.  The
+ *          plans must outlive the batch: the batch refers to their device
+ *          tables.  sos_batch_replan keeps the batch's kind (block or not).
  * C        number of channels, >= 1.
  * n        host [C]: channel lengths, >= 0.
  * offsets  host [C] or NULL: first sample of channel c in the concatenated

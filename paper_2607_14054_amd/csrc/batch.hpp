@@ -8,12 +8,15 @@
 #include "kernels.hpp"
 #include "adjoint_types.hpp"
 #include "plan.hpp"
+#include "dispatch.hpp"
 
 struct sos_batch_s {
   int C = 0, N = 0, io_dtype = SOS_F32, compute_dtype = SOS_F64;
   int kmax = 0, mix = SOS_PH;
   int32_t tile_groups = 0;
   bool b0one = true, host_only = false;
+  bool block = false;                     // block-filtering channels (SOS_BLOCK plans)
+  int block_pt = 0;                       // their product type
   int device = -1;
   int64_t total = 0, items = 0;
   std::vector<int64_t> n, off, tile;
@@ -46,4 +49,7 @@ bool batch_descriptors_valid(const sos_batch_s &b);
 namespace sosf {
 // the adjoint schedule, host side (sosfilt_backward.hip)
 sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups);
+// batched block filtering (sosfilt_block.hip)
+Residency block_batched_residency(int io_dtype, int pt, int kmax);
+sos_status launch_block_batched(const sos_batch_s &b, const void *x, void *y, hipStream_t s);
 }

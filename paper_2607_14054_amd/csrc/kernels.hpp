@@ -469,8 +469,9 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_kernel(
 // item_chan[i], and the channels are ordered so that costly items come
 // first.
 struct BatchChan {
-  const void *tab;          // the channel plan's device table (compute dtype)
+  const void *tab;          // the channel plan's device table (compute dtype; block filtering: its block table)
   const int32_t *solver;    // device [K]
+  const void *aop;          // block filtering: the MFMA A operands of the channel's Toeplitz products
   int64_t off, n;           // first sample in x / y, length
   int64_t tile, warm;       // samples per row tile and of run-in (multiples of the group)
   int64_t first_item;       // the channel's first wave item

@@ -93,44 +93,30 @@ __device__ __forceinline__ void store4(double *p, const double (&V)[4]) {
   __builtin_nontemporal_store(v, reinterpret_cast<vd2 *>(p) + 1);
 }
 
+// One wavefront's tile: samples [t0, t0 + tile) of a signal of n samples,
+// after a run-in over the warm samples before t0 (samples outside [0, n)
+// read as zero and are not stored).  g_s, a_s: the sections' correction
+// rows and MFMA A operands in LDS; st: the wavefront's 2 + 2K carries (the
+// raw input's last two samples, then each section's last two outputs).
 template <typename TI, int PT>
-__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
-    const TI *__restrict__ x, TI *__restrict__ y, const double *__restrict__ bt,
-    const void *__restrict__ aop, BlockArgs a) {
+__device__ __forceinline__ void block_rows(const TI *__restrict__ x, TI *__restrict__ y, const double *__restrict__ bt,
+                                           const double *g_s, const unsigned char *a_s, double *st, int64_t n,
+                                           int64_t t0, int64_t tile, int64_t warm, int K) {
   typedef double T;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // LDS: the block's copies of the per-lane correction rows and of the MFMA
-  // A operands (every wavefront reads all of them once per group), then the
-  // carries of each wavefront
-  constexpr int AOP = PT == PT_F64 ? 256 * 8 : 256 * 2;   // A-operand bytes per section
-  double *g_s = reinterpret_cast<double *>(smem);   // per section: G (64), then HT (32)
-  unsigned char *a_s = smem + (size_t)a.K * 96 * sizeof(double);
-  for (int i = threadIdx.x; i < a.K * 96; i += kWavesPerBlock * 64)
-    g_s[i] = bt[(int64_t)(i / 96) * kBlockStride + BT_G + (i % 96)];
-  for (int i = threadIdx.x; i < a.K * AOP / 16; i += kWavesPerBlock * 64)
-    reinterpret_cast<vf4 *>(a_s)[i] = reinterpret_cast<const vf4 *>(aop)[i];
-  __syncthreads();
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
-  if (wave >= a.ntiles) return;
   const int lane = lane_id(), q = lane >> 4, j = lane & 15;
-  // carries (uniform per wavefront): the raw input's last two samples, then
-  // each section's last two outputs
-  T *st = reinterpret_cast<T *>(a_s + (size_t)a.K * AOP) + w * (2 + 2 * a.K);
-  for (int i = 0; i < 2 + 2 * a.K; ++i) st[i] = T(0);
+  for (int i = 0; i < 2 + 2 * K; ++i) st[i] = T(0);
   const ctab<T> cb = as_ctab(bt);
-  const int64_t t0 = wave * a.tile;
-  const int64_t steps = (a.warm + a.tile) / kBlockGroup;
+  const int64_t steps = (warm + tile) / kBlockGroup;
   const int src_prev = 48 + ((j + 15) & 15);   // lane (3, j - 1)
   for (int64_t it = 0; it < steps; ++it) {
-    const int64_t g = t0 - a.warm + it * kBlockGroup;
+    const int64_t g = t0 - warm + it * kBlockGroup;
     const int64_t e0 = g + 16 * j + 4 * q;   // this lane's 4 consecutive samples
     T V[4];
-    if (e0 >= 0 && e0 + 4 <= a.n) {
+    if (e0 >= 0 && e0 + 4 <= n) {
       load4(V, x + e0);
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) V[i] = (e0 + i >= 0 && e0 + i < a.n) ? T(x[e0 + i]) : T(0);
+      for (int i = 0; i < 4; ++i) V[i] = (e0 + i >= 0 && e0 + i < n) ? T(x[e0 + i]) : T(0);
     }
     // the raw input's two samples before block j: lane (3, j - 1), or the carry
     T xb2 = __shfl(V[2], src_prev), xb1 = __shfl(V[3], src_prev);
@@ -140,7 +126,7 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
     }
     const T nraw2 = __shfl(V[2], 63), nraw1 = __shfl(V[3], 63);
     if (PT == PT_F64) row_transpose4(V);   // to the FP64 MFMA layout, m = q + 4 r
-    for (int k = 0; k < a.K; ++k) {
+    for (int k = 0; k < K; ++k) {
       const ctab<T> c = cb + (int64_t)k * kBlockStride;
       T P[4];
       if (PT == PT_F64) {
@@ -220,15 +206,75 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
     st[1] = nraw1;
     if (g >= t0) {
       if (PT == PT_F64) row_transpose4(V);   // back to 4 consecutive samples per lane
-      if (e0 >= 0 && e0 + 4 <= a.n) {
+      if (e0 >= 0 && e0 + 4 <= n) {
         store4(y + e0, V);
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (e0 + i >= 0 && e0 + i < a.n) y[e0 + i] = (TI)V[i];
+          if (e0 + i >= 0 && e0 + i < n) y[e0 + i] = (TI)V[i];
       }
     }
   }
+}
+
+template <typename TI, int PT>
+__host__ __device__ constexpr int block_aop_bytes() {
+  return PT == PT_F64 ? 256 * 8 : 256 * 2;   // A-operand bytes per section
+}
+
+// Stage the correction rows and A operands of K sections into LDS.
+template <int PT>
+__device__ __forceinline__ void block_stage_tables(const double *__restrict__ bt, const void *__restrict__ aop, int K,
+                                                   double *g_s, unsigned char *a_s) {
+  constexpr int AOP = block_aop_bytes<float, PT>();
+  for (int i = threadIdx.x; i < K * 96; i += kWavesPerBlock * 64)
+    g_s[i] = bt[(int64_t)(i / 96) * kBlockStride + BT_G + (i % 96)];
+  for (int i = threadIdx.x; i < K * AOP / 16; i += kWavesPerBlock * 64)
+    reinterpret_cast<vf4 *>(a_s)[i] = reinterpret_cast<const vf4 *>(aop)[i];
+}
+
+// Single signal: wavefront w takes tile w.
+template <typename TI, int PT>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
+    const TI *__restrict__ x, TI *__restrict__ y, const double *__restrict__ bt,
+    const void *__restrict__ aop, BlockArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  // LDS: the block's copies of the per-lane correction rows and of the MFMA
+  // A operands (every wavefront reads all of them once per group), then the
+  // carries of each wavefront
+  constexpr int AOP = block_aop_bytes<TI, PT>();
+  double *g_s = reinterpret_cast<double *>(smem);   // per section: G (64), then HT (32)
+  unsigned char *a_s = smem + (size_t)a.K * 96 * sizeof(double);
+  block_stage_tables<PT>(bt, aop, a.K, g_s, a_s);
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
+  if (wave >= a.ntiles) return;
+  double *st = reinterpret_cast<double *>(a_s + (size_t)a.K * AOP) + w * (2 + 2 * a.K);
+  block_rows<TI, PT>(x, y, bt, g_s, a_s, st, a.n, wave * a.tile, a.tile, a.warm, a.K);
+}
+
+// Batches: one workgroup per work item, four tiles of one channel (one per
+// wavefront), so that the workgroup stages that channel's tables only.  The
+// channel's tiles cover [-shift, n), which puts every 4-sample vector of x
+// and y on a 16-byte boundary.
+template <typename TI, int PT>
+__global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_batched_kernel(
+    const TI *__restrict__ x, TI *__restrict__ y, const BatchChan *__restrict__ chans,
+    const int32_t *__restrict__ item_chan, int32_t kmax) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  constexpr int AOP = block_aop_bytes<TI, PT>();
+  const BatchChan &ch = chans[item_chan[blockIdx.x]];
+  double *g_s = reinterpret_cast<double *>(smem);
+  unsigned char *a_s = smem + (size_t)kmax * 96 * sizeof(double);
+  block_stage_tables<PT>(static_cast<const double *>(ch.tab), ch.aop, ch.K, g_s, a_s);
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int64_t tile_index = ((int64_t)blockIdx.x - ch.first_item) * kWavesPerBlock + w;
+  if (tile_index * ch.tile >= ch.n + ch.shift) return;
+  double *st = reinterpret_cast<double *>(a_s + (size_t)kmax * AOP) + w * (2 + 2 * kmax);
+  block_rows<TI, PT>(x + ch.off, y + ch.off, static_cast<const double *>(ch.tab), g_s, a_s, st, ch.n,
+                     tile_index * ch.tile - ch.shift, ch.tile, ch.warm, ch.K);
 }
 
 }  // namespace sosf

@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "plan.hpp"
 #include "batch.hpp"
+#include "kernels_block.hpp"
 
 using namespace sosf;
 
@@ -38,7 +39,8 @@ struct ChanWork {
 // a long run-in (poles near the unit circle) needs the short tiles for
 // parallelism even at the cost of run-in many times its tile.  Ties go to
 // the longer tile.
-int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t waves_per_simd) {
+int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t waves_per_simd,
+                          int64_t waves_per_item = 1) {
   int64_t best_tg = 8;
   double best = -1.0;
   for (int e = 12; e >= 0; --e) {
@@ -50,7 +52,7 @@ int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t
       const int64_t tgc = (c.groups + 4 * quads - 1) / (4 * quads);
       const int64_t wc = std::min<int64_t>(c.warm_groups, (c.groups - 1) / tgc * tgc);
       const double item = (double)c.K * (double)(tgc + wc);
-      total += (double)quads * item;
+      total += (double)(quads * waves_per_item) * item;
       longest = std::max(longest, item);
     }
     const double a = total / (double)std::max<int64_t>(simds, 1), b = longest * (double)waves_per_simd;
@@ -104,8 +106,10 @@ sos_status validate(const sos_plan_t *plans, int32_t C, const int64_t *n, bool h
     const sos_plan_s *p = plans[c];
     if (!p || n[c] < 0) return SOS_E_ARG;
     if (!host_only && !p->d_table) return SOS_E_ARG;   // a host-only plan cannot filter
-    if (p->solver_opt == SOS_PH_DEFERRED || p->solver_opt == SOS_SCALAR || p->solver_opt == SOS_BLOCK)
-      return SOS_E_UNSUPPORTED;
+    if (p->solver_opt == SOS_PH_DEFERRED || p->solver_opt == SOS_SCALAR) return SOS_E_UNSUPPORTED;
+    // block filtering batches only with block filtering (its own kernel)
+    if ((p->solver_opt == SOS_BLOCK) != (plans[0]->solver_opt == SOS_BLOCK)) return SOS_E_UNSUPPORTED;
+    if (!host_only && p->solver_opt == SOS_BLOCK && (!p->d_block || !p->d_aop)) return SOS_E_ARG;
     if (p->N != plans[0]->N || p->io_dtype != plans[0]->io_dtype ||
         p->compute_dtype != plans[0]->compute_dtype)
       return SOS_E_UNSUPPORTED;
@@ -149,7 +153,10 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
     }
   }
   const size_t esz = b.io_dtype == SOS_F64 ? 8 : 4;
-  const int64_t G = (int64_t)b.N * kL;
+  // block filtering: its own kernel, tiles in groups of 16 blocks
+  b.block = plans[0]->solver_opt == SOS_BLOCK;
+  b.block_pt = plans[0]->block_pt;
+  const int64_t G = b.block ? (int64_t)kBlockGroup : (int64_t)b.N * kL;
   for (int c = 0; c < C; ++c) b.total = std::max(b.total, b.off[c] + n[c]);
   // each channel's solver class: SOS_CR or SOS_PH when all its sections use
   // that solver, SOS_AUTO otherwise; the batch takes a specialised kernel
@@ -168,19 +175,25 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   for (int c = 1; c < C; ++c)
     if (cls[c] != b.mix) b.mix = SOS_AUTO;
   Residency res;
-  if (!b.host_only)
+  if (!b.host_only && b.block)
+    res = block_batched_residency(b.io_dtype, b.block_pt, b.kmax);
+  else if (!b.host_only)
     dispatch_rows<ResidencyBatched>(b.N, b.io_dtype, b.compute_dtype, b.b0one, b.mix, b.kmax, &res);
   // a channel whose first sample is off a 16-byte boundary is filtered over
   // [-shift, n): the shift samples before it read as zeros (zero state stays
-  // zero) and are not stored, and every group then starts on a boundary
-  const int64_t V = 16 / (int64_t)esz;
+  // zero) and are not stored, and every group then starts on a boundary.
+  // Block filtering moves 4 samples per lane (16 or 32 bytes).
+  const int64_t V = b.block ? 4 : 16 / (int64_t)esz;
   std::vector<int32_t> shift(C, 0);
   std::vector<ChanWork> work(C);
   for (int c = 0; c < C; ++c) {
     shift[c] = (int32_t)(b.off[c] % V);
     work[c] = ChanWork{n[c] == 0 ? 0 : (n[c] + shift[c] + G - 1) / G, plans[c]->warm / G, plans[c]->K};
   }
-  const int64_t tg = tile_groups > 0 ? tile_groups : batch_tile_groups(work, res.simds, res.waves_per_simd);
+  // an item is four row tiles in one wavefront, or (block filtering) four
+  // tiles in the four wavefronts of a workgroup
+  const int64_t tg = tile_groups > 0 ? tile_groups
+                                     : batch_tile_groups(work, res.simds, res.waves_per_simd, b.block ? 4 : 1);
   // per-channel tiles: quads of four row tiles under the cap, as even as
   // the length allows
   b.tile.assign(C, 0);
@@ -209,7 +222,8 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
     const int32_t c = b.order[i];
     const sos_plan_s *p = plans[c];
     BatchChan &ch = b.chans[i];
-    ch.tab = p->d_table;
+    ch.tab = b.block ? p->d_block : p->d_table;
+    ch.aop = b.block ? p->d_aop : nullptr;
     ch.solver = static_cast<const int32_t *>(p->d_solver);
     ch.off = b.off[c];
     ch.n = n[c];
@@ -281,7 +295,8 @@ void point(sos_batch_s &b, const BlobLayout &l) {
 // Capacity for channel sets of up to C channels and `samples` samples in
 // all: tiles of at least one group give at most total / (4 G) + 2 C items.
 size_t capacity_bytes(const sos_batch_s &b, int64_t C, int64_t samples) {
-  const int64_t G = (int64_t)b.N * kL, Gb = (int64_t)kBwdN * kL;
+  const int64_t G = b.block ? std::min<int64_t>((int64_t)b.N * kL, kBlockGroup) : (int64_t)b.N * kL;
+  const int64_t Gb = (int64_t)kBwdN * kL;
   const int64_t items = samples / (4 * G) + 2 * C + 1, adj_items = (samples + 3 * C) / (4 * Gb) + 2 * C + 1;
   return blob_layout((size_t)C, (size_t)items, (size_t)adj_items, (size_t)C * SOS_MAX_SECTIONS).bytes;
 }
@@ -362,7 +377,8 @@ sos_status sos_batch_replan(sos_batch_t b, const sos_plan_t *plans, int32_t C, c
   if (!b) return SOS_E_ARG;
   sos_status st = validate(plans, C, n, b->host_only);
   if (st != SOS_OK) return st;
-  if (plans[0]->N != b->N || plans[0]->io_dtype != b->io_dtype || plans[0]->compute_dtype != b->compute_dtype)
+  if (plans[0]->N != b->N || plans[0]->io_dtype != b->io_dtype || plans[0]->compute_dtype != b->compute_dtype ||
+      (plans[0]->solver_opt == SOS_BLOCK) != b->block)
     return SOS_E_UNSUPPORTED;
   // schedule into a copy, so that an invalid request leaves the batch as it was
   sos_batch_s t;
@@ -425,6 +441,7 @@ sos_status sos_filt_batched(sos_batch_t b, const void *x, void *y, void *workspa
   if (xb < yb + bytes && yb < xb + bytes) return SOS_E_ARG;   // overlap
   if ((xb | yb) & 15) return SOS_E_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (b->block) return launch_block_batched(*b, x, y, s);
   return dispatch_rows<LaunchBatched>(b->N, b->io_dtype, b->compute_dtype, b->b0one, b->mix, *b, x, y, s);
 }
 

@@ -10,6 +10,7 @@
 #include "dispatch.hpp"
 #include "kernels_block.hpp"
 #include "plan.hpp"
+#include "batch.hpp"
 
 using namespace sosf;
 
@@ -221,6 +222,42 @@ sos_status launch_block(const sos_plan_s &p, const void *x, void *y, int64_t n, 
   void *args[] = {&xa, &ya, &ta, &aa, &a};   // addresses of the kernel's five arguments
   if (hipLaunchKernel(block_kernel(p), dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), args, block_lds(p), s) !=
       hipSuccess)
+    return SOS_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+}
+
+// Batches of block-filtering channels (sosfilt_batch.hip schedules them):
+// one workgroup per item of four tiles, the channel's tables in LDS.
+namespace {
+template <typename TI, int PT>
+const void *block_batched_ptr() {
+  return reinterpret_cast<const void *>(&sos_block_batched_kernel<TI, PT>);
+}
+const void *block_batched_kernel(int io_dtype, int pt) {
+  const bool f32 = io_dtype == SOS_F32;
+  switch (pt) {
+    case PT_F16: return f32 ? block_batched_ptr<float, PT_F16>() : block_batched_ptr<double, PT_F16>();
+    case PT_BF16: return f32 ? block_batched_ptr<float, PT_BF16>() : block_batched_ptr<double, PT_BF16>();
+    default: return f32 ? block_batched_ptr<float, PT_F64>() : block_batched_ptr<double, PT_F64>();
+  }
+}
+size_t block_batched_lds(int kmax, int pt) {
+  const size_t aop = pt == PT_F64 ? 256 * 8 : 256 * 2;
+  return (size_t)kmax * (96 * sizeof(double) + aop) + (size_t)kWavesPerBlock * (2 + 2 * kmax) * sizeof(double);
+}
+}  // namespace
+
+Residency block_batched_residency(int io_dtype, int pt, int kmax) {
+  return residency_of(block_batched_kernel(io_dtype, pt), block_batched_lds(kmax, pt), kWavesPerBlock * 64);
+}
+
+sos_status launch_block_batched(const sos_batch_s &b, const void *x, void *y, hipStream_t s) {
+  const void *xa = x, *ca = b.d_chans, *ia = b.d_item_chan;
+  void *ya = y;
+  int32_t kmax = b.kmax;
+  void *args[] = {&xa, &ya, &ca, &ia, &kmax};   // addresses of the kernel's five arguments
+  if (hipLaunchKernel(block_batched_kernel(b.io_dtype, b.block_pt), dim3((unsigned)b.items),
+                      dim3(kWavesPerBlock * 64), args, block_batched_lds(b.kmax, b.block_pt), s) != hipSuccess)
     return SOS_E_DEVICE;
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }

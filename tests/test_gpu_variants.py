@@ -118,3 +118,96 @@ def test_low_precision_only_with_block():
     with pytest.raises(S.SosError) as e:
         S.Plan(W.make_sos(17, 0.5, 0.9, 69), io_dtype="f32", solver="scalar")
     assert e.value.code == S.SOS_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype,io", [("f64", "f64"), ("f64", "f32"), ("f16", "f32"), ("bf16", "f32")])
+def test_block_batched_ragged_shifted_channels(dtype, io):
+    """Block filtering in one batched launch: ragged lengths around whole
+    256-sample groups, K from 1 to 12, channels starting 0..3 samples past a
+    4-sample boundary with gaps between them.  Each channel matches the
+    oracle at the single-channel bars (FP64 products); with FP16 / BF16
+    products, whose error depends on the draw, each channel's error is
+    within twice that of the same plan launched on the channel alone (the
+    tile boundaries differ).  The gap samples keep their value."""
+    dt = np.float64 if io == "f64" else np.float32
+    lengths = [1, 3, 255, 256, 257, 1000, 4099, 70001, 2 ** 18 + 5]
+    offsets, pos = [], 0
+    for i, n in enumerate(lengths):
+        pos = (pos + 3) // 4 * 4 + i % 4
+        offsets.append(pos)
+        pos += n + 1 + i % 3
+    Ks = [1 + (3 * c) % 12 for c in range(len(lengths))]
+    sos = [W.make_sos(k, 0.5, 0.95, 400 + c) for c, k in enumerate(Ks)]
+    plans = [S.Plan(s_, io_dtype=io, compute_dtype=dtype, solver="block") for s_ in sos]
+    b = S.Batch(plans, lengths, offsets=offsets)
+    xs = [W.make_signal(n, 401 + c, dt) for c, n in enumerate(lengths)]
+    xb = np.zeros(b.total, dt)
+    for c, o in enumerate(offsets):
+        xb[o:o + lengths[c]] = xs[c]
+    y0 = torch.full((b.total,), -5.0, dtype=torch.float64 if io == "f64" else torch.float32, device=DEV)
+    y = S.filt_batched(b, torch.from_numpy(xb).to(DEV), y0)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    mask = np.ones(b.total, bool)
+    for c, o in enumerate(offsets):
+        n = lengths[c]
+        mask[o:o + n] = False
+        ref = oracle.sosfilt(xs[c].astype(np.float64), sos[c])
+        err = oracle.rel_rms(y[o:o + n], ref)
+        if dtype == "f64":
+            assert err < (1e-12 if io == "f64" else 1e-6), (c, n, err)
+        else:
+            assert np.all(np.isfinite(y[o:o + n]))
+            alone = S.filt(plans[c], torch.from_numpy(xs[c]).to(DEV))
+            torch.cuda.synchronize()
+            err_alone = oracle.rel_rms(alone.cpu().numpy(), ref)
+            print("c=%d n=%d K=%d %s batched %.3e alone %.3e" % (c, n, Ks[c], dtype, err, err_alone))
+            assert err <= 2 * err_alone + 1e-7, (c, n, err, err_alone)
+    assert np.all(y[mask] == -5.0)
+
+
+def test_block_batched_precision_config_channels():
+    """The precision workload's shape (r up to 0.999, K = 8; run-ins of tens
+    of thousands of samples) on 8 channels of 2^18 samples, FP64 products:
+    the batch's tiles, each several run-ins long, give the oracle's result
+    within max(1e-12, 4x the FP64 oracle's own error), or within 1.5x of the
+    same plan launched on the channel alone where the block method's own
+    FP64 rounding is larger at these poles."""
+    C, n = 8, 2 ** 18
+    sos = [W.make_sos(8, 0.9, 0.999, 410 + c) for c in range(C)]
+    plans = [S.Plan(s_, io_dtype="f64", compute_dtype="f64", solver="block") for s_ in sos]
+    b = S.Batch(plans, [n] * C)
+    xs = [W.make_signal(n, 411 + c, np.float64) for c in range(C)]
+    y = S.filt_batched(b, torch.from_numpy(np.concatenate(xs)).to(DEV))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    for c in range(C):
+        ld = oracle.sosfilt_ld(xs[c], sos[c])
+        err, own = oracle.rel_rms(y[c * n:(c + 1) * n], ld), oracle.rel_rms(oracle.sosfilt(xs[c], sos[c]), ld)
+        alone = S.filt(plans[c], torch.from_numpy(xs[c]).to(DEV))
+        torch.cuda.synchronize()
+        err_alone = oracle.rel_rms(alone.cpu().numpy(), ld)
+        print("c=%d batched %.3e alone %.3e oracle %.3e" % (c, err, err_alone, own))
+        assert err <= max(1e-12, 4 * own, 1.5 * err_alone), (c, err, err_alone, own)
+
+
+def test_block_batches_keep_their_kind():
+    """Block and PH plans do not mix in a batch, and a block batch replans
+    only with block plans."""
+    sos = W.make_sos(2, 0.5, 0.9, 420)
+    pb = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="block")
+    pp = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="ph")
+    with pytest.raises(S.SosError) as e:
+        S.Batch([pb, pp], [100, 100])
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    b = S.Batch([pb], [1000], max_channels=4, max_samples=10000)
+    with pytest.raises(S.SosError) as e:
+        b.replan([pp], [1000])
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    b.replan([pb, pb], [3000, 5000])
+    x = W.make_signal(8000, 421, np.float32)
+    y = S.filt_batched(b, torch.from_numpy(x).to(DEV))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    assert oracle.rel_rms(y[:3000], oracle.sosfilt(x[:3000], sos)) < 1e-6
+    assert oracle.rel_rms(y[3000:], oracle.sosfilt(x[3000:], sos)) < 1e-6

@@ -333,6 +333,12 @@ def test_batch_rejections():
     with pytest.raises(S.SosError) as e:
         S.Batch(mixed_io, [10, 10], host_only=True)
     assert e.value.code == S.SOS_E_UNSUPPORTED
+    block_ph = [S.Plan(W.make_sos(2, 0.5, 0.9, 0), N=32, solver=s_, host_only=True) for s_ in ("block", "ph")]
+    with pytest.raises(S.SosError) as e:
+        S.Batch(block_ph, [10, 10], host_only=True)
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    blocks = S.Batch(block_ph[:1] * 3, [10, 700, 70000], host_only=True)
+    assert blocks.query()["total"] == 70710
     phd = [S.Plan(W.make_sos(2, 0.5, 0.9, 0), N=32, solver="phd", host_only=True)]
     with pytest.raises(S.SosError) as e:
         S.Batch(phd, [10], host_only=True)
