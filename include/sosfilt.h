@@ -330,10 +330,12 @@ sos_status sos_filt_batched(sos_batch_t batch, const void *x, void *y, void *wor
  *  - recompute: the forward pass stores the cascade state (2K + 2 values)
  *    at every group of 256 samples, and the adjoint recomputes section k's
  *    input from the group's state (K(K-1)/2 + 1 forward section passes per
- *    group).
+ *    group).  With FP32 I/O and 4 <= K <= 17 it also keeps section K/2's
+ *    input per group in LDS, and recomputes later inputs from it.
  * Measured costs per sample on MI355X are 3.74 + 4.00 K ps (saved) and
- * 4.48 + 1.36 K + 0.38 (K(K-1)/2 + 1) ps (recompute), so without a flag a
- * plan recomputes for K <= 14.
+ * 4.48 + 1.36 K + 0.38 P ps (recompute, P passes per group; 6.68 + 1.63 K
+ * + 0.319 P with the kept input).  So without a flag a plan recomputes for
+ * K <= 17 with FP32 I/O and K <= 14 with FP64 I/O.
  *
  * sos_backward_workspace_size -- device bytes sos_filt_backward needs for n
  * samples: the saved outputs (K n doubles, padded) or the group states

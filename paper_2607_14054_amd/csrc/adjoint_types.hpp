@@ -12,6 +12,7 @@ struct AdjView {
   int64_t n, np, tile, warm, ntiles, sstride;
   int64_t shift;            // forward tiles cover [-shift, n); saved arrays start shift elements in
   int64_t nck;              // recompute mode: group checkpoints, one per group of [-shift, np)
+  int64_t stash;            // recompute mode: S > 0 keeps u_S per group in LDS (0: none)
   int32_t K, stride;
 };
 
@@ -27,6 +28,7 @@ struct AdjChan {
   int64_t partial_off;      // doubles into the workspace (ntiles x 5K)
   int64_t sstride;
   int64_t nck;              // recompute mode: group checkpoints (see AdjView)
+  int64_t stash;            // recompute mode: stashed section input (see AdjView)
   int32_t K, stride;
   int32_t shift;            // forward tiles cover [-shift, n) (see AdjView)
   int32_t gsos_row;         // first row of the channel in gsos

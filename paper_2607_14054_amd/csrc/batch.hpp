@@ -27,6 +27,7 @@ struct sos_batch_s {
   int32_t *d_item_chan = nullptr;
   // adjoint schedule (device batches whose plans carry the adjoint)
   bool adj = false, adj_b0one = true, adj_rc = false;   // adj_rc: recompute mode
+  bool adj_stash = false;                 // recompute mode: the stash fits (per channel with K >= 4)
   int64_t adj_items = 0, adj_rows = 0;    // wave items; rows of gsos (sum of K)
   size_t adj_ws = 0;                      // workspace bytes
   std::vector<int64_t> adj_gsos_row;      // per channel (caller order): first gsos row

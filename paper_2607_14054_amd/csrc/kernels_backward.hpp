@@ -26,6 +26,8 @@
 //    traffic.
 #pragma once
 
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "adjoint_types.hpp"
 
@@ -151,6 +153,7 @@ struct BwdArgs {
   int64_t sstride;          // elements between saved section outputs
   int64_t shift;            // forward tiles cover [-shift, n)
   int64_t nck;              // recompute mode: group checkpoints
+  int64_t stash;            // recompute mode: stashed section input (0: none)
   int32_t K, stride;
 };
 
@@ -215,15 +218,23 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
 // in turn (no copies between steps).
 // st: 7K values (2K all-pole output states, then 5K running sums); RC adds
 // the group's checkpoint and a working copy of it (2 + 2K each).
+// RC with v.stash = S > 0: the first pass of a group leaves u_S (forward
+// layout) in the row's stash, one FP64 group in LDS, and u_k for k > S is
+// recomputed from it (k - S passes instead of k).  rowbuf: the row's stage,
+// FP64 in the saved-output mode (which reads FP64 groups), else of the I/O
+// type.
 template <int N, typename TI, bool B0ONE, bool RC>
 __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__restrict__ gx,
                                              const TI *__restrict__ x, const double *__restrict__ saved,
                                              ctab<double> ct, ctab<double> cb, double *__restrict__ sums,
                                              const AdjView &v, int64_t tile_index, bool aligned,
-                                             double *st, unsigned char *rowbuf) {
+                                             double *st, unsigned char *rowbuf, double *stash) {
   typedef double T;
   TI *buf = reinterpret_cast<TI *>(rowbuf);
   double *dbuf = reinterpret_cast<double *>(rowbuf);
+  const int S = RC ? (int)v.stash : 0;
+  constexpr int SRUN = Stage<N, double>::RUN;   // stash doubles per lane (padded)
+  double *my_stash = stash + row_lane() * SRUN;
   T *acc = st + 2 * v.K;
   const int SE = state_elems(v.K);
   T *ck = st + 7 * v.K, *cw = ck + SE;   // RC: checkpoint, working copy
@@ -238,26 +249,51 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   bool full = false, live = false;
 
   // RC: F = the group's forward-time input through sections 0 .. upto-1
-  // (from the checkpoint); the chain's input state is left in xs2, xs1
+  // (from the checkpoint; capture: leave u_S in the stash on the way); the
+  // chain's input state is left in xs2, xs1
   T xs2 = T(0), xs1 = T(0);
-  auto forward = [&](int upto) {
+  auto forward = [&](int upto, bool capture) {
     stage_to_regs<N, TI, T>(F, buf);
     for (int i = row_lane(); i < SE; i += kL) cw[i] = ck[i];
     __builtin_amdgcn_wave_barrier();
     xs2 = cw[0];
     xs1 = cw[1];
-    for (int q = 0; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
+    for (int q = 0; q < upto; ++q) {
+      ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
+      if (capture && q + 1 == S) {
+#pragma unroll
+        for (int m = 0; m < N; m += 2) *reinterpret_cast<vd2 *>(my_stash + m) = vd2{F[m], F[m + 1]};
+      }
+    }
+  };
+  // RC: F = u_S from the stash through sections S .. upto-1
+  auto forward_from_stash = [&](int upto) {
+#pragma unroll
+    for (int m = 0; m < N; m += 2) {
+      const vd2 p = *reinterpret_cast<const vd2 *>(my_stash + m);
+      F[m] = p[0];
+      F[m + 1] = p[1];
+    }
+    for (int i = row_lane(); i < SE; i += kL) cw[i] = ck[i];
+    __builtin_amdgcn_wave_barrier();
+    xs2 = cw[2 * S];       // section S-1's last two outputs before the group
+    xs1 = cw[2 * S + 1];
+    for (int q = S; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
   };
   // U = u_k in reversed time
   auto input_of = [&](int k, T (&U)[N]) {
-    if (RC) {
-      forward(k);
+    if constexpr (RC) {
+      if (S > 0 && k >= S)
+        forward_from_stash(k);
+      else
+        forward(k, false);
       to_reversed<N>(U, F);
       __builtin_amdgcn_wave_barrier();
-    } else if (k == 0) {
-      load_group_rev<N, TI, T>(U, x, g, v.n, v.np, full, buf);
     } else {
-      load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * v.sstride, g, v.n, v.np, full, dbuf);
+      if (k == 0)
+        load_group_rev<N, TI, T>(U, x, g, v.n, v.np, full, buf);
+      else
+        load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * v.sstride, g, v.n, v.np, full, dbuf);
     }
   };
   // the adjoint of section k on X, with U = u_k, W = w_k
@@ -319,7 +355,7 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
     load_group_rev<N, TI, T>(X, gy, g, v.n, v.np, full, buf);
     if (live) {
       // A = u_{K-1}, B = w_{K-1}
-      if (RC) {
+      if constexpr (RC) {
         // the group covers forward samples [np - g - G, np - g): its input in
         // forward order (kept in the row's stage until the group's gx is
         // stored) and the state the cascade enters it with
@@ -327,7 +363,7 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
         const int64_t j = g / G;
         for (int i = row_lane(); i < SE; i += kL) ck[i] = j < v.nck ? saved[j * SE + i] : T(0);
         __builtin_amdgcn_wave_barrier();
-        forward(v.K - 1);
+        forward(v.K - 1, S > 0);
         to_reversed<N>(A, F);
         ph_section<N, T, B0ONE>(F, ct + (int64_t)(v.K - 1) * v.stride, xs2, xs1, cw + 2 + 2 * (v.K - 1));
         to_reversed<N>(B, F);
@@ -356,6 +392,30 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
 // in recompute mode the group's checkpoint and its working copy.
 __host__ __device__ constexpr int adj_row_elems(int K, bool rc) { return 7 * K + (rc ? 2 * state_elems(K) : 0); }
 
+// LDS of the adjoint pass per workgroup: the rows' stages (FP64 in the
+// saved-output mode, the I/O type in recompute mode), then the rows' states
+// (adj_row_elems each), then, with a stash, one padded FP64 group per row.
+template <int N, typename TI, bool RC>
+struct AdjLds {
+  typedef typename std::conditional<RC, TI, double>::type SI;
+  static constexpr int ROWBUF_BYTES = Stage<N, SI>::ROWBUF * (int)sizeof(SI);
+  static constexpr int STAGE_BYTES = kWavesPerBlock * kRows * ROWBUF_BYTES;
+  static constexpr int STASH_ROW = Stage<N, double>::ROWBUF;   // doubles per row
+  static __host__ __device__ constexpr size_t bytes(int kmax, bool stash) {
+    return (size_t)STAGE_BYTES + (size_t)kWavesPerBlock * kRows * adj_row_elems(kmax, RC) * sizeof(double) +
+           (stash ? (size_t)kWavesPerBlock * kRows * STASH_ROW * sizeof(double) : 0);
+  }
+  // row r (0 .. 15) of the workgroup
+  static __device__ unsigned char *rowbuf(unsigned char *smem, int r) { return smem + r * ROWBUF_BYTES; }
+  static __device__ double *states(unsigned char *smem, int r, int kmax) {
+    return reinterpret_cast<double *>(smem + STAGE_BYTES) + r * adj_row_elems(kmax, RC);
+  }
+  static __device__ double *stash(unsigned char *smem, int r, int kmax) {
+    return reinterpret_cast<double *>(smem + STAGE_BYTES) + kWavesPerBlock * kRows * adj_row_elems(kmax, RC) +
+           r * STASH_ROW;
+  }
+};
+
 __device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
   AdjView v;
   v.n = a.n;
@@ -366,6 +426,7 @@ __device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
   v.sstride = a.sstride;
   v.shift = a.shift;
   v.nck = a.nck;
+  v.stash = a.stash;
   v.K = a.K;
   v.stride = a.stride;
   return v;
@@ -401,11 +462,11 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
   if (wave * kRows >= a.ntiles) return;
   const int row = lane_id() >> 4;
   const int64_t tile_index = wave * kRows + row;
-  double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
-               (int64_t)(w * kRows + row) * adj_row_elems(a.K, RC);
-  unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  typedef AdjLds<N, TI, RC> Lds;
+  const int r = w * kRows + row;
   adjoint_rows<N, TI, B0ONE, RC>(gy, gx, x, saved, as_ctab(tab), as_ctab(bwd), partials + tile_index * 5 * a.K,
-                                 adj_view(a), tile_index, true, st, rowbuf);
+                                 adj_view(a), tile_index, true, Lds::states(smem, r, a.K), Lds::rowbuf(smem, r),
+                                 Lds::stash(smem, r, a.K));
 }
 
 __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
@@ -418,6 +479,7 @@ __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
   v.sstride = c.sstride;
   v.shift = c.shift;
   v.nck = c.nck;
+  v.stash = c.stash;
   v.K = c.K;
   v.stride = c.stride;
   return v;
@@ -453,12 +515,12 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_batched_
   const AdjChan &c = chans[item_chan[item]];
   const int row = lane_id() >> 4;
   const int64_t tile_index = (item - c.first_item) * kRows + row;
-  double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
-               (int64_t)(w * kRows + row) * adj_row_elems(kmax, RC);
-  unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
+  typedef AdjLds<N, TI, RC> Lds;
+  const int r = w * kRows + row;
   adjoint_rows<N, TI, B0ONE, RC>(gy + c.off, gx + c.off, x + c.off, ws + c.saved_off, as_ctab(c.tab),
                                  as_ctab(c.bwd), ws + c.partial_off + tile_index * 5 * c.K, adj_view(c),
-                                 tile_index, true, st, rowbuf);
+                                 tile_index, true, Lds::states(smem, r, kmax), Lds::rowbuf(smem, r),
+                                 Lds::stash(smem, r, kmax));
 }
 
 // dL/d(sos) from the per-tile sums of one section: the block sums

@@ -85,7 +85,8 @@ void build_deferred_tables(sos_plan_s &p);
 sos_status attach_adjoint(sos_plan_s &p, const double *sos);
 bool adjoint_recompute(const sos_plan_s &p);
 double adjoint_cost_saved(int K);
-double adjoint_cost_recompute(int K);
+double adjoint_cost_recompute(int K, bool stash);
+bool adjoint_stash(bool rc, int io_dtype, int kmax);
 // block filtering plans (sosfilt_block.hip)
 sos_status build_block_plan(sos_plan_s &p);
 sos_status upload_block_plan(sos_plan_s &p);

@@ -43,18 +43,34 @@ sos_status attach_adjoint(sos_plan_s &p, const double *sos) {
   return SOS_OK;
 }
 
+// The recompute mode's stash of u_S, S = K/2: with FP32 I/O (whose stage
+// leaves room for it) and K >= 4, where it fits two workgroups per CU.
+// Without it, u_k takes k passes; with it, k - S for k > S.
+bool adjoint_stash(bool rc, int io_dtype, int kmax) {
+  return rc && io_dtype == SOS_F32 && kmax >= 4 && AdjLds<kBwdN, float, true>::bytes(kmax, true) <= 80 * 1024;
+}
+
 // Recompute (group checkpoints) or saved outputs, by measured costs per
-// sample (MI355X, 2^24 float32 samples, ps): saved outputs move about 16K
-// bytes per sample, 3.74 + 4.00 K; recompute takes K(K-1)/2 + 1 forward
-// section passes per group besides the adjoint's own work,
-// 4.48 + 1.36 K + 0.38 (K(K-1)/2 + 1).  They cross between K = 14 and 15.
+// sample (MI355X, 2^24 float32 samples, ps).  Saved outputs move about 16K
+// bytes per sample: 3.74 + 4.00 K.  Recompute takes P forward section
+// passes per group besides the adjoint's own work: without the stash
+// P = K(K-1)/2 + 1 and 4.48 + 1.36 K + 0.38 P; with the stash of u_S
+// (S = K/2) P = K + (K-2-S)(K-1-S)/2 + S(S-1)/2 and 6.68 + 1.63 K + 0.319 P.
+// They cross between K = 14 and 15 without the stash; with it recompute
+// stays cheaper as far as the stash fits (K <= 17).
 double adjoint_cost_saved(int K) { return 3.74 + 4.00 * K; }
-double adjoint_cost_recompute(int K) { return 4.48 + 1.36 * K + 0.38 * (0.5 * K * (K - 1) + 1); }
+double adjoint_cost_recompute(int K, bool stash) {
+  if (stash && K >= 4) {
+    const double S = K / 2;
+    return 6.68 + 1.63 * K + 0.319 * (K + 0.5 * (K - 2 - S) * (K - 1 - S) + 0.5 * S * (S - 1));
+  }
+  return 4.48 + 1.36 * K + 0.38 * (0.5 * K * (K - 1) + 1);
+}
 
 bool adjoint_recompute(const sos_plan_s &p) {
   if (p.flags & SOS_FLAG_ADJ_RECOMPUTE) return true;
   if (p.flags & SOS_FLAG_ADJ_SAVE) return false;
-  return adjoint_cost_recompute(p.K) < adjoint_cost_saved(p.K);
+  return adjoint_cost_recompute(p.K, adjoint_stash(true, p.io_dtype, p.K)) < adjoint_cost_saved(p.K);
 }
 
 }  // namespace sosf
@@ -70,7 +86,7 @@ void launch_single(const BwdArgs &f, const BwdArgs &a, int K, const void *x, con
   const unsigned blocks_f = (unsigned)((f.ntiles + per_block - 1) / per_block);
   hipLaunchKernelGGL((sos_rows_save_kernel<N, TI, B0ONE, RC>), dim3(blocks_f), dim3(kWavesPerBlock * 64), lds_f,
                      s, static_cast<const TI *>(x), saved, tab, rows, f);
-  const unsigned lds_a = (unsigned)(stage_bytes<N, double>() + kWavesPerBlock * kRows * adj_row_elems(K, RC) * 8);
+  const unsigned lds_a = (unsigned)AdjLds<N, TI, RC>::bytes(K, a.stash > 0);
   const unsigned blocks_a = (unsigned)((a.ntiles + per_block - 1) / per_block);
   hipLaunchKernelGGL((sos_rows_adjoint_kernel<N, TI, B0ONE, RC>), dim3(blocks_a), dim3(kWavesPerBlock * 64),
                      lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx), static_cast<const TI *>(x),
@@ -79,6 +95,7 @@ void launch_single(const BwdArgs &f, const BwdArgs &a, int K, const void *x, con
 
 struct BwdLayout {
   bool rc;                  // recompute mode
+  int64_t stash;            // recompute mode: S (0: no stash)
   int64_t np, tile, ntiles, sstride;
   int64_t shift, nck;       // forward tiles over [-shift, n); checkpoints (recompute mode)
   int64_t ftile, fntiles;   // the forward pass's tiles
@@ -90,6 +107,7 @@ BwdLayout layout(const sos_plan_s &p, int64_t n) {
   const int64_t V = 16 / (int64_t)esz, G = (int64_t)kBwdN * kL;
   BwdLayout l;
   l.rc = adjoint_recompute(p);
+  l.stash = adjoint_stash(l.rc, p.io_dtype, p.K) ? p.K / 2 : 0;
   l.np = (n + V - 1) / V * V;
   l.tile = sos_plan_tile(p.bwd, std::max<int64_t>(l.np, 1));
   l.ntiles = (l.np + l.tile - 1) / l.tile;
@@ -127,6 +145,7 @@ sos_status launch_adjoint(const sos_plan_s &p, const void *x, const void *gy, vo
   a.sstride = l.sstride;
   a.shift = l.shift;
   a.nck = l.nck;
+  a.stash = l.stash;
   const double *tab = static_cast<const double *>(b.d_table);
   const double *rows = static_cast<const double *>(p.d_bwd_rows);
   if (n > 0) {
@@ -163,15 +182,18 @@ const void *adjoint_batched_kernel_ptr(bool rc) {
 }
 
 size_t adj_lds_save(int kmax) { return (size_t)lds_bytes<kBwdN, double, double>(kmax); }
-size_t adj_lds_adjoint(int kmax, bool rc) {
-  return (size_t)stage_bytes<kBwdN, double>() + (size_t)kWavesPerBlock * kRows * adj_row_elems(kmax, rc) * sizeof(double);
+size_t adj_lds_adjoint(int io_dtype, int kmax, bool rc, bool stash) {
+  if (io_dtype == SOS_F32)
+    return rc ? AdjLds<kBwdN, float, true>::bytes(kmax, stash) : AdjLds<kBwdN, float, false>::bytes(kmax, false);
+  return rc ? AdjLds<kBwdN, double, true>::bytes(kmax, stash) : AdjLds<kBwdN, double, false>::bytes(kmax, false);
 }
 
 template <typename TI, bool B0ONE, bool RC>
 void launch_batched(const sos_batch_s &b, const void *x, const void *gy, void *gx, double *w, hipStream_t s) {
   constexpr int N = kBwdN;
   const unsigned blocks = (unsigned)((b.adj_items + kWavesPerBlock - 1) / kWavesPerBlock);
-  const unsigned lds_f = (unsigned)adj_lds_save(b.kmax), lds_a = (unsigned)adj_lds_adjoint(b.kmax, RC);
+  const unsigned lds_f = (unsigned)adj_lds_save(b.kmax);
+  const unsigned lds_a = (unsigned)adj_lds_adjoint(b.io_dtype, b.kmax, RC, b.adj_stash);
   hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, B0ONE, RC>), dim3(blocks), dim3(kWavesPerBlock * 64),
                      lds_f, s, static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items,
                      (int32_t)b.kmax);
@@ -233,10 +255,11 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
   for (int c = 0; c < b.C; ++c) {
     any_save = any_save || (plans[c]->flags & SOS_FLAG_ADJ_SAVE);
     any_rc = any_rc || (plans[c]->flags & SOS_FLAG_ADJ_RECOMPUTE);
-    cost_rc += (double)b.n[c] * adjoint_cost_recompute(plans[c]->K);
+    cost_rc += (double)b.n[c] * adjoint_cost_recompute(plans[c]->K, adjoint_stash(true, b.io_dtype, b.kmax));
     cost_saved += (double)b.n[c] * adjoint_cost_saved(plans[c]->K);
   }
   b.adj_rc = !any_save && (any_rc || cost_rc < cost_saved);
+  b.adj_stash = adjoint_stash(b.adj_rc, b.io_dtype, b.kmax);
   std::vector<int64_t> np(b.C), shift(b.C), span(b.C);
   int64_t total_groups = 0;
   b.adj_b0one = true;
@@ -250,7 +273,7 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
   }
   const Residency r = residency_of(b.io_dtype == SOS_F64 ? adjoint_batched_kernel_ptr<double>(b.adj_rc)
                                                          : adjoint_batched_kernel_ptr<float>(b.adj_rc),
-                                   adj_lds_adjoint(b.kmax, b.adj_rc), kWavesPerBlock * 64);
+                                   adj_lds_adjoint(b.io_dtype, b.kmax, b.adj_rc, b.adj_stash), kWavesPerBlock * 64);
   const int64_t resident_rows = (int64_t)4 * r.simds * r.waves_per_simd;
   b.adj_gsos_row.assign(b.C, 0);
   int64_t rows = 0;
@@ -290,6 +313,7 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
     a.first_item = items;
     a.sstride = (b.n[c] + shift[c] + 63) / 64 * 64;
     a.nck = b.adj_rc && b.n[c] ? (np[c] + shift[c]) / G : 0;
+    a.stash = b.adj_stash && plans[c]->K >= 4 ? plans[c]->K / 2 : 0;
     a.saved_off = ws;
     ws += b.adj_rc ? (a.nck * state_elems(plans[c]->K) + 31) / 32 * 32 : (int64_t)plans[c]->K * a.sstride;
     a.partial_off = ws;

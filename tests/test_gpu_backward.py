@@ -87,18 +87,21 @@ def test_backward_recompute_equals_saved_outputs(io, K):
 
 
 def test_backward_mode_choice_and_workspace():
-    """Automatic mode: recompute up to K = 14 (checkpoints: 2K + 2 doubles
-    per 256-sample group), saved outputs above (K doubles per sample); both
-    flags together are rejected."""
+    """Automatic mode: recompute (checkpoints: 2K + 2 doubles per 256-sample
+    group) up to K = 17 with FP32 I/O (where section K/2's input is also
+    kept in LDS) and K = 14 with FP64 I/O, saved outputs above (K doubles
+    per sample); both flags together are rejected."""
     n = 2 ** 20
-    for K, rc in ((1, True), (8, True), (14, True), (15, False), (40, False)):
-        sos = W.make_sos(K, 0.5, 0.95, 150 + K)
-        auto = S.Plan(sos, io_dtype="f32").backward_workspace_size(n)
-        save = S.Plan(sos, io_dtype="f32", adjoint="save").backward_workspace_size(n)
-        rec = S.Plan(sos, io_dtype="f32", adjoint="recompute").backward_workspace_size(n)
-        assert save >= K * n * 8
-        assert rec < (2 * K + 2) * 8 * (n // 256 + 2) + save - K * n * 8
-        assert auto == (rec if rc else save), K
+    for io, cases in (("f32", ((1, True), (8, True), (16, True), (17, True), (18, False), (40, False))),
+                      ("f64", ((1, True), (8, True), (14, True), (15, False), (40, False)))):
+        for K, rc in cases:
+            sos = W.make_sos(K, 0.5, 0.95, 150 + K)
+            auto = S.Plan(sos, io_dtype=io).backward_workspace_size(n)
+            save = S.Plan(sos, io_dtype=io, adjoint="save").backward_workspace_size(n)
+            rec = S.Plan(sos, io_dtype=io, adjoint="recompute").backward_workspace_size(n)
+            assert save >= K * n * 8
+            assert rec < (2 * K + 2) * 8 * (n // 256 + 2) + save - K * n * 8
+            assert auto == (rec if rc else save), (io, K)
     import ctypes
     s2 = np.ascontiguousarray(W.make_sos(2, 0.5, 0.9, 1))
     o = S._Opts(S.SOS_F32, S.SOS_F64, S.SOS_AUTO, 0, 16, 0, S.SOS_FLAG_ADJ_SAVE | S.SOS_FLAG_ADJ_RECOMPUTE)
