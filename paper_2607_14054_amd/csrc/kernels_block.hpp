@@ -143,7 +143,10 @@ __device__ __forceinline__ void block_rows(const TI *__restrict__ x, TI *__restr
           const v4h A = reinterpret_cast<const v4h *>(a_s)[k * 64 + lane];
           v4h B;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) B[r] = (_Float16)(float)(V[r] * sc);
+          // the power-of-two scale in FP32 is exact; scaling there keeps the
+          // conversion to FP16 one hardware step from FP32 (from FP64 the
+          // compiler would emulate it)
+          for (int r = 0; r < 4; ++r) B[r] = (_Float16)((float)V[r] * (float)sc);
           acc = __builtin_amdgcn_mfma_f32_16x16x16f16(A, B, acc, 0, 0, 0);
         } else {
           const v4s A = reinterpret_cast<const v4s *>(a_s)[k * 64 + lane];
