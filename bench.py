@@ -135,6 +135,34 @@ def bench_batch(S, W, torch, dev, args):
     return out
 
 
+def forms_summary(extra, plain_gsps):
+    """The batched, adjoint and precision forms beside the plain one: each
+    one's throughput on its own workload, its ratio to the plain GS/s, and
+    its error against the FP64 oracle on sampled channels (null when the
+    CPU checks were skipped)."""
+    b, g, p = extra["batch"], extra["grad"], extra["precision"]
+    out = {
+        "batched": {"workload": "4096 channels, lengths log-uniform in [2^10, 2^22] float32, K ~ U{1..16}, "
+                                "r U[0.5,0.95]; one graph-replayed launch, autotuned",
+                    "GSps": b["GSps"], "vs_plain": b["GSps"] / plain_gsps, "N": b["N"],
+                    "rel_rms_max": b.get("rel_rms_max_sampled")},
+        "adjoint": {"workload": "64 x 2^18 float32, K=8, r U[0.5,0.95]; batched forward + batched adjoint",
+                    "GSps": g["GSps"], "vs_plain": g["GSps"] / plain_gsps,
+                    "saved_outputs_GSps": g["saved_outputs"]["GSps"],
+                    "gx_rel_rms_max": g.get("gx_rel_rms_max"), "gsos_row_err_max": g.get("gsos_row_err_max")},
+        "precision": {"workload": "256 x 2^20 float32, K=8, r U[0.9,0.999]; one batched launch per row",
+                      "rows": [{"compute": r["compute"], "solver": r["solver"], "GSps": r["GSps"],
+                                "vs_plain": r["GSps"] / plain_gsps, "rel_rms_max": r.get("rel_rms_max")}
+                               for r in p["rows"]]},
+    }
+    for f in (out["batched"], out["adjoint"]):
+        e = f.get("rel_rms_max", f.get("gx_rel_rms_max"))
+        f["within_1e-4"] = None if e is None else bool(e <= 1e-4)
+    for r in out["precision"]["rows"]:
+        r["within_1e-4"] = None if r["rel_rms_max"] is None else bool(r["rel_rms_max"] <= 1e-4)
+    return out
+
+
 HEADLINE_SOURCES = ("kernels.hpp", "plan.hpp", "plan.cpp", "dispatch.hpp", "sosfilt_api.hip")
 
 
@@ -534,6 +562,9 @@ def main():
     ap.add_argument("--draws", action="store_true",
                     help="also the kernel's and the FP32 floor's error over 16 coefficient draws")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched, adjoint and precision forms that the default run reports "
+                         "beside the plain one")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -612,6 +643,10 @@ def main():
                 % (solver, NN, cd, p2.tile(n), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
         extra["sweep"] = rows
 
+    # the forms the metric reports beside the plain one, run by default
+    forms = not args.no_forms and not args.copy_only
+    if forms:
+        args.batch = args.grad = args.precision = True
     if args.batch or args.grad or args.precision or args.grad_long or args.stream:
         del x, y
         torch.cuda.empty_cache()
@@ -688,6 +723,8 @@ def main():
         "cpu_comparator": comparator,
         "accuracy": accuracy,
     }
+    if forms:
+        line["forms"] = forms_summary(extra, gsps)
     print(json.dumps(line), flush=True)
     if args.out:
         extra["line"] = line
