@@ -366,3 +366,22 @@ def test_adjoint_graph_replays_match_eager(adjoint):
         call(torch.cuda.current_stream())
         torch.cuda.synchronize()
         assert torch.equal(got_x, gx) and torch.equal(got_s, gs), rep
+
+
+@pytest.mark.parametrize("K", [4, 5, 17])
+def test_backward_stash_edges(K):
+    """FP32 I/O recompute with the stash of section K/2's input: its
+    smallest K (4, 5) and the largest whose stash fits two workgroups per
+    CU (17).  Equal to the saved-output mode to rounding and to the oracle
+    adjoint."""
+    n = 2 ** 17 + 333
+    sos = W.make_sos(K, 0.5, 0.97, 160 + K)
+    x = W.make_signal(n, 161, np.float32)
+    g = W.grad_seed_signal(n, 161, np.float32)
+    rx, rs = run_backward(sos, x, g, adjoint="recompute")
+    sx, ss = run_backward(sos, x, g, adjoint="save")
+    assert oracle.rel_rms(rx, sx) < 1e-6
+    assert row_err(rs, ss) < 1e-10
+    ox, os_ = oracle.sosfilt_backward(x.astype(np.float64), sos, g.astype(np.float64))
+    assert oracle.rel_rms(rx, ox) < 1e-6
+    assert row_err(rs, os_) < 1e-9
