@@ -438,8 +438,8 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
     const TI *__restrict__ x, double *__restrict__ saved, const double *__restrict__ tab,
     const double *__restrict__ bwd, BwdArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  // the stage holds one group per row in FP64 (the saved outputs), which
-  // also fits the input's group
+  // the stage holds one group per row in FP64 (the saved outputs, in that
+  // mode), which also fits the input's group
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (wave * kRows >= a.ntiles) return;

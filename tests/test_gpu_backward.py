@@ -11,8 +11,9 @@ Tolerances:
   strongly attenuating cascades cancel large intermediates: on K = 8 draws the
   FP64 oracle itself is ~1e-12 (dL/dx) and ~3e-11 (dL/dsos) off.
 * FP32 in/out: dL/dx within 1e-6 relative RMS (FP32 output rounding);
-  dL/dsos within 1e-9 of the row's largest entry (FP64 arithmetic and FP64
-  saved section outputs; the inputs x and dL/dy are exact in both).
+  dL/dsos within 1e-9 of the row's largest entry (FP64 arithmetic, and FP64
+  section outputs whether saved or recomputed; the inputs x and dL/dy are
+  exact in both).
 """
 import numpy as np
 import pytest
