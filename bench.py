@@ -146,8 +146,10 @@ def forms_summary(extra, plain_gsps):
                                 "r U[0.5,0.95]; one graph-replayed launch, autotuned",
                     "GSps": b["GSps"], "vs_plain": b["GSps"] / plain_gsps, "N": b["N"],
                     "rel_rms_max": b.get("rel_rms_max_sampled")},
-        "adjoint": {"workload": "64 x 2^18 float32, K=8, r U[0.5,0.95]; batched forward + batched adjoint",
+        "adjoint": {"workload": "64 x 2^18 float32, K=8, r U[0.5,0.95]; training step: batched forward that "
+                                "fills the adjoint's workspace, then the batched adjoint from it",
                     "GSps": g["GSps"], "vs_plain": g["GSps"] / plain_gsps,
+                    "one_call_GSps": g["one_call"]["GSps"],
                     "saved_outputs_GSps": g["saved_outputs"]["GSps"],
                     "gx_rel_rms_max": g.get("gx_rel_rms_max"), "gsos_row_err_max": g.get("gsos_row_err_max")},
         "precision": {"workload": "256 x 2^20 float32, K=8, r U[0.9,0.999]; one batched launch per row",
@@ -199,11 +201,14 @@ def measured_traffic(N, solver_opt, solvers, n):
 def bench_grad(S, W, torch, dev, args):
     """The adjoint workload: 64 channels x 2^18 float32 samples, K = 8,
     r in [0.5, 0.95], loss sum(y * g) with g ~ N(0, 1) (seed + 2); channel c
-    drawn with seed c.  One step is the batched forward (sos_filt_batched)
-    and the batched adjoint (sos_filt_backward_batched) of all channels, in
-    the automatic adjoint mode (recompute from group checkpoints at K = 8)
-    and, for comparison, with every section output saved.  A sample of
-    channels is checked against the oracle adjoint."""
+    drawn with seed c.  One step is a training step of all channels: the
+    batched forward that also fills the adjoint's workspace
+    (sos_filt_batched_for_backward) and the batched adjoint from it
+    (sos_filt_backward_batched_stored), in the automatic adjoint mode
+    (recompute from group checkpoints at K = 8).  For comparison: the same
+    step as sos_filt_batched plus the one-call sos_filt_backward_batched,
+    and with every section output saved.  A sample of channels is checked
+    against the oracle adjoint."""
     cfg = W.CONFIGS["grad"]
     C, n = cfg.channels, cfg.n
     sos = [W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed + c) for c in range(C)]
@@ -216,13 +221,17 @@ def bench_grad(S, W, torch, dev, args):
     gx = torch.empty_like(xb)
     total = C * n
     out = {"channels": C, "samples": total, "K": cfg.K}
-    for mode in ("auto", "save"):
+    for mode, two_call, key in (("auto", True, None), ("auto", False, "one_call"), ("save", True, "saved_outputs")):
         plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver="auto", N=64, adjoint=mode)
                  for s_ in sos]
         b = S.Batch(plans, [n] * C)
         assert b.total == total
+        ws = torch.empty(max(b.backward_workspace_size(), 16), dtype=torch.uint8, device=dev)
 
         def one_pass():
+            if two_call:
+                S.filt_batched_for_backward(b, xb, yb, workspace=ws)
+                return S.filt_backward_batched_stored(b, xb, gb, ws, gx)
             S.filt_batched(b, xb, yb)
             return S.filt_backward_batched(b, xb, gb, gx)
 
@@ -238,8 +247,9 @@ def bench_grad(S, W, torch, dev, args):
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3 / steps
         row = {"ms": sec * 1e3, "GSps": total / sec / 1e9}
+        label = "%s, %s" % (mode, "two calls" if two_call else "one call")
         log("grad (%s): %d x %d batched forward+backward %.3f ms  %.1f GS/s"
-            % (mode, C, n, sec * 1e3, total / sec / 1e9))
+            % (label, C, n, sec * 1e3, total / sec / 1e9))
         if not args.no_cpu:
             import oracle
             _, gsos, first = one_pass()
@@ -255,11 +265,11 @@ def bench_grad(S, W, torch, dev, args):
                 worst_s = max(worst_s, float(np.max(np.abs(g - rs) / np.max(np.abs(rs), axis=1, keepdims=True))))
             row["gx_rel_rms_max"] = worst_x
             row["gsos_row_err_max"] = worst_s
-            log("grad (%s): sampled channels gx rel_rms %.2e, gsos row err %.2e" % (mode, worst_x, worst_s))
-        if mode == "auto":
+            log("grad (%s): sampled channels gx rel_rms %.2e, gsos row err %.2e" % (label, worst_x, worst_s))
+        if key is None:
             out.update(row)
         else:
-            out["saved_outputs"] = row
+            out[key] = row
         b.close()
         for p_ in plans:
             p_.close()
@@ -323,31 +333,53 @@ def bench_stream(S, W, torch, dev, args):
 
 def bench_grad_long(S, W, torch, dev, args):
     """The adjoint on one long channel: 2^26 float32 samples, K = 8,
-    r in [0.5, 0.95]; one sos_filt_backward per step, in the automatic mode
-    (recompute) and with saved outputs."""
+    r in [0.5, 0.95]: one sos_filt_backward per step, in the automatic mode
+    (recompute) and with saved outputs; and the training step (forward and
+    backward) in the automatic mode, as sos_filt + sos_filt_backward and as
+    sos_filt_for_backward + sos_filt_backward_stored."""
     n = 1 << 26
     sos = W.make_sos(8, 0.5, 0.95, 0)
     x = torch.from_numpy(W.make_signal(n, 0, np.float32)).to(dev)
     g = torch.from_numpy(W.grad_seed_signal(n, 0, np.float32)).to(dev)
     gx = torch.empty_like(x)
+    y = torch.empty_like(x)
     out = {"samples": n}
-    for mode in ("auto", "save"):
-        plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=64, adjoint=mode)
-        S.filt_backward(plan, x, g, gx)
+    steps = max(3, args.steps // 4)
+
+    def timed(fn):
+        fn()
         torch.cuda.synchronize()
-        steps = max(3, args.steps // 4)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(steps):
-            S.filt_backward(plan, x, g, gx)
+            fn()
         e1.record()
         torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / 1e3 / steps
+        return e0.elapsed_time(e1) / 1e3 / steps
+
+    for mode in ("auto", "save"):
+        plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=64, adjoint=mode)
+        sec = timed(lambda: S.filt_backward(plan, x, g, gx))
         log("grad-long (%s): 2^26 backward %.3f ms  %.1f GS/s" % (mode, sec * 1e3, n / sec / 1e9))
         row = {"ms": sec * 1e3, "GSps": n / sec / 1e9}
         if mode == "auto":
             out.update(row)
+            ws = torch.empty(max(plan.backward_workspace_size(n), 16), dtype=torch.uint8, device=dev)
+
+            def one_call():
+                S.filt(plan, x, y)
+                S.filt_backward(plan, x, g, gx)
+
+            def two_calls():
+                S.filt_for_backward(plan, x, y, workspace=ws)
+                S.filt_backward_stored(plan, x, g, ws, gx)
+
+            for name, fn in (("step_one_call", one_call), ("step_two_calls", two_calls)):
+                s2 = timed(fn)
+                out[name] = {"ms": s2 * 1e3, "GSps": n / s2 / 1e9}
+                log("grad-long (auto): 2^26 training step, %s: %.3f ms  %.1f GS/s"
+                    % (name.replace("step_", "").replace("_", " "), s2 * 1e3, n / s2 / 1e9))
         else:
             out["saved_outputs"] = row
         plan.close()

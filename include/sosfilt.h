@@ -358,11 +358,34 @@ size_t sos_backward_workspace_size(sos_plan_t plan, int64_t n);
  * The adjoint always runs PH with FP64 arithmetic at N = 16, whatever the
  * plan's solver, N and compute dtype (the same cascade, exact to rounding).
  * It first re-runs the forward pass (saving section outputs or group
- * states, as above), so the caller's forward result is not needed.  Sums over the signal are formed
- * per tile and added in a fixed order: results are deterministic.
+ * states, as above), so the caller's forward result is not needed.  Sums
+ * over the signal are formed per tile and added in a fixed order: results
+ * are deterministic.
  */
 sos_status sos_filt_backward(sos_plan_t plan, const void *x, const void *gy, void *gx,
                              double *gsos, int64_t n, void *workspace, sos_stream_t stream);
+
+/*
+ * A training step in two calls, without the backward's own forward pass.
+ * The two calls give the same gx and gsos as sos_filt_backward.
+ *
+ * sos_filt_for_backward -- the forward pass of sos_filt_backward, which
+ * also stores y = cascade(x).  It fills the workspace with what the adjoint
+ * needs (section outputs or group states).
+ *   x          device, n samples (io_dtype), read.
+ *   y          device, n samples (io_dtype), written; must not overlap x.
+ *              Computed by the adjoint's path (PH, FP64 arithmetic,
+ *              N = 16): sos_filt's result to rounding.
+ *   workspace  device, sos_backward_workspace_size(plan, n) bytes, 16-byte
+ *              aligned.
+ * sos_filt_backward_stored -- the adjoint of sos_filt_backward from that
+ * workspace: the same plan, x, n and workspace, left unchanged in between.
+ * Other arguments as sos_filt_backward.
+ */
+sos_status sos_filt_for_backward(sos_plan_t plan, const void *x, void *y, int64_t n, void *workspace,
+                                 sos_stream_t stream);
+sos_status sos_filt_backward_stored(sos_plan_t plan, const void *x, const void *gy, void *gx,
+                                    double *gsos, int64_t n, void *workspace, sos_stream_t stream);
 
 /*
  * Batched adjoint: sos_filt_backward for every channel of a device batch in
@@ -387,6 +410,15 @@ size_t sos_batch_backward_workspace_size(sos_batch_t batch);
 sos_status sos_batch_query_adjoint(sos_batch_t batch, int64_t *gsos_rows, int64_t *first_row);
 sos_status sos_filt_backward_batched(sos_batch_t batch, const void *x, const void *gy, void *gx,
                                      double *gsos, void *workspace, sos_stream_t stream);
+/*
+ * The batched training step in two calls, as sos_filt_for_backward and
+ * sos_filt_backward_stored.  y has the batch's layout and is written at
+ * the channels' samples only.
+ */
+sos_status sos_filt_batched_for_backward(sos_batch_t batch, const void *x, void *y, void *workspace,
+                                         sos_stream_t stream);
+sos_status sos_filt_backward_batched_stored(sos_batch_t batch, const void *x, const void *gy, void *gx,
+                                            double *gsos, void *workspace, sos_stream_t stream);
 
 /*
  * sos_batch_tune -- autotuner for batches: times sos_filt_batched for every

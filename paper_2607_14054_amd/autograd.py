@@ -1,5 +1,7 @@
-"""torch.autograd.Function over the C ABI: forward sos_filt, backward
-sos_filt_backward (argument marshalling only)."""
+"""torch.autograd.Function over the C ABI (argument marshalling only).
+When a gradient is needed, the forward is sos_filt_for_backward, which
+also fills the adjoint's workspace, and the backward sos_filt_backward_stored;
+otherwise the forward is sos_filt."""
 from __future__ import annotations
 
 import numpy as np
@@ -18,15 +20,22 @@ class SosFilt(torch.autograd.Function):
         plan = S.Plan(sos.detach().to("cpu", torch.float64).numpy(), io_dtype=io, compute_dtype="f64",
                       solver=solver, N=N)
         xc = x.contiguous()
-        y = S.filt(plan, xc)
         ctx.plan = plan
+        ctx.ws = None
+        if any(ctx.needs_input_grad[:2]):
+            y, ctx.ws = S.filt_for_backward(plan, xc)
+        else:
+            y = S.filt(plan, xc)
         ctx.save_for_backward(xc, sos)
         return y
 
     @staticmethod
     def backward(ctx, gy):
         x, sos = ctx.saved_tensors
-        gx, gsos = S.filt_backward(ctx.plan, x, gy.contiguous())
+        if ctx.ws is not None:
+            gx, gsos = S.filt_backward_stored(ctx.plan, x, gy.contiguous(), ctx.ws)
+        else:
+            gx, gsos = S.filt_backward(ctx.plan, x, gy.contiguous())
         gsos = gsos.to(device=sos.device, dtype=sos.dtype)
         return (gx if ctx.needs_input_grad[0] else None,
                 gsos if ctx.needs_input_grad[1] else None, None, None)

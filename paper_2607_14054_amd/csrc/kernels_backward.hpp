@@ -163,12 +163,14 @@ struct BwdArgs {
 // state the cascade enters the group with) as checkpoint j = (np - g)/G - 1,
 // the reversed-time group that covers the same samples; the tiles start
 // where the groups line up with the reversed-time ones (shift = -np mod G).
-// PH, FP64 arithmetic, tiles as in filter_rows.  st: 2 + 2K boundary values;
+// PH, FP64 arithmetic, tiles as in filter_rows.  STORE_Y: also store the
+// cascade's output y (the forward pass of a training step, which then
+// needs no second pass for the adjoint).  st: 2 + 2K boundary values;
 // rowbuf: one FP64 group.
-template <int N, typename TI, bool B0ONE, bool RC>
+template <int N, typename TI, bool B0ONE, bool RC, bool STORE_Y>
 __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__restrict__ saved,
-                                          ctab<double> ct, ctab<double> cb, const AdjView &v,
-                                          int64_t tile_index, bool aligned, double *st,
+                                          TI *__restrict__ y, ctab<double> ct, ctab<double> cb,
+                                          const AdjView &v, int64_t tile_index, bool aligned, double *st,
                                           unsigned char *rowbuf) {
   typedef double T;
   TI *buf = reinterpret_cast<TI *>(rowbuf);
@@ -202,6 +204,8 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
         store_group<N, double, T>(X, saved + (int64_t)k * v.sstride, g, v.n, full, cb[kBwdRow * k + BW_SCALE],
                                   dbuf);
     }
+    if (STORE_Y && live)
+      store_group<N, TI, T>(X, y, g, v.n, full, cb[kBwdRow * (v.K - 1) + BW_SCALE], buf);
   }
 }
 
@@ -433,9 +437,9 @@ __device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
 }
 
 // Single signal: row r of wavefront w takes tile 4w + r.
-template <int N, typename TI, bool B0ONE, bool RC>
+template <int N, typename TI, bool B0ONE, bool RC, bool STORE_Y>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
-    const TI *__restrict__ x, double *__restrict__ saved, const double *__restrict__ tab,
+    const TI *__restrict__ x, double *__restrict__ saved, TI *__restrict__ y, const double *__restrict__ tab,
     const double *__restrict__ bwd, BwdArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   // the stage holds one group per row in FP64 (the saved outputs, in that
@@ -447,8 +451,8 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_kernel(
   double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
                (int64_t)(w * kRows + row) * state_elems(a.K);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
-  save_rows<N, TI, B0ONE, RC>(x, saved, as_ctab(tab), as_ctab(bwd), adj_view(a), wave * kRows + row, true,
-                              st, rowbuf);
+  save_rows<N, TI, B0ONE, RC, STORE_Y>(x, saved, y, as_ctab(tab), as_ctab(bwd), adj_view(a), wave * kRows + row,
+                                       true, st, rowbuf);
 }
 
 template <int N, typename TI, bool B0ONE, bool RC>
@@ -485,9 +489,9 @@ __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
   return v;
 }
 
-template <int N, typename TI, bool B0ONE, bool RC>
+template <int N, typename TI, bool B0ONE, bool RC, bool STORE_Y>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_batched_kernel(
-    const TI *__restrict__ x, double *__restrict__ ws, const AdjChan *__restrict__ chans,
+    const TI *__restrict__ x, double *__restrict__ ws, TI *__restrict__ y, const AdjChan *__restrict__ chans,
     const int32_t *__restrict__ item_chan, int64_t items, int32_t kmax) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -499,8 +503,8 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_batched_ker
   double *st = reinterpret_cast<double *>(smem + stage_bytes<N, double>()) +
                (int64_t)(w * kRows + row) * state_elems(kmax);
   unsigned char *rowbuf = smem + (w * kRows + row) * Stage<N, double>::ROWBUF * 8;
-  save_rows<N, TI, B0ONE, RC>(x + c.off, ws + c.saved_off, as_ctab(c.tab), as_ctab(c.bwd), adj_view(c),
-                              tile_index, true, st, rowbuf);
+  save_rows<N, TI, B0ONE, RC, STORE_Y>(x + c.off, ws + c.saved_off, STORE_Y ? y + c.off : nullptr, as_ctab(c.tab),
+                                       as_ctab(c.bwd), adj_view(c), tile_index, true, st, rowbuf);
 }
 
 template <int N, typename TI, bool B0ONE, bool RC>

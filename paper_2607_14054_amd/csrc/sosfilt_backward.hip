@@ -77,20 +77,33 @@ bool adjoint_recompute(const sos_plan_s &p) {
 
 namespace {
 
+// The steps of a backward call: the forward-time pass that fills the
+// workspace (and, for a training step's forward, stores y), and the
+// reversed-time adjoint with the reduction of the coefficient sums.
+enum : int { STEP_FORWARD = 1, STEP_ADJOINT = 2 };
+
 template <typename TI, bool B0ONE, bool RC>
-void launch_single(const BwdArgs &f, const BwdArgs &a, int K, const void *x, const void *gy, void *gx,
-                   double *saved, const double *tab, const double *rows, double *partials, hipStream_t s) {
+void launch_single(int steps, const BwdArgs &f, const BwdArgs &a, int K, const void *x, void *y, const void *gy,
+                   void *gx, double *saved, const double *tab, const double *rows, double *partials, hipStream_t s) {
   constexpr int N = kBwdN;
   const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
-  const unsigned lds_f = (unsigned)lds_bytes<N, double, double>(K);
-  const unsigned blocks_f = (unsigned)((f.ntiles + per_block - 1) / per_block);
-  hipLaunchKernelGGL((sos_rows_save_kernel<N, TI, B0ONE, RC>), dim3(blocks_f), dim3(kWavesPerBlock * 64), lds_f,
-                     s, static_cast<const TI *>(x), saved, tab, rows, f);
-  const unsigned lds_a = (unsigned)AdjLds<N, TI, RC>::bytes(K, a.stash > 0);
-  const unsigned blocks_a = (unsigned)((a.ntiles + per_block - 1) / per_block);
-  hipLaunchKernelGGL((sos_rows_adjoint_kernel<N, TI, B0ONE, RC>), dim3(blocks_a), dim3(kWavesPerBlock * 64),
-                     lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx), static_cast<const TI *>(x),
-                     saved, tab, rows, partials, a);
+  if (steps & STEP_FORWARD) {
+    const unsigned lds_f = (unsigned)lds_bytes<N, double, double>(K);
+    const unsigned blocks_f = (unsigned)((f.ntiles + per_block - 1) / per_block);
+    if (y)
+      hipLaunchKernelGGL((sos_rows_save_kernel<N, TI, B0ONE, RC, true>), dim3(blocks_f), dim3(kWavesPerBlock * 64),
+                         lds_f, s, static_cast<const TI *>(x), saved, static_cast<TI *>(y), tab, rows, f);
+    else
+      hipLaunchKernelGGL((sos_rows_save_kernel<N, TI, B0ONE, RC, false>), dim3(blocks_f), dim3(kWavesPerBlock * 64),
+                         lds_f, s, static_cast<const TI *>(x), saved, static_cast<TI *>(nullptr), tab, rows, f);
+  }
+  if (steps & STEP_ADJOINT) {
+    const unsigned lds_a = (unsigned)AdjLds<N, TI, RC>::bytes(K, a.stash > 0);
+    const unsigned blocks_a = (unsigned)((a.ntiles + per_block - 1) / per_block);
+    hipLaunchKernelGGL((sos_rows_adjoint_kernel<N, TI, B0ONE, RC>), dim3(blocks_a), dim3(kWavesPerBlock * 64),
+                       lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx), static_cast<const TI *>(x),
+                       saved, tab, rows, partials, a);
+  }
 }
 
 struct BwdLayout {
@@ -129,8 +142,8 @@ BwdLayout layout(const sos_plan_s &p, int64_t n) {
 }
 
 template <typename TI>
-sos_status launch_adjoint(const sos_plan_s &p, const void *x, const void *gy, void *gx, double *gsos,
-                          int64_t n, void *ws, hipStream_t s) {
+sos_status launch_adjoint(int steps, const sos_plan_s &p, const void *x, void *y, const void *gy, void *gx,
+                          double *gsos, int64_t n, void *ws, hipStream_t s) {
   const sos_plan_s &b = *p.bwd;
   const BwdLayout l = layout(p, n);
   double *saved = static_cast<double *>(ws);
@@ -158,19 +171,20 @@ sos_status launch_adjoint(const sos_plan_s &p, const void *x, const void *gy, vo
     a.ntiles = l.ntiles;
     if (l.rc) {
       if (b.b0_factored)
-        launch_single<TI, true, true>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+        launch_single<TI, true, true>(steps, f, a, p.K, x, y, gy, gx, saved, tab, rows, partials, s);
       else
-        launch_single<TI, false, true>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+        launch_single<TI, false, true>(steps, f, a, p.K, x, y, gy, gx, saved, tab, rows, partials, s);
     } else {
       if (b.b0_factored)
-        launch_single<TI, true, false>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+        launch_single<TI, true, false>(steps, f, a, p.K, x, y, gy, gx, saved, tab, rows, partials, s);
       else
-        launch_single<TI, false, false>(f, a, p.K, x, gy, gx, saved, tab, rows, partials, s);
+        launch_single<TI, false, false>(steps, f, a, p.K, x, y, gy, gx, saved, tab, rows, partials, s);
     }
     if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
   }
-  hipLaunchKernelGGL(sos_adjoint_reduce_kernel, dim3((unsigned)p.K), dim3(256), 0, s, partials,
-                     n > 0 ? l.ntiles : (int64_t)0, (int32_t)p.K, rows, gsos);
+  if (steps & STEP_ADJOINT)
+    hipLaunchKernelGGL(sos_adjoint_reduce_kernel, dim3((unsigned)p.K), dim3(256), 0, s, partials,
+                       n > 0 ? l.ntiles : (int64_t)0, (int32_t)p.K, rows, gsos);
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }
 
@@ -189,39 +203,50 @@ size_t adj_lds_adjoint(int io_dtype, int kmax, bool rc, bool stash) {
 }
 
 template <typename TI, bool B0ONE, bool RC>
-void launch_batched(const sos_batch_s &b, const void *x, const void *gy, void *gx, double *w, hipStream_t s) {
+void launch_batched(int steps, const sos_batch_s &b, const void *x, void *y, const void *gy, void *gx, double *w,
+                    hipStream_t s) {
   constexpr int N = kBwdN;
   const unsigned blocks = (unsigned)((b.adj_items + kWavesPerBlock - 1) / kWavesPerBlock);
-  const unsigned lds_f = (unsigned)adj_lds_save(b.kmax);
-  const unsigned lds_a = (unsigned)adj_lds_adjoint(b.io_dtype, b.kmax, RC, b.adj_stash);
-  hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, B0ONE, RC>), dim3(blocks), dim3(kWavesPerBlock * 64),
-                     lds_f, s, static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items,
-                     (int32_t)b.kmax);
-  hipLaunchKernelGGL((sos_rows_adjoint_batched_kernel<N, TI, B0ONE, RC>), dim3(blocks),
-                     dim3(kWavesPerBlock * 64), lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx),
-                     static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+  if (steps & STEP_FORWARD) {
+    const unsigned lds_f = (unsigned)adj_lds_save(b.kmax);
+    if (y)
+      hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, B0ONE, RC, true>), dim3(blocks),
+                         dim3(kWavesPerBlock * 64), lds_f, s, static_cast<const TI *>(x), w, static_cast<TI *>(y),
+                         b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+    else
+      hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, B0ONE, RC, false>), dim3(blocks),
+                         dim3(kWavesPerBlock * 64), lds_f, s, static_cast<const TI *>(x), w,
+                         static_cast<TI *>(nullptr), b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+  }
+  if (steps & STEP_ADJOINT) {
+    const unsigned lds_a = (unsigned)adj_lds_adjoint(b.io_dtype, b.kmax, RC, b.adj_stash);
+    hipLaunchKernelGGL((sos_rows_adjoint_batched_kernel<N, TI, B0ONE, RC>), dim3(blocks),
+                       dim3(kWavesPerBlock * 64), lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx),
+                       static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+  }
 }
 
 template <typename TI>
-sos_status launch_adjoint_batched(const sos_batch_s &b, const void *x, const void *gy, void *gx, double *gsos,
-                                  void *ws, hipStream_t s) {
+sos_status launch_adjoint_batched(int steps, const sos_batch_s &b, const void *x, void *y, const void *gy, void *gx,
+                                  double *gsos, void *ws, hipStream_t s) {
   double *w = static_cast<double *>(ws);
   if (b.adj_items > 0) {
     if (b.adj_rc) {
       if (b.adj_b0one)
-        launch_batched<TI, true, true>(b, x, gy, gx, w, s);
+        launch_batched<TI, true, true>(steps, b, x, y, gy, gx, w, s);
       else
-        launch_batched<TI, false, true>(b, x, gy, gx, w, s);
+        launch_batched<TI, false, true>(steps, b, x, y, gy, gx, w, s);
     } else {
       if (b.adj_b0one)
-        launch_batched<TI, true, false>(b, x, gy, gx, w, s);
+        launch_batched<TI, true, false>(steps, b, x, y, gy, gx, w, s);
       else
-        launch_batched<TI, false, false>(b, x, gy, gx, w, s);
+        launch_batched<TI, false, false>(steps, b, x, y, gy, gx, w, s);
     }
     if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
   }
-  hipLaunchKernelGGL(sos_adjoint_reduce_batched_kernel, dim3((unsigned)b.adj_rows), dim3(256), 0, s, w, b.d_adj,
-                     b.d_adj_red, gsos);
+  if (steps & STEP_ADJOINT)
+    hipLaunchKernelGGL(sos_adjoint_reduce_batched_kernel, dim3((unsigned)b.adj_rows), dim3(256), 0, s, w, b.d_adj,
+                       b.d_adj_red, gsos);
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }
 
@@ -337,6 +362,60 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
 
 }  // namespace sosf
 
+namespace {
+
+bool disjoint(uintptr_t a, uintptr_t b, uintptr_t bytes) { return !(a < b + bytes && b < a + bytes); }
+
+// Arguments of a backward call with `bytes` of signal: the forward step
+// reads x and writes y (if any); the adjoint step reads x and gy and writes
+// gx.  Signals and workspace 16-byte aligned; what a step writes overlaps
+// nothing it reads (tiles read beyond their own range); gsos 8-byte aligned.
+sos_status check_backward(int steps, uintptr_t bytes, const void *x, const void *y, const void *gy,
+                          const void *gx, const double *gsos, const void *workspace) {
+  if (!workspace) return SOS_E_ARG;
+  if ((steps & STEP_ADJOINT) && (!gsos || ((uintptr_t)gsos & 7))) return SOS_E_ARG;
+  if (bytes == 0) return SOS_OK;
+  const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y, gyb = (uintptr_t)gy, gxb = (uintptr_t)gx;
+  if (!x || ((xb | (uintptr_t)workspace) & 15)) return SOS_E_ARG;
+  if (steps & STEP_FORWARD) {
+    if (y && ((yb & 15) || !disjoint(xb, yb, bytes))) return SOS_E_ARG;
+  }
+  if (steps & STEP_ADJOINT) {
+    if (!gy || !gx || ((gyb | gxb) & 15)) return SOS_E_ARG;
+    if (!disjoint(gxb, xb, bytes) || !disjoint(gxb, gyb, bytes)) return SOS_E_ARG;
+  }
+  return SOS_OK;
+}
+
+sos_status backward_single(int steps, sos_plan_t p, const void *x, void *y, const void *gy, void *gx, double *gsos,
+                           int64_t n, void *workspace, sos_stream_t stream) {
+  if (!p || n < 0) return SOS_E_ARG;
+  if (!p->bwd || !p->d_bwd_rows) return SOS_E_ARG;   // host-only plan
+  if ((steps & STEP_FORWARD) && !(steps & STEP_ADJOINT) && n > 0 && !y) return SOS_E_ARG;
+  const size_t esz = p->io_dtype == SOS_F64 ? 8 : 4;
+  const sos_status st = check_backward(steps, (uintptr_t)n * esz, x, y, gy, gx, gsos, workspace);
+  if (st != SOS_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (p->io_dtype == SOS_F32) return launch_adjoint<float>(steps, *p, x, y, gy, gx, gsos, n, workspace, s);
+  return launch_adjoint<double>(steps, *p, x, y, gy, gx, gsos, n, workspace, s);
+}
+
+sos_status backward_batched(int steps, sos_batch_t b, const void *x, void *y, const void *gy, void *gx, double *gsos,
+                            void *workspace, sos_stream_t stream) {
+  if (!b || !b->adj) return SOS_E_ARG;
+  if (!batch_descriptors_valid(*b)) return SOS_E_ARG;
+  if ((steps & STEP_FORWARD) && !(steps & STEP_ADJOINT) && b->adj_items > 0 && !y) return SOS_E_ARG;
+  const size_t esz = b->io_dtype == SOS_F64 ? 8 : 4;
+  const sos_status st =
+      check_backward(steps, b->adj_items > 0 ? (uintptr_t)b->total * esz : 0, x, y, gy, gx, gsos, workspace);
+  if (st != SOS_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (b->io_dtype == SOS_F32) return launch_adjoint_batched<float>(steps, *b, x, y, gy, gx, gsos, workspace, s);
+  return launch_adjoint_batched<double>(steps, *b, x, y, gy, gx, gsos, workspace, s);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t sos_batch_backward_workspace_size(sos_batch_t b) { return (b && b->adj) ? b->adj_ws : 0; }
@@ -351,22 +430,18 @@ sos_status sos_batch_query_adjoint(sos_batch_t b, int64_t *gsos_rows, int64_t *f
 
 sos_status sos_filt_backward_batched(sos_batch_t b, const void *x, const void *gy, void *gx, double *gsos,
                                      void *workspace, sos_stream_t stream) {
-  if (!b || !b->adj || !gsos || !workspace) return SOS_E_ARG;
-  if (!batch_descriptors_valid(*b)) return SOS_E_ARG;
-  if (b->adj_items > 0) {
-    if (!x || !gy || !gx) return SOS_E_ARG;
-    const size_t esz = b->io_dtype == SOS_F64 ? 8 : 4;
-    const uintptr_t xb = (uintptr_t)x, gyb = (uintptr_t)gy, gxb = (uintptr_t)gx;
-    const uintptr_t bytes = (uintptr_t)b->total * esz;
-    if ((xb | gyb | gxb | (uintptr_t)workspace) & 15) return SOS_E_ARG;
-    if ((gxb < xb + bytes && xb < gxb + bytes) || (gxb < gyb + bytes && gyb < gxb + bytes)) return SOS_E_ARG;
-  }
-  if ((uintptr_t)gsos & 7) return SOS_E_ARG;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (b->io_dtype == SOS_F32) return launch_adjoint_batched<float>(*b, x, gy, gx, gsos, workspace, s);
-  return launch_adjoint_batched<double>(*b, x, gy, gx, gsos, workspace, s);
+  return backward_batched(STEP_FORWARD | STEP_ADJOINT, b, x, nullptr, gy, gx, gsos, workspace, stream);
 }
 
+sos_status sos_filt_batched_for_backward(sos_batch_t b, const void *x, void *y, void *workspace,
+                                         sos_stream_t stream) {
+  return backward_batched(STEP_FORWARD, b, x, y, nullptr, nullptr, nullptr, workspace, stream);
+}
+
+sos_status sos_filt_backward_batched_stored(sos_batch_t b, const void *x, const void *gy, void *gx, double *gsos,
+                                            void *workspace, sos_stream_t stream) {
+  return backward_batched(STEP_ADJOINT, b, x, nullptr, gy, gx, gsos, workspace, stream);
+}
 
 size_t sos_backward_workspace_size(sos_plan_t p, int64_t n) {
   if (!p || n < 0 || !p->bwd) return 0;
@@ -376,21 +451,17 @@ size_t sos_backward_workspace_size(sos_plan_t p, int64_t n) {
 
 sos_status sos_filt_backward(sos_plan_t p, const void *x, const void *gy, void *gx, double *gsos,
                              int64_t n, void *workspace, sos_stream_t stream) {
-  if (!p || n < 0 || !gsos || !workspace) return SOS_E_ARG;
-  if (!p->bwd || !p->d_bwd_rows) return SOS_E_ARG;   // host-only plan
-  const size_t esz = p->io_dtype == SOS_F64 ? 8 : 4;
-  if (n > 0) {
-    if (!x || !gy || !gx) return SOS_E_ARG;
-    const uintptr_t xb = (uintptr_t)x, gyb = (uintptr_t)gy, gxb = (uintptr_t)gx;
-    const uintptr_t bytes = (uintptr_t)n * esz;
-    if ((xb | gyb | gxb | (uintptr_t)workspace) & 15) return SOS_E_ARG;
-    // gx may not overlap x or gy (tiles read both beyond their own range)
-    if ((gxb < xb + bytes && xb < gxb + bytes) || (gxb < gyb + bytes && gyb < gxb + bytes)) return SOS_E_ARG;
-  }
-  if ((uintptr_t)gsos & 7) return SOS_E_ARG;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  if (p->io_dtype == SOS_F32) return launch_adjoint<float>(*p, x, gy, gx, gsos, n, workspace, s);
-  return launch_adjoint<double>(*p, x, gy, gx, gsos, n, workspace, s);
+  return backward_single(STEP_FORWARD | STEP_ADJOINT, p, x, nullptr, gy, gx, gsos, n, workspace, stream);
+}
+
+sos_status sos_filt_for_backward(sos_plan_t p, const void *x, void *y, int64_t n, void *workspace,
+                                 sos_stream_t stream) {
+  return backward_single(STEP_FORWARD, p, x, y, nullptr, nullptr, nullptr, n, workspace, stream);
+}
+
+sos_status sos_filt_backward_stored(sos_plan_t p, const void *x, const void *gy, void *gx, double *gsos, int64_t n,
+                                    void *workspace, sos_stream_t stream) {
+  return backward_single(STEP_ADJOINT, p, x, nullptr, gy, gx, gsos, n, workspace, stream);
 }
 
 }  // extern "C"

@@ -34,7 +34,8 @@ EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", 
             "sos_workspace_size", "sos_filt", "sos_batch_plan", "sos_batch_destroy",
             "sos_batch_query", "sos_batch_replan", "sos_filt_batched", "sos_batch_tune", "sos_backward_workspace_size",
             "sos_filt_backward", "sos_batch_backward_workspace_size", "sos_batch_query_adjoint",
-            "sos_filt_backward_batched", "sos_status_string"]
+            "sos_filt_backward_batched", "sos_filt_for_backward", "sos_filt_backward_stored",
+            "sos_filt_batched_for_backward", "sos_filt_backward_batched_stored", "sos_status_string"]
 
 _DTYPES = {"f32": SOS_F32, "f64": SOS_F64, "f16": SOS_F16, "bf16": SOS_BF16,
            np.float32: SOS_F32, np.float64: SOS_F64}
@@ -113,11 +114,16 @@ def lib():
         L.sos_batch_backward_workspace_size.restype = ctypes.c_size_t
         L.sos_batch_query_adjoint.argtypes = [vp, p64, p64]
         L.sos_filt_backward_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.sos_filt_for_backward.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.sos_filt_backward_stored.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
+        L.sos_filt_batched_for_backward.argtypes = [vp, vp, vp, vp, vp]
+        L.sos_filt_backward_batched_stored.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt",
                   "sos_batch_plan", "sos_batch_destroy", "sos_batch_query", "sos_batch_replan",
                   "sos_filt_batched",
                   "sos_batch_tune", "sos_filt_backward", "sos_batch_query_adjoint",
-                  "sos_filt_backward_batched"):
+                  "sos_filt_backward_batched", "sos_filt_for_backward", "sos_filt_backward_stored",
+                  "sos_filt_batched_for_backward", "sos_filt_backward_batched_stored"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -399,6 +405,101 @@ def filt_backward(plan: Plan, x, gy, gx=None, stream=None):
                                    ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gsos.data_ptr()), n,
                                    ctypes.c_void_p(wsb.data_ptr()), _stream_ptr(stream)), "sos_filt_backward")
     return gx, gsos
+
+
+def _workspace(given, nbytes, device):
+    import torch
+    if given is None:
+        return torch.empty(max(nbytes, 16), dtype=torch.uint8, device=device)
+    if not (given.is_cuda and given.dtype == torch.uint8 and given.is_contiguous() and given.numel() >= nbytes):
+        raise ValueError("workspace must be a contiguous uint8 device tensor of at least %d bytes" % nbytes)
+    return given
+
+
+def filt_for_backward(plan: Plan, x, y=None, stream=None, workspace=None):
+    """sos_filt_for_backward: (y, workspace) for a training step's forward
+    pass; hand the workspace to filt_backward_stored.  workspace: a uint8
+    device tensor to reuse (allocated when None)."""
+    import torch
+    want = torch.float32 if plan.io_dtype == "f32" else torch.float64
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == want and x.dim() == 1 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous 1-D device tensor of dtype %s" % want)
+    n = x.numel()
+    if y is None:
+        y = torch.empty_like(x)
+    ws = int(lib().sos_backward_workspace_size(plan.handle, n))
+    wsb = _workspace(workspace, ws, x.device)
+    _check(lib().sos_filt_for_backward(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n,
+                                       ctypes.c_void_p(wsb.data_ptr()), _stream_ptr(stream)), "sos_filt_for_backward")
+    return y, wsb
+
+
+def filt_backward_stored(plan: Plan, x, gy, workspace, gx=None, stream=None):
+    """sos_filt_backward_stored: (gx, gsos) from filt_for_backward's
+    workspace (same plan and x)."""
+    import torch
+    want = torch.float32 if plan.io_dtype == "f32" else torch.float64
+    for name, t in (("x", x), ("gy", gy)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.dim() == 1
+                and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous 1-D device tensor of dtype %s" % (name, want))
+    if gy.shape != x.shape:
+        raise ValueError("gy must have the shape of x")
+    n = x.numel()
+    if workspace.numel() < int(lib().sos_backward_workspace_size(plan.handle, n)):
+        raise ValueError("workspace is smaller than this plan needs for n samples")
+    if gx is None:
+        gx = torch.empty_like(x)
+    gsos = torch.empty((plan.K, 6), dtype=torch.float64, device=x.device)
+    _check(lib().sos_filt_backward_stored(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
+                                          ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gsos.data_ptr()), n,
+                                          ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream)),
+           "sos_filt_backward_stored")
+    return gx, gsos
+
+
+def filt_batched_for_backward(batch: Batch, x, y=None, stream=None, workspace=None):
+    """sos_filt_batched_for_backward: (y, workspace) in the batch's layout.
+    workspace: a uint8 device tensor to reuse (allocated when None)."""
+    import torch
+    want = torch.float32 if batch.io_dtype == "f32" else torch.float64
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == want and x.dim() == 1
+            and x.is_contiguous() and x.numel() >= batch.total):
+        raise ValueError("x must be a contiguous 1-D device tensor of dtype %s with %d samples" % (want, batch.total))
+    if y is None:
+        y = torch.zeros_like(x)
+    ws = int(lib().sos_batch_backward_workspace_size(batch.handle))
+    wsb = _workspace(workspace, ws, x.device)
+    _check(lib().sos_filt_batched_for_backward(batch.handle, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(wsb.data_ptr()),
+                                               _stream_ptr(stream)), "sos_filt_batched_for_backward")
+    return y, wsb
+
+
+def filt_backward_batched_stored(batch: Batch, x, gy, workspace, gx=None, stream=None):
+    """sos_filt_backward_batched_stored: (gx, gsos, first_row) from
+    filt_batched_for_backward's workspace."""
+    import torch
+    want = torch.float32 if batch.io_dtype == "f32" else torch.float64
+    for name, t in (("x", x), ("gy", gy)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.dim() == 1
+                and t.is_contiguous() and t.numel() >= batch.total):
+            raise ValueError("%s must be a contiguous 1-D device tensor of dtype %s with %d samples"
+                             % (name, want, batch.total))
+    if workspace.numel() < int(lib().sos_batch_backward_workspace_size(batch.handle)):
+        raise ValueError("workspace is smaller than this batch needs")
+    if gx is None:
+        gx = torch.zeros_like(x)
+    rows = ctypes.c_int64()
+    first = np.zeros(batch.C, np.int64)
+    _check(lib().sos_batch_query_adjoint(batch.handle, ctypes.byref(rows), _i64p(first)), "sos_batch_query_adjoint")
+    gsos = torch.empty((max(rows.value, 1), 6), dtype=torch.float64, device=x.device)
+    _check(lib().sos_filt_backward_batched_stored(batch.handle, ctypes.c_void_p(x.data_ptr()),
+                                                  ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(gx.data_ptr()),
+                                                  ctypes.c_void_p(gsos.data_ptr()),
+                                                  ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream)),
+           "sos_filt_backward_batched_stored")
+    return gx, gsos[:rows.value], first
 
 
 def filt_backward_batched(batch: Batch, x, gy, gx=None, stream=None):

@@ -386,3 +386,80 @@ def test_backward_stash_edges(K):
     ox, os_ = oracle.sosfilt_backward(x.astype(np.float64), sos, g.astype(np.float64))
     assert oracle.rel_rms(rx, ox) < 1e-6
     assert row_err(rs, os_) < 1e-9
+
+
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
+@pytest.mark.parametrize("io", ["f64", "f32"])
+def test_training_step_in_two_calls(io, adjoint):
+    """sos_filt_for_backward then sos_filt_backward_stored: y matches the
+    oracle at the forward bars, and gx and gsos equal sos_filt_backward's
+    bit for bit (the same forward arithmetic fills the workspace)."""
+    dt = np.float64 if io == "f64" else np.float32
+    n = 2 ** 18 + 77
+    sos = W.make_sos(6, 0.5, 0.97, 170)
+    p = S.Plan(sos, io_dtype=io, compute_dtype="f64", N=32, adjoint=adjoint)
+    x = torch.from_numpy(W.make_signal(n, 171, dt)).to(DEV)
+    g = torch.from_numpy(W.grad_seed_signal(n, 171, dt)).to(DEV)
+    y, ws = S.filt_for_backward(p, x)
+    gx2, gs2 = S.filt_backward_stored(p, x, g, ws)
+    gx1, gs1 = S.filt_backward(p, x, g)
+    torch.cuda.synchronize()
+    assert torch.equal(gx1, gx2) and torch.equal(gs1, gs2)
+    ref = oracle.sosfilt(x.cpu().numpy().astype(np.float64), sos)
+    assert oracle.rel_rms(y.cpu().numpy(), ref) < (1e-12 if io == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
+def test_batched_training_step_in_two_calls(adjoint):
+    """The batched pair: y at the channels' samples only (gaps keep their
+    value), matching the oracle; gx and gsos equal the one-call batched
+    backward bit for bit."""
+    lengths = [1, 255, 5000, 70001, 2 ** 17 + 3]
+    offsets, pos = [], 0
+    for i, n in enumerate(lengths):
+        pos = (pos + 3) // 4 * 4 + 1 + i % 3
+        offsets.append(pos)
+        pos += n + 2
+    Ks = [3, 8, 1, 12, 5]
+    sos = [W.make_sos(k, 0.5, 0.95, 180 + c) for c, k in enumerate(Ks)]
+    plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", N=32, adjoint=adjoint) for s_ in sos]
+    b = S.Batch(plans, lengths, offsets=offsets)
+    xs = [W.make_signal(n, 181 + c, np.float32) for c, n in enumerate(lengths)]
+    gs = [W.grad_seed_signal(n, 181 + c, np.float32) for c, n in enumerate(lengths)]
+    xb = np.zeros(b.total, np.float32)
+    gb = np.zeros(b.total, np.float32)
+    for c, o in enumerate(offsets):
+        xb[o:o + lengths[c]] = xs[c]
+        gb[o:o + lengths[c]] = gs[c]
+    xt, gt = torch.from_numpy(xb).to(DEV), torch.from_numpy(gb).to(DEV)
+    y0 = torch.full((b.total,), -7.0, dtype=torch.float32, device=DEV)
+    y, ws = S.filt_batched_for_backward(b, xt, y0)
+    gx2, gs2, _ = S.filt_backward_batched_stored(b, xt, gt, ws)
+    gx1, gs1, _ = S.filt_backward_batched(b, xt, gt)
+    torch.cuda.synchronize()
+    assert torch.equal(gx1, gx2) and torch.equal(gs1, gs2)
+    y = y.cpu().numpy()
+    mask = np.ones(b.total, bool)
+    for c, o in enumerate(offsets):
+        n = lengths[c]
+        mask[o:o + n] = False
+        assert oracle.rel_rms(y[o:o + n], oracle.sosfilt(xs[c].astype(np.float64), sos[c])) < 1e-6, c
+    assert np.all(y[mask] == -7.0)
+
+
+def test_training_step_bad_arguments():
+    import ctypes
+    lib = S.lib()
+    vp = ctypes.c_void_p
+    p = S.Plan(W.make_sos(2, 0.5, 0.9, 190), io_dtype="f32")
+    n = 4096
+    x = torch.zeros(2 * n, dtype=torch.float32, device=DEV)
+    ws = torch.empty(lib.sos_backward_workspace_size(p.handle, n), dtype=torch.uint8, device=DEV)
+    # y overlapping x, y missing, workspace missing
+    assert lib.sos_filt_for_backward(p.handle, vp(x.data_ptr()), vp(x.data_ptr() + 64), n, vp(ws.data_ptr()),
+                                     None) == S.SOS_E_ARG
+    assert lib.sos_filt_for_backward(p.handle, vp(x.data_ptr()), None, n, vp(ws.data_ptr()), None) == S.SOS_E_ARG
+    assert lib.sos_filt_for_backward(p.handle, vp(x.data_ptr()), vp(x.data_ptr() + 4 * n), n, None,
+                                     None) == S.SOS_E_ARG
+    # n == 0 does nothing and succeeds
+    assert lib.sos_filt_for_backward(p.handle, None, None, 0, vp(ws.data_ptr()), None) == S.SOS_OK
