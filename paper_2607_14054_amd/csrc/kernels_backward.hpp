@@ -212,8 +212,10 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
 // Reversed-time adjoint of one row's tile: run-in, then per group
 // lambda = r(gy), and for k = K-1 .. 0 mu = (1/A_k) lambda, the five sums of
 // section k, lambda = B_k mu; the group's final lambda is r(dL/dx).  The
-// tile's sums go to sums[k][0..4]: sum mu[t] u[t], mu[t-1] u[t],
-// mu[t-2] u[t], mu[t-1] w[t], mu[t-2] w[t] (reversed time, t over the tile).
+// tile's sums go to sums[k][tile][0..4] (section-major, so that each
+// section's reduction reads contiguous memory): sum mu[t] u[t],
+// mu[t-1] u[t], mu[t-2] u[t], mu[t-1] w[t], mu[t-2] w[t] (reversed time, t
+// over the tile).
 // u = u_k and w = w_k come from the saved outputs, or (RC) from the group's
 // checkpoint: the group's input in forward time through sections 0 .. k-1
 // (and k, for w_{K-1}), then mirrored into reversed time; those values are
@@ -389,7 +391,8 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   }
   // one lane per row writes the row's sums (rows past the last tile have none)
   if (row_lane() == 0 && tile_index < v.ntiles)
-    for (int i = 0; i < 5 * v.K; ++i) sums[i] = acc[i];
+    for (int k = 0; k < v.K; ++k)
+      for (int j = 0; j < 5; ++j) sums[((int64_t)k * v.ntiles + tile_index) * 5 + j] = acc[5 * k + j];
 }
 
 // LDS doubles per row of the adjoint pass: all-pole states and sums, and
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_kernel(
   const int64_t tile_index = wave * kRows + row;
   typedef AdjLds<N, TI, RC> Lds;
   const int r = w * kRows + row;
-  adjoint_rows<N, TI, B0ONE, RC>(gy, gx, x, saved, as_ctab(tab), as_ctab(bwd), partials + tile_index * 5 * a.K,
+  adjoint_rows<N, TI, B0ONE, RC>(gy, gx, x, saved, as_ctab(tab), as_ctab(bwd), partials,
                                  adj_view(a), tile_index, true, Lds::states(smem, r, a.K), Lds::rowbuf(smem, r),
                                  Lds::stash(smem, r, a.K));
 }
@@ -522,27 +525,30 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_batched_
   typedef AdjLds<N, TI, RC> Lds;
   const int r = w * kRows + row;
   adjoint_rows<N, TI, B0ONE, RC>(gy + c.off, gx + c.off, x + c.off, ws + c.saved_off, as_ctab(c.tab),
-                                 as_ctab(c.bwd), ws + c.partial_off + tile_index * 5 * c.K, adj_view(c),
+                                 as_ctab(c.bwd), ws + c.partial_off, adj_view(c),
                                  tile_index, true, Lds::states(smem, r, kmax), Lds::rowbuf(smem, r),
                                  Lds::stash(smem, r, kmax));
 }
 
 // dL/d(sos) from the per-tile sums of one section: the block sums
-// sums[t][k][j] over the tiles in a fixed order (deterministic), then
+// sums[k][t][j] over the tiles in a fixed order (deterministic), then
 // applies the chain rule through the division by a0: with normalised
 // c = (b0, b1, b2, a1, a2)/a0, dL/db_j = gb_j / a0, dL/da_j = ga_j / a0
 // (j = 1, 2) and dL/da0 = -(gb . (b0, b1, b2) + ga . (a1, a2)) / a0.
+// THREADS: the block size (a power of two); the order of the sums depends
+// on it and on nothing else.
+template <int THREADS>
 __device__ __forceinline__ void adjoint_reduce(const double *__restrict__ partials, int64_t ntiles, int32_t K,
                                                int k, const double *__restrict__ bwd,
                                                double *__restrict__ g) {
-  __shared__ double red[5][256];
+  __shared__ double red[5][THREADS];
   const int tid = threadIdx.x;
   double s[5] = {0, 0, 0, 0, 0};
-  for (int64_t t = tid; t < ntiles; t += 256)
-    for (int j = 0; j < 5; ++j) s[j] += partials[(t * K + k) * 5 + j];
+  for (int64_t t = tid; t < ntiles; t += THREADS)
+    for (int j = 0; j < 5; ++j) s[j] += partials[((int64_t)k * ntiles + t) * 5 + j];
   for (int j = 0; j < 5; ++j) red[j][tid] = s[j];
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = THREADS / 2; h > 0; h >>= 1) {
     if (tid < h)
       for (int j = 0; j < 5; ++j) red[j][tid] += red[j][tid + h];
     __syncthreads();
@@ -561,12 +567,14 @@ __device__ __forceinline__ void adjoint_reduce(const double *__restrict__ partia
   }
 }
 
-// block k: section k of the single signal
-__global__ __launch_bounds__(256) void sos_adjoint_reduce_kernel(const double *__restrict__ partials,
-                                                                 int64_t ntiles, int32_t K,
-                                                                 const double *__restrict__ bwd,
-                                                                 double *__restrict__ gsos) {
-  adjoint_reduce(partials, ntiles, K, blockIdx.x, bwd, gsos + 6 * blockIdx.x);
+// block k: section k of the single signal (one block per section, so a
+// wide one: a long signal has tens of thousands of tiles)
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void sos_adjoint_reduce_kernel(const double *__restrict__ partials,
+                                                                            int64_t ntiles, int32_t K,
+                                                                            const double *__restrict__ bwd,
+                                                                            double *__restrict__ gsos) {
+  adjoint_reduce<kReduceThreads>(partials, ntiles, K, blockIdx.x, bwd, gsos + 6 * blockIdx.x);
 }
 
 // block b: row b of the batch's gsos, i.e. section b - gsos_row of channel
@@ -576,7 +584,7 @@ __global__ __launch_bounds__(256) void sos_adjoint_reduce_batched_kernel(
     double *__restrict__ gsos) {
   const AdjChan &c = chans[red_chan[blockIdx.x]];
   const int k = (int)blockIdx.x - c.gsos_row;
-  adjoint_reduce(ws + c.partial_off, c.ntiles, c.K, k, c.bwd, gsos + 6 * (int64_t)blockIdx.x);
+  adjoint_reduce<256>(ws + c.partial_off, c.ntiles, c.K, k, c.bwd, gsos + 6 * (int64_t)blockIdx.x);
 }
 
 }  // namespace sosf

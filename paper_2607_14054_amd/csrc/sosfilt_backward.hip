@@ -183,7 +183,7 @@ sos_status launch_adjoint(int steps, const sos_plan_s &p, const void *x, void *y
     if (hipGetLastError() != hipSuccess) return SOS_E_DEVICE;
   }
   if (steps & STEP_ADJOINT)
-    hipLaunchKernelGGL(sos_adjoint_reduce_kernel, dim3((unsigned)p.K), dim3(256), 0, s, partials,
+    hipLaunchKernelGGL(sos_adjoint_reduce_kernel, dim3((unsigned)p.K), dim3(kReduceThreads), 0, s, partials,
                        n > 0 ? l.ntiles : (int64_t)0, (int32_t)p.K, rows, gsos);
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }
