@@ -330,12 +330,16 @@ sos_status sos_filt_batched(sos_batch_t batch, const void *x, void *y, void *wor
  *  - recompute: the forward pass stores the cascade state (2K + 2 values)
  *    at every group of 256 samples, and the adjoint recomputes section k's
  *    input from the group's state (K(K-1)/2 + 1 forward section passes per
- *    group).  With FP32 I/O and 4 <= K <= 17 it also keeps section K/2's
- *    input per group in LDS, and recomputes later inputs from it.
- * Measured costs per sample on MI355X are 3.74 + 4.00 K ps (saved) and
- * 4.48 + 1.36 K + 0.38 P ps (recompute, P passes per group; 6.68 + 1.63 K
- * + 0.319 P with the kept input).  So without a flag a plan recomputes for
- * K <= 17 with FP32 I/O and K <= 14 with FP64 I/O.
+ *    group).  It also keeps one or two section inputs per group and
+ *    recomputes later inputs from them: section K/2's in LDS (FP32 I/O,
+ *    4 <= K <= 17) and section K/4's in registers, or section K/2's in
+ *    registers otherwise (K >= 4).  At K = 8 that is 13 passes instead of
+ *    29.
+ * Measured costs per sample on MI355X, in ps: 4.95 + 3.827 K for saved
+ * outputs, plus 6.59 - 0.438 K with FP64 I/O; 4.43 + 1.642 K + 0.321 P for
+ * recompute with P passes per group, plus 3.92 with FP64 I/O.  So without
+ * a flag a plan recomputes for K <= 27 with FP32 I/O and K <= 23 with FP64
+ * I/O.
  *
  * sos_backward_workspace_size -- device bytes sos_filt_backward needs for n
  * samples: the saved outputs (K n doubles, padded) or the group states

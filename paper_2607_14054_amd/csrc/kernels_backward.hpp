@@ -239,6 +239,10 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   TI *buf = reinterpret_cast<TI *>(rowbuf);
   double *dbuf = reinterpret_cast<double *>(rowbuf);
   const int S = RC ? (int)v.stash : 0;
+  // a stash kept in registers: u_S1 with S1 = S / 2 under the LDS stash
+  // (S >= 4), or S1 = K / 2 where there is no LDS stash (K >= 4); u_k for
+  // S1 < k (< S) then takes k - S1 passes
+  const int S1 = !RC ? 0 : (S >= 4 ? S / 2 : (S == 0 && v.K >= 4 ? v.K / 2 : 0));
   constexpr int SRUN = Stage<N, double>::RUN;   // stash doubles per lane (padded)
   double *my_stash = stash + row_lane() * SRUN;
   T *acc = st + 2 * v.K;
@@ -250,7 +254,7 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   const int64_t t0 = tile_index * v.tile;
   const int64_t pad = v.np - v.n;
   const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
-  T X[N], A[N], B[N], F[N];
+  T X[N], A[N], B[N], F[N], R1[N];
   int64_t g = 0;
   bool full = false, live = false;
 
@@ -270,6 +274,10 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
 #pragma unroll
         for (int m = 0; m < N; m += 2) *reinterpret_cast<vd2 *>(my_stash + m) = vd2{F[m], F[m + 1]};
       }
+      if (capture && q + 1 == S1) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) R1[m] = F[m];
+      }
     }
   };
   // RC: F = u_S from the stash through sections S .. upto-1
@@ -287,10 +295,22 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
     for (int q = S; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
   };
   // U = u_k in reversed time
+  // RC: F = u_S1 from the registers through sections S1 .. upto-1
+  auto forward_from_regs = [&](int upto) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) F[m] = R1[m];
+    for (int i = row_lane(); i < SE; i += kL) cw[i] = ck[i];
+    __builtin_amdgcn_wave_barrier();
+    xs2 = cw[2 * S1];
+    xs1 = cw[2 * S1 + 1];
+    for (int q = S1; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
+  };
   auto input_of = [&](int k, T (&U)[N]) {
     if constexpr (RC) {
       if (S > 0 && k >= S)
         forward_from_stash(k);
+      else if (S1 > 0 && k >= S1)
+        forward_from_regs(k);
       else
         forward(k, false);
       to_reversed<N>(U, F);
@@ -369,7 +389,7 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
         const int64_t j = g / G;
         for (int i = row_lane(); i < SE; i += kL) ck[i] = j < v.nck ? saved[j * SE + i] : T(0);
         __builtin_amdgcn_wave_barrier();
-        forward(v.K - 1, S > 0);
+        forward(v.K - 1, S > 0 || S1 > 0);
         to_reversed<N>(A, F);
         ph_section<N, T, B0ONE>(F, ct + (int64_t)(v.K - 1) * v.stride, xs2, xs1, cw + 2 + 2 * (v.K - 1));
         to_reversed<N>(B, F);

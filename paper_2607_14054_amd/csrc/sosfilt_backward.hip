@@ -50,27 +50,39 @@ bool adjoint_stash(bool rc, int io_dtype, int kmax) {
   return rc && io_dtype == SOS_F32 && kmax >= 4 && AdjLds<kBwdN, float, true>::bytes(kmax, true) <= 80 * 1024;
 }
 
+// The recompute mode's stash indices, as the adjoint kernel derives them:
+// S (LDS, 0 if none) and S1 (registers): S1 = S / 2 under an LDS stash of
+// S >= 4, else K / 2 where there is no LDS stash.  Forward section passes
+// per group: K for u_{K-1} and w_{K-1}, then for k = K-2 .. 1, k minus the
+// largest stash index at or below k.
+int adjoint_passes(int K, int S) {
+  const int S1 = S >= 4 ? S / 2 : (S == 0 && K >= 4 ? K / 2 : 0);
+  int passes = K;
+  for (int k = 1; k <= K - 2; ++k) passes += k - (k >= S && S > 0 ? S : (k >= S1 && S1 > 0 ? S1 : 0));
+  return passes;
+}
+
 // Recompute (group checkpoints) or saved outputs, by measured costs per
-// sample (MI355X, 2^24 float32 samples, ps).  Saved outputs move about 16K
-// bytes per sample: 3.74 + 4.00 K.  Recompute takes P forward section
-// passes per group besides the adjoint's own work: without the stash
-// P = K(K-1)/2 + 1 and 4.48 + 1.36 K + 0.38 P; with the stash of u_S
-// (S = K/2) P = K + (K-2-S)(K-1-S)/2 + S(S-1)/2 and 6.68 + 1.63 K + 0.319 P.
-// They cross between K = 14 and 15 without the stash; with it recompute
-// stays cheaper as far as the stash fits (K <= 17).
-double adjoint_cost_saved(int K) { return 3.74 + 4.00 * K; }
-double adjoint_cost_recompute(int K, bool stash) {
-  if (stash && K >= 4) {
-    const double S = K / 2;
-    return 6.68 + 1.63 * K + 0.319 * (K + 0.5 * (K - 2 - S) * (K - 1 - S) + 0.5 * S * (S - 1));
-  }
-  return 4.48 + 1.36 * K + 0.38 * (0.5 * K * (K - 1) + 1);
+// sample (MI355X, 2^24 samples, ps, fitted over K = 1 .. 32 with relative
+// weights):
+//   saved outputs (about 16K bytes per sample): 4.95 + 3.827 K, plus
+//     6.59 - 0.438 K with FP64 I/O;
+//   recompute: 4.43 + 1.642 K + 0.321 P, plus 3.92 with FP64 I/O, P the
+//     passes above.
+// Recompute is the cheaper up to K = 27 (FP32 I/O) and K = 23 (FP64 I/O).
+double adjoint_cost_saved(int K, int io_dtype) {
+  return 4.95 + 3.827 * K + (io_dtype == SOS_F64 ? 6.59 - 0.438 * K : 0.0);
+}
+double adjoint_cost_recompute(int K, int io_dtype, bool stash) {
+  const int S = stash && K >= 4 ? K / 2 : 0;
+  return 4.43 + 1.642 * K + 0.321 * adjoint_passes(K, S) + (io_dtype == SOS_F64 ? 3.92 : 0.0);
 }
 
 bool adjoint_recompute(const sos_plan_s &p) {
   if (p.flags & SOS_FLAG_ADJ_RECOMPUTE) return true;
   if (p.flags & SOS_FLAG_ADJ_SAVE) return false;
-  return adjoint_cost_recompute(p.K, adjoint_stash(true, p.io_dtype, p.K)) < adjoint_cost_saved(p.K);
+  return adjoint_cost_recompute(p.K, p.io_dtype, adjoint_stash(true, p.io_dtype, p.K)) <
+         adjoint_cost_saved(p.K, p.io_dtype);
 }
 
 }  // namespace sosf
@@ -280,8 +292,8 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
   for (int c = 0; c < b.C; ++c) {
     any_save = any_save || (plans[c]->flags & SOS_FLAG_ADJ_SAVE);
     any_rc = any_rc || (plans[c]->flags & SOS_FLAG_ADJ_RECOMPUTE);
-    cost_rc += (double)b.n[c] * adjoint_cost_recompute(plans[c]->K, adjoint_stash(true, b.io_dtype, b.kmax));
-    cost_saved += (double)b.n[c] * adjoint_cost_saved(plans[c]->K);
+    cost_rc += (double)b.n[c] * adjoint_cost_recompute(plans[c]->K, b.io_dtype, adjoint_stash(true, b.io_dtype, b.kmax));
+    cost_saved += (double)b.n[c] * adjoint_cost_saved(plans[c]->K, b.io_dtype);
   }
   b.adj_rc = !any_save && (any_rc || cost_rc < cost_saved);
   b.adj_stash = adjoint_stash(b.adj_rc, b.io_dtype, b.kmax);

@@ -88,13 +88,13 @@ def test_backward_recompute_equals_saved_outputs(io, K):
 
 
 def test_backward_mode_choice_and_workspace():
-    """Automatic mode: recompute (checkpoints: 2K + 2 doubles per 256-sample
-    group) up to K = 17 with FP32 I/O (where section K/2's input is also
-    kept in LDS) and K = 14 with FP64 I/O, saved outputs above (K doubles
-    per sample); both flags together are rejected."""
+    """Automatic mode by the measured cost model: recompute (checkpoints:
+    2K + 2 doubles per 256-sample group) up to K = 27 with FP32 I/O and
+    K = 23 with FP64 I/O, saved outputs above (K doubles per sample); both
+    flags together are rejected."""
     n = 2 ** 20
-    for io, cases in (("f32", ((1, True), (8, True), (16, True), (17, True), (18, False), (40, False))),
-                      ("f64", ((1, True), (8, True), (14, True), (15, False), (40, False)))):
+    for io, cases in (("f32", ((1, True), (8, True), (17, True), (18, True), (27, True), (28, False), (40, False))),
+                      ("f64", ((1, True), (8, True), (23, True), (24, False), (40, False)))):
         for K, rc in cases:
             sos = W.make_sos(K, 0.5, 0.95, 150 + K)
             auto = S.Plan(sos, io_dtype=io).backward_workspace_size(n)
@@ -212,7 +212,8 @@ def test_batched_adjoint_mode_choice():
     """One adjoint mode per batch: saved outputs if any plan asks for them,
     else recompute if any asks for it, else the cheaper one over the batch's
     samples (K = 2 and 4 channels recompute; a batch dominated by K = 32
-    keeps the outputs).  The workspace shows the mode."""
+    keeps the outputs, one dominated by K = 4 recomputes).  The workspace
+    shows the mode."""
     def ws(Ks, modes, lengths=(5000, 70001)):
         plans = [S.Plan(W.make_sos(k, 0.5, 0.95, 190 + i), io_dtype="f32", adjoint=m)
                  for i, (k, m) in enumerate(zip(Ks, modes))]
@@ -223,7 +224,7 @@ def test_batched_adjoint_mode_choice():
     assert ws([2, 4], ["recompute", "auto"]) < saved_bytes / 4
     assert ws([2, 4], ["recompute", "save"]) >= saved_bytes
     assert ws([2, 32], ["auto", "auto"]) >= 8 * (2 * 5000 + 32 * 70001)
-    assert ws([32, 2], ["auto", "auto"], (1000, 200000)) < 8 * (32 * 1000 + 2 * 200000) / 4
+    assert ws([32, 4], ["auto", "auto"], (1000, 200000)) < 8 * (32 * 1000 + 4 * 200000) / 4
 
 
 @pytest.mark.parametrize("adjoint", ["save", "recompute"])
