@@ -370,12 +370,13 @@ def test_adjoint_graph_replays_match_eager(adjoint):
         assert torch.equal(got_x, gx) and torch.equal(got_s, gs), rep
 
 
-@pytest.mark.parametrize("K", [4, 5, 17])
+@pytest.mark.parametrize("K", [4, 5, 8, 17, 18, 21])
 def test_backward_stash_edges(K):
-    """FP32 I/O recompute with the stash of section K/2's input: its
-    smallest K (4, 5) and the largest whose stash fits two workgroups per
-    CU (17).  Equal to the saved-output mode to rounding and to the oracle
-    adjoint."""
+    """FP32 I/O recompute with its stashes of section inputs: the LDS stash
+    alone (K = 4, 5), LDS and register stashes (8, and 17, the largest
+    whose LDS stash fits two workgroups per CU), and the register stash
+    alone (18, 21).  Equal to the saved-output mode to rounding and to the
+    oracle adjoint."""
     n = 2 ** 17 + 333
     sos = W.make_sos(K, 0.5, 0.97, 160 + K)
     x = W.make_signal(n, 161, np.float32)
