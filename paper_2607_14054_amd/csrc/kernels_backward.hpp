@@ -224,11 +224,13 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
 // in turn (no copies between steps).
 // st: 7K values (2K all-pole output states, then 5K running sums); RC adds
 // the group's checkpoint and a working copy of it (2 + 2K each).
-// RC with v.stash = S > 0: the first pass of a group leaves u_S (forward
-// layout) in the row's stash, one FP64 group in LDS, and u_k for k > S is
-// recomputed from it (k - S passes instead of k).  rowbuf: the row's stage,
-// FP64 in the saved-output mode (which reads FP64 groups), else of the I/O
-// type.
+// RC keeps section inputs from the first pass of each group and
+// recomputes later ones from the nearest kept one below: with v.stash =
+// S > 0, u_S in the row's LDS stash (one FP64 group, forward layout) and
+// u_{S/2} in registers; with no LDS stash, u_{K/2} in registers (K >= 4).
+// u_k then takes k - s passes, s the kept index at or below k.  rowbuf:
+// the row's stage, FP64 in the saved-output mode (which reads FP64
+// groups), else of the I/O type.
 template <int N, typename TI, bool B0ONE, bool RC>
 __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__restrict__ gx,
                                              const TI *__restrict__ x, const double *__restrict__ saved,
@@ -294,7 +296,6 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
     xs1 = cw[2 * S + 1];
     for (int q = S; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
   };
-  // U = u_k in reversed time
   // RC: F = u_S1 from the registers through sections S1 .. upto-1
   auto forward_from_regs = [&](int upto) {
 #pragma unroll
@@ -305,6 +306,7 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
     xs1 = cw[2 * S1 + 1];
     for (int q = S1; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
   };
+  // U = u_k in reversed time
   auto input_of = [&](int k, T (&U)[N]) {
     if constexpr (RC) {
       if (S > 0 && k >= S)
