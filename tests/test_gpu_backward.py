@@ -465,3 +465,23 @@ def test_training_step_bad_arguments():
                                      None) == S.SOS_E_ARG
     # n == 0 does nothing and succeeds
     assert lib.sos_filt_for_backward(p.handle, None, None, 0, vp(ws.data_ptr()), None) == S.SOS_OK
+
+
+@pytest.mark.parametrize("io", ["f64", "f32"])
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
+def test_backward_k64(io, adjoint):
+    """K = 64, the plan limit, in both modes (the automatic choice keeps
+    the outputs here; recompute runs about 1000 forward passes per group
+    with its register stash): against the oracle adjoint."""
+    dt = np.float64 if io == "f64" else np.float32
+    n = 2 ** 14 + 5
+    sos = W.make_sos(64, 0.5, 0.9, 195)
+    x = W.make_signal(n, 196, dt)
+    g = W.grad_seed_signal(n, 196, dt)
+    gx, gs = run_backward(sos, x, g, adjoint=adjoint)
+    if io == "f64":
+        check_f64(x, sos, g, gx, gs, "K=64 %s" % adjoint)
+    else:
+        rx, rs = oracle.sosfilt_backward(x.astype(np.float64), sos, g.astype(np.float64))
+        assert oracle.rel_rms(gx, rx) < 1e-6
+        assert row_err(gs, rs) < 1e-9
