@@ -118,6 +118,23 @@ void launch_single(int steps, const BwdArgs &f, const BwdArgs &a, int K, const v
   }
 }
 
+// The adjoint kernel's own residency (it keeps fewer wavefronts per SIMD
+// than the forward kernel of the sub-plan), for its launch shape.
+Residency adjoint_residency(int io_dtype, bool rc, int K, bool stash) {
+  const void *k;
+  size_t lds;
+  if (io_dtype == SOS_F32) {
+    k = rc ? reinterpret_cast<const void *>(&sos_rows_adjoint_kernel<kBwdN, float, true, true>)
+           : reinterpret_cast<const void *>(&sos_rows_adjoint_kernel<kBwdN, float, true, false>);
+    lds = rc ? AdjLds<kBwdN, float, true>::bytes(K, stash) : AdjLds<kBwdN, float, false>::bytes(K, false);
+  } else {
+    k = rc ? reinterpret_cast<const void *>(&sos_rows_adjoint_kernel<kBwdN, double, true, true>)
+           : reinterpret_cast<const void *>(&sos_rows_adjoint_kernel<kBwdN, double, true, false>);
+    lds = rc ? AdjLds<kBwdN, double, true>::bytes(K, stash) : AdjLds<kBwdN, double, false>::bytes(K, false);
+  }
+  return residency_of(k, lds, kWavesPerBlock * 64);
+}
+
 struct BwdLayout {
   bool rc;                  // recompute mode
   int64_t stash;            // recompute mode: S (0: no stash)
@@ -134,7 +151,12 @@ BwdLayout layout(const sos_plan_s &p, int64_t n) {
   l.rc = adjoint_recompute(p);
   l.stash = adjoint_stash(l.rc, p.io_dtype, p.K) ? p.K / 2 : 0;
   l.np = (n + V - 1) / V * V;
-  l.tile = sos_plan_tile(p.bwd, std::max<int64_t>(l.np, 1));
+  if (p.bwd->tile_groups > 0) {
+    l.tile = sos_plan_tile(p.bwd, std::max<int64_t>(l.np, 1));
+  } else {
+    const Residency r = adjoint_residency(p.io_dtype, l.rc, p.K, l.stash > 0);
+    l.tile = model_tile_groups((std::max<int64_t>(l.np, 1) + G - 1) / G, p.bwd->warm / G, r) * G;
+  }
   l.ntiles = (l.np + l.tile - 1) / l.tile;
   l.sstride = (n + 63) / 64 * 64;
   if (l.rc) {
