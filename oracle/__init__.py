@@ -16,6 +16,9 @@ source for the adjoint's derivation from Section III's matrix form):
 * ``sosfilt_f32arith(x, sos)``   -> y evaluated in plain float32
 * ``sosfilt_backward(x, sos, g)``-> (dL/dx, dL/dsos) for L = sum(y * g)
 * ``sosfilt_batch(xs, soss)``    -> list of y, channels on host threads
+
+``oracle.method`` takes the method's own steps in FP64, and
+``oracle.lowprec`` models block filtering with FP16 / BF16 products.
 """
 from __future__ import annotations
 
