@@ -449,6 +449,60 @@ def test_batched_training_step_in_two_calls(adjoint):
     assert np.all(y[mask] == -7.0)
 
 
+
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
+def test_batched_training_step_graph_replays_match_eager(adjoint):
+    """The batched two-call training step (forward that fills the workspace,
+    then the stored adjoint) captured in one HIP graph: with new x and gy
+    before each of three replays, y, gx and gsos equal the eager pair's bit
+    for bit."""
+    import ctypes
+    lib = S.lib()
+    lengths = [300, 5000, 2 ** 16 + 9]
+    Ks = [2, 8, 5]
+    sos = [W.make_sos(k, 0.5, 0.95, 190 + c) for c, k in enumerate(Ks)]
+    plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", N=32, adjoint=adjoint) for s_ in sos]
+    b = S.Batch(plans, lengths)
+    T = b.total
+    x = torch.zeros(T, dtype=torch.float32, device=DEV)
+    g = torch.zeros_like(x)
+    y, gx = torch.zeros_like(x), torch.zeros_like(x)
+    gs = torch.zeros((sum(Ks), 6), dtype=torch.float64, device=DEV)
+    ws = torch.empty(max(b.backward_workspace_size(), 16), dtype=torch.uint8, device=DEV)
+    vp = ctypes.c_void_p
+
+    def fill(seed):
+        x.copy_(torch.from_numpy(W.make_signal(T, seed, np.float32)).to(DEV))
+        g.copy_(torch.from_numpy(W.grad_seed_signal(T, seed, np.float32)).to(DEV))
+
+    def step(stream):
+        sp = vp(stream.cuda_stream)
+        assert lib.sos_filt_batched_for_backward(b.handle, vp(x.data_ptr()), vp(y.data_ptr()),
+                                                 vp(ws.data_ptr()), sp) == 0
+        assert lib.sos_filt_backward_batched_stored(b.handle, vp(x.data_ptr()), vp(g.data_ptr()),
+                                                    vp(gx.data_ptr()), vp(gs.data_ptr()),
+                                                    vp(ws.data_ptr()), sp) == 0
+
+    fill(195)
+    step(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=torch.cuda.Stream()):
+        step(torch.cuda.current_stream())
+    for rep in range(3):
+        fill(196 + rep)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (y.clone(), gx.clone(), gs.clone())
+        step(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert torch.equal(got[0], y) and torch.equal(got[1], gx) and torch.equal(got[2], gs), rep
+    # and the eager result is the oracle's on one channel
+    o, n = b.offsets[1], lengths[1]
+    ref = oracle.sosfilt(x[o:o + n].cpu().numpy().astype(np.float64), sos[1])
+    assert oracle.rel_rms(y[o:o + n].cpu().numpy(), ref) < 1e-6
+
 def test_training_step_bad_arguments():
     import ctypes
     lib = S.lib()
