@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -21,6 +22,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def algorithmic_fma_per_sample(solvers, N, L):
+    """The paper's FMA count per sample of the cascade (Tables I and III):
+    per PH section 6 + (2 log2 L - 4) / N, per CR section 6 + (L - 1) / N
+    (its terminal Toeplitz block); one per section of the list."""
+    lg = int(math.log2(L))
+    return sum(6.0 + ((2 * lg - 4) if s == "ph" else (L - 1)) / N for s in solvers)
 
 
 def log(*a):
@@ -634,6 +644,9 @@ def main():
     sec = timed_filter(S, torch, plan, x, y, args.steps, args.warmup)
     gsps = n / sec / 1e9
     achieved = 8.0 * n / sec / 1e9
+    # the same launch priced in FP64 vector arithmetic, its measured bound
+    fma_ps = algorithmic_fma_per_sample(info.solver, info.N, info.L)
+    alu_tflops = 2.0 * fma_ps * n / sec / 1e12
     log("main: N=%d solvers=%s warm=%d tile=%d waves/SIMD=%d  %.3f ms/step  %.1f GS/s  %.0f GB/s"
         % (N, info.solver, info.warm_samples, plan.tile(n), info.waves_per_simd, sec * 1e3, gsps,
            achieved))
@@ -751,6 +764,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(N, args.solver, info.solver, n)},
+        "alu_roofline": {"bound": "alu", "achieved": alu_tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": alu_tflops / FP64_VECTOR_PEAK_TFLOPS,
+                         "flop_per_sample": 2.0 * fma_ps},
         "cpu_baseline": cpu,
         "cpu_comparator": comparator,
         "accuracy": accuracy,

@@ -150,6 +150,23 @@ def test_operation_counts_match_tables(N, L):
     assert ops["reduction_shuffle"] == lgN and ops["backsub_shuffle"] == lgN + 1
 
 
+
+@pytest.mark.parametrize("N,L", [(64, 16), (8, 16), (32, 64)])
+def test_bench_flop_count_is_the_models(N, L):
+    """The FP64 roofline that bench.py reports prices each section at the
+    FMAs per sample that the method model counts per group (Tables I, III)."""
+    import bench
+    X = np.random.default_rng(4).standard_normal((N, L))
+    per = {}
+    for solver, solve, keys in (("ph", M.ph_solve, ("particular_fma", "rd_fma", "homog_fma")),
+                                ("cr", M.cr_solve, ("reduction_fma", "terminal_fma", "backsub_fma"))):
+        ops = Counter()
+        V = M.nonrecursive_stage(X, 1.0, 0.1, 0.2, -0.5, 0.3, (0, 0), (0, 0), ops)
+        solve(V, -0.5, 0.3, ops)
+        per[solver] = (ops["nonrec_fma"] + sum(ops[k] for k in keys)) / N
+    got = bench.algorithmic_fma_per_sample(["ph", "cr", "ph"], N, L)
+    assert got == pytest.approx(2 * per["ph"] + per["cr"], rel=1e-15)
+
 def test_method_in_float32_is_near_plain_float32():
     """The FP32 accuracy floor: the method in float32 lands at the level of a
     plain float32 sequential cascade on the same draw (both far from FP64)."""
