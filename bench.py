@@ -6,6 +6,11 @@ One step = one call of sos_filt over the whole signal: a K = 8 cascade over
 arithmetic inside the kernel, input already resident in HBM.  Prints one JSON
 line; extra detail (per-solver/N sweep, copy ceiling) goes to stderr and, with
 --out, to a JSON file.
+
+The FP64 oracle (test infrastructure) runs only in the CPU leg, which
+--no-cpu skips as a whole: the oracle's own timing (`cpu_baseline`) and the
+accuracy checks of the headline and of the forms against it.  The filter
+itself always runs through the HIP library.
 """
 from __future__ import annotations
 
@@ -603,7 +608,8 @@ def main():
                     help="also the run-in against the exact scan carry on long-run-in single signals")
     ap.add_argument("--draws", action="store_true",
                     help="also the kernel's and the FP32 floor's error over 16 coefficient draws")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU leg: the oracle's timing and every accuracy check that runs the oracle")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, adjoint and precision forms that the default run reports "
                          "beside the plain one")
@@ -705,7 +711,7 @@ def main():
         extra["stream"] = bench_stream(S, W, torch, dev, args)
     if args.precision:
         extra["precision"] = bench_precision(S, W, torch, dev, args)
-    if args.draws:
+    if args.draws and not args.no_cpu:   # an accuracy-only leg: part of the CPU leg
         extra["draws"] = bench_draws(S, W, torch, dev, args)
     if args.carry:
         extra["carry"] = bench_carry(S, W, torch, dev, args)
