@@ -174,6 +174,26 @@ def test_block_batched_low_precision_matches_rounding_model(dtype):
         _emulation_check(y[o:o + lengths[c]], xs[c], sos[c], dtype, -(o % 4), "channel %d shift %d" % (c, o % 4))
 
 
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_block_low_precision_full_precision_workload(dtype):
+    """The precision workload at its full size, in the launch the benchmark
+    times (256 channels x 2^20 float32 samples, K = 8, r in [0.9, 0.999],
+    one batched launch): sampled channels against the rounding model."""
+    cfg = W.CONFIGS["precision"]
+    C, n = cfg.channels, cfg.n
+    sos = [W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed + c) for c in range(C)]
+    xb = torch.empty(C * n, dtype=torch.float32, device=DEV)
+    for c in range(C):
+        xb[c * n:(c + 1) * n] = torch.from_numpy(W.make_signal(n, cfg.seed + c, np.float32)).to(DEV)
+    plans = [S.Plan(s_, io_dtype="f32", compute_dtype=dtype, solver="block", N=64) for s_ in sos]
+    b = S.Batch(plans, [n] * C)
+    y = S.filt_batched(b, xb)
+    torch.cuda.synchronize()
+    for c in (0, C - 1):
+        x_c = xb[c * n:(c + 1) * n].cpu().numpy()
+        _emulation_check(y[c * n:(c + 1) * n].cpu().numpy(), x_c, sos[c], dtype, 0, "precision channel %d" % c)
+
 def test_low_precision_only_with_block():
     sos = W.make_sos(2, 0.5, 0.9, 69)
     for dt in ("f16", "bf16"):
