@@ -19,6 +19,14 @@ source for the adjoint's derivation from Section III's matrix form):
 
 ``oracle.method`` takes the method's own steps in FP64, and
 ``oracle.lowprec`` models block filtering with FP16 / BF16 products.
+
+Pins: ``tests/test_oracle.py`` (the FP64 cascade and its adjoint: closed
+forms, frequency response, dense solves, finite differences),
+``tests/test_oracle_twins.py`` (``sosfilt_ld`` against the exact recurrence
+and 50-digit closed forms where FP64 loses digits; ``sosfilt_f32arith``
+bit-exact where FP32 arithmetic is exact, and at scipy's single-precision
+error elsewhere; ``sosfilt_batch`` against closed forms per channel),
+``tests/test_method_model.py`` and ``tests/test_oracle_lowprec.py``.
 """
 from __future__ import annotations
 
@@ -168,7 +176,9 @@ def sosfilt_backward_ld(x, sos, gy):
 
 
 def sosfilt_batch(xs, soss, threads: int | None = None):
-    """Filter independent channels, one host thread per channel at a time."""
+    """Filter independent channels (list of 1-D arrays, list of [K, 6] rows)
+    with ``sosfilt``, one host thread per channel at a time (the C library
+    releases the GIL); returns the FP64 outputs in channel order."""
     _load()
     threads = threads or os.cpu_count() or 1
     with ThreadPoolExecutor(max_workers=threads) as ex:
