@@ -229,6 +229,14 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on(stream):
+    """Context in which the binding allocates what a launch on `stream`
+    uses: the caching allocator then ties those blocks to that stream, so it
+    does not hand them out again while the launch may still run."""
+    import torch
+    return torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream())
+
+
 def filt(plan: Plan, x, y=None, stream=None):
     """y = cascade(x) for a 1-D CUDA (HIP) tensor x of the plan's io dtype."""
     import torch
@@ -237,12 +245,17 @@ def filt(plan: Plan, x, y=None, stream=None):
         raise ValueError("x must be a 1-D device tensor of dtype %s" % want)
     x = x.contiguous()
     if y is None:
-        y = torch.empty_like(x)
+        with _on(stream):
+            y = torch.empty_like(x)
     if not (y.is_cuda and y.dtype == want and y.shape == x.shape and y.is_contiguous()):
         raise ValueError("y must be a contiguous device tensor like x")
     n = x.numel()
     ws = plan.workspace_size(n)
-    wsb = torch.empty(ws, dtype=torch.uint8, device=x.device) if ws else None
+    # the temporary workspace belongs to the launch stream: allocated there,
+    # the caching allocator does not hand it out again before the kernels
+    # enqueued on that stream have run
+    with _on(stream):
+        wsb = torch.empty(ws, dtype=torch.uint8, device=x.device) if ws else None
     _check(lib().sos_filt(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                           n, ctypes.c_void_p(wsb.data_ptr()) if wsb is not None else None,
                           _stream_ptr(stream)), "sos_filt")
@@ -347,7 +360,8 @@ def filt_batched(batch: Batch, x, y=None, stream=None):
         raise ValueError("x must be a contiguous 1-D device tensor of dtype %s with %d samples"
                          % (want, batch.total))
     if y is None:
-        y = torch.zeros_like(x)
+        with _on(stream):
+            y = torch.zeros_like(x)
     if not (y.is_cuda and y.dtype == want and y.numel() >= batch.total and y.is_contiguous()):
         raise ValueError("y must be a contiguous device tensor like x")
     _check(lib().sos_filt_batched(batch.handle, ctypes.c_void_p(x.data_ptr()),
@@ -396,11 +410,12 @@ def filt_backward(plan: Plan, x, gy, gx=None, stream=None):
     if gy.shape != x.shape:
         raise ValueError("gy must have the shape of x")
     n = x.numel()
-    if gx is None:
-        gx = torch.empty_like(x)
-    gsos = torch.empty((plan.K, 6), dtype=torch.float64, device=x.device)
     ws = int(lib().sos_backward_workspace_size(plan.handle, n))
-    wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=x.device)
+    with _on(stream):
+        if gx is None:
+            gx = torch.empty_like(x)
+        gsos = torch.empty((plan.K, 6), dtype=torch.float64, device=x.device)
+        wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=x.device)
     _check(lib().sos_filt_backward(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
                                    ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gsos.data_ptr()), n,
                                    ctypes.c_void_p(wsb.data_ptr()), _stream_ptr(stream)), "sos_filt_backward")
@@ -425,10 +440,11 @@ def filt_for_backward(plan: Plan, x, y=None, stream=None, workspace=None):
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == want and x.dim() == 1 and x.is_contiguous()):
         raise ValueError("x must be a contiguous 1-D device tensor of dtype %s" % want)
     n = x.numel()
-    if y is None:
-        y = torch.empty_like(x)
     ws = int(lib().sos_backward_workspace_size(plan.handle, n))
-    wsb = _workspace(workspace, ws, x.device)
+    with _on(stream):
+        if y is None:
+            y = torch.empty_like(x)
+        wsb = _workspace(workspace, ws, x.device)
     _check(lib().sos_filt_for_backward(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), n,
                                        ctypes.c_void_p(wsb.data_ptr()), _stream_ptr(stream)), "sos_filt_for_backward")
     return y, wsb
@@ -448,9 +464,10 @@ def filt_backward_stored(plan: Plan, x, gy, workspace, gx=None, stream=None):
     n = x.numel()
     if workspace.numel() < int(lib().sos_backward_workspace_size(plan.handle, n)):
         raise ValueError("workspace is smaller than this plan needs for n samples")
-    if gx is None:
-        gx = torch.empty_like(x)
-    gsos = torch.empty((plan.K, 6), dtype=torch.float64, device=x.device)
+    with _on(stream):
+        if gx is None:
+            gx = torch.empty_like(x)
+        gsos = torch.empty((plan.K, 6), dtype=torch.float64, device=x.device)
     _check(lib().sos_filt_backward_stored(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(gy.data_ptr()),
                                           ctypes.c_void_p(gx.data_ptr()), ctypes.c_void_p(gsos.data_ptr()), n,
                                           ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream)),
@@ -466,10 +483,11 @@ def filt_batched_for_backward(batch: Batch, x, y=None, stream=None, workspace=No
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == want and x.dim() == 1
             and x.is_contiguous() and x.numel() >= batch.total):
         raise ValueError("x must be a contiguous 1-D device tensor of dtype %s with %d samples" % (want, batch.total))
-    if y is None:
-        y = torch.zeros_like(x)
     ws = int(lib().sos_batch_backward_workspace_size(batch.handle))
-    wsb = _workspace(workspace, ws, x.device)
+    with _on(stream):
+        if y is None:
+            y = torch.zeros_like(x)
+        wsb = _workspace(workspace, ws, x.device)
     _check(lib().sos_filt_batched_for_backward(batch.handle, ctypes.c_void_p(x.data_ptr()),
                                                ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(wsb.data_ptr()),
                                                _stream_ptr(stream)), "sos_filt_batched_for_backward")
@@ -488,12 +506,13 @@ def filt_backward_batched_stored(batch: Batch, x, gy, workspace, gx=None, stream
                              % (name, want, batch.total))
     if workspace.numel() < int(lib().sos_batch_backward_workspace_size(batch.handle)):
         raise ValueError("workspace is smaller than this batch needs")
-    if gx is None:
-        gx = torch.zeros_like(x)
     rows = ctypes.c_int64()
     first = np.zeros(batch.C, np.int64)
     _check(lib().sos_batch_query_adjoint(batch.handle, ctypes.byref(rows), _i64p(first)), "sos_batch_query_adjoint")
-    gsos = torch.empty((max(rows.value, 1), 6), dtype=torch.float64, device=x.device)
+    with _on(stream):
+        if gx is None:
+            gx = torch.zeros_like(x)
+        gsos = torch.empty((max(rows.value, 1), 6), dtype=torch.float64, device=x.device)
     _check(lib().sos_filt_backward_batched_stored(batch.handle, ctypes.c_void_p(x.data_ptr()),
                                                   ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(gx.data_ptr()),
                                                   ctypes.c_void_p(gsos.data_ptr()),
@@ -514,14 +533,15 @@ def filt_backward_batched(batch: Batch, x, gy, gx=None, stream=None):
                 and t.is_contiguous() and t.numel() >= batch.total):
             raise ValueError("%s must be a contiguous 1-D device tensor of dtype %s with %d samples"
                              % (name, want, batch.total))
-    if gx is None:
-        gx = torch.zeros_like(x)
     rows = ctypes.c_int64()
     first = np.zeros(batch.C, np.int64)
     _check(lib().sos_batch_query_adjoint(batch.handle, ctypes.byref(rows), _i64p(first)), "sos_batch_query_adjoint")
-    gsos = torch.empty((max(rows.value, 1), 6), dtype=torch.float64, device=x.device)
     ws = int(lib().sos_batch_backward_workspace_size(batch.handle))
-    wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=x.device)
+    with _on(stream):
+        if gx is None:
+            gx = torch.zeros_like(x)
+        gsos = torch.empty((max(rows.value, 1), 6), dtype=torch.float64, device=x.device)
+        wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=x.device)
     _check(lib().sos_filt_backward_batched(batch.handle, ctypes.c_void_p(x.data_ptr()),
                                            ctypes.c_void_p(gy.data_ptr()), ctypes.c_void_p(gx.data_ptr()),
                                            ctypes.c_void_p(gsos.data_ptr()), ctypes.c_void_p(wsb.data_ptr()),
