@@ -51,7 +51,9 @@ typedef enum {
     SOS_E_UNSTABLE = 3,     /* a section with |a2| >= 1 or |a1| >= 1 + a2 (after a0 division) */
     SOS_E_UNSUPPORTED = 4,  /* N, L, dtype combination or K not built */
     SOS_E_DEVICE = 5,       /* a HIP call failed (no device, launch error) */
-    SOS_E_NOMEM = 6         /* host or device allocation failed (plan creation only) */
+    SOS_E_NOMEM = 6,        /* host or device allocation failed (plan creation only) */
+    SOS_E_SCRATCH = 7       /* sos_filt_static: the call needs more workspace than the
+                               library's static buffer holds (SOS_STATIC_SCRATCH_BYTES) */
 } sos_status;
 
 typedef enum {
@@ -215,6 +217,30 @@ size_t sos_workspace_size(sos_plan_t plan, int64_t n);
  */
 sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
                     void *workspace, sos_stream_t stream);
+
+/*
+ * sos_filt_static -- sos_filt for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same result as sos_filt(plan, x, y, n, ws, stream) with a
+ * workspace of sos_workspace_size(plan, n) bytes, but the workspace is a
+ * fixed buffer of SOS_STATIC_SCRATCH_BYTES inside the library's device code,
+ * one per GPU, held from the first call on that GPU until the process ends.
+ *
+ * x, y, n, stream  as sos_filt (device x and y on the current device, which
+ *                  must be the plan's).
+ * Returns SOS_E_SCRATCH, enqueuing nothing, when sos_workspace_size(plan, n)
+ * exceeds SOS_STATIC_SCRATCH_BYTES (only the exact carry uses a workspace;
+ * calls that carry by the run-in need none).  The first call on a device
+ * looks up the buffer's address there (SOS_E_DEVICE if that fails).  No
+ * allocation, no synchronisation.  Every call on one GPU uses the same
+ * buffer, whatever the plan or stream: calls whose launches can overlap on
+ * one GPU (different streams, or different host threads without ordering)
+ * race on it and must be serialised by the caller.  The buffer keeps the
+ * last call's contents; the kernels write every word they read first.
+ */
+#define SOS_STATIC_SCRATCH_BYTES (16u << 20)
+
+sos_status sos_filt_static(sos_plan_t plan, const void *x, void *y, int64_t n, sos_stream_t stream);
 
 /*
  * Batched ragged channels (one launch for many independent signals, each

@@ -107,5 +107,8 @@ CarryLayout carry_layout(const sos_plan_s &p, int64_t n, int64_t runin_tile);
 sos_status launch_carry(const sos_plan_s &p, const CarryLayout &l, const void *x, void *y, int64_t n, void *ws,
                         hipStream_t s);
 }
+namespace sosf {
+sos_status check_filt_args(const sos_plan_s &p, const void *x, const void *y, int64_t n);
+}
 sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
                        sos_plan_t *out);

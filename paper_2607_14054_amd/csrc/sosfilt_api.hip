@@ -219,6 +219,21 @@ int64_t choose_tile(const sos_plan_s &p, int64_t n) {
 
 }  // namespace
 
+namespace sosf {
+
+// sos_filt's checks of x, y and the plan for n > 0 samples.
+sos_status check_filt_args(const sos_plan_s &p, const void *x, const void *y, int64_t n) {
+  if (!x || !y) return SOS_E_ARG;
+  if (!p.d_table) return SOS_E_ARG;   // a host-only plan cannot filter
+  const size_t esz = p.io_dtype == SOS_F64 ? 8 : 4;
+  const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y;
+  if (xb < yb + (uintptr_t)n * esz && yb < xb + (uintptr_t)n * esz) return SOS_E_ARG;   // overlap
+  if ((xb | yb) & 15) return SOS_E_ARG;   // 16-byte vector access
+  return SOS_OK;
+}
+
+}  // namespace sosf
+
 extern "C" {
 
 const char *sos_status_string(sos_status s) {
@@ -230,6 +245,7 @@ const char *sos_status_string(sos_status s) {
     case SOS_E_UNSUPPORTED: return "unsupported configuration";
     case SOS_E_DEVICE: return "HIP device error";
     case SOS_E_NOMEM: return "out of memory";
+    case SOS_E_SCRATCH: return "workspace needed exceeds the static scratch buffer (SOS_STATIC_SCRATCH_BYTES)";
   }
   return "unknown status";
 }
@@ -423,12 +439,8 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
                     sos_stream_t stream) {
   if (!p || n < 0) return SOS_E_ARG;
   if (n == 0) return SOS_OK;
-  if (!x || !y) return SOS_E_ARG;
-  if (!p->d_table) return SOS_E_ARG;   // a host-only plan cannot filter
-  const size_t esz = p->io_dtype == SOS_F64 ? 8 : 4;
-  const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y;
-  if (xb < yb + (uintptr_t)n * esz && yb < xb + (uintptr_t)n * esz) return SOS_E_ARG;   // overlap
-  if ((xb | yb) & 15) return SOS_E_ARG;   // 16-byte vector access
+  const sos_status chk = sosf::check_filt_args(*p, x, y, n);
+  if (chk != SOS_OK) return chk;
   Ptrs q{x, y, p->d_table, static_cast<const int32_t *>(p->d_solver)};
   FiltArgs a;
   a.n = n;

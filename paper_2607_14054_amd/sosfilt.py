@@ -16,7 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsosfilt.so")
 
-SOS_OK, SOS_E_ARG, SOS_E_COEF, SOS_E_UNSTABLE, SOS_E_UNSUPPORTED, SOS_E_DEVICE, SOS_E_NOMEM = range(7)
+(SOS_OK, SOS_E_ARG, SOS_E_COEF, SOS_E_UNSTABLE, SOS_E_UNSUPPORTED, SOS_E_DEVICE, SOS_E_NOMEM,
+ SOS_E_SCRATCH) = range(8)
+SOS_STATIC_SCRATCH_BYTES = 16 << 20
 SOS_F32, SOS_F64, SOS_F16, SOS_BF16 = 0, 1, 2, 3
 SOS_AUTO, SOS_PH, SOS_CR, SOS_PH_DEFERRED, SOS_SCALAR, SOS_BLOCK = 0, 1, 2, 3, 4, 5
 SOS_FLAG_HOST_ONLY = 0x1
@@ -35,7 +37,8 @@ EXPORTED = ["sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", 
             "sos_batch_query", "sos_batch_replan", "sos_filt_batched", "sos_batch_tune", "sos_backward_workspace_size",
             "sos_filt_backward", "sos_batch_backward_workspace_size", "sos_batch_query_adjoint",
             "sos_filt_backward_batched", "sos_filt_for_backward", "sos_filt_backward_stored",
-            "sos_filt_batched_for_backward", "sos_filt_backward_batched_stored", "sos_status_string"]
+            "sos_filt_batched_for_backward", "sos_filt_backward_batched_stored", "sos_status_string",
+            "sos_filt_static"]
 
 _DTYPES = {"f32": SOS_F32, "f64": SOS_F64, "f16": SOS_F16, "bf16": SOS_BF16,
            np.float32: SOS_F32, np.float64: SOS_F64}
@@ -94,6 +97,7 @@ def lib():
         L.sos_workspace_size.argtypes = [vp, i64]
         L.sos_workspace_size.restype = ctypes.c_size_t
         L.sos_filt.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.sos_filt_static.argtypes = [vp, vp, vp, i64, vp]
         L.sos_status_string.argtypes = [ctypes.c_int]
         L.sos_status_string.restype = ctypes.c_char_p
         p64 = ctypes.POINTER(ctypes.c_int64)
@@ -118,7 +122,7 @@ def lib():
         L.sos_filt_backward_stored.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp]
         L.sos_filt_batched_for_backward.argtypes = [vp, vp, vp, vp, vp]
         L.sos_filt_backward_batched_stored.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-        for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt",
+        for f in ("sos_plan", "sos_plan_destroy", "sos_plan_query", "sos_plan_table", "sos_filt", "sos_filt_static",
                   "sos_batch_plan", "sos_batch_destroy", "sos_batch_query", "sos_batch_replan",
                   "sos_filt_batched",
                   "sos_batch_tune", "sos_filt_backward", "sos_batch_query_adjoint",
@@ -259,6 +263,24 @@ def filt(plan: Plan, x, y=None, stream=None):
     _check(lib().sos_filt(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                           n, ctypes.c_void_p(wsb.data_ptr()) if wsb is not None else None,
                           _stream_ptr(stream)), "sos_filt")
+    return y
+
+
+def filt_static(plan: Plan, x, y, stream=None):
+    """sos_filt_static: y = cascade(x) into the caller's y, with the exact
+    carry's workspace in the library's static device buffer (nothing is
+    allocated).  Raises SosError(SOS_E_SCRATCH) if the call needs more than
+    SOS_STATIC_SCRATCH_BYTES."""
+    import torch
+    want = torch.float32 if plan.io_dtype == "f32" else torch.float64
+    for t in (x, y):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.dim() == 1
+                and t.is_contiguous()):
+            raise ValueError("x and y must be contiguous 1-D device tensors of dtype %s" % want)
+    if y.shape != x.shape:
+        raise ValueError("y must have x's shape")
+    _check(lib().sos_filt_static(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                 x.numel(), _stream_ptr(stream)), "sos_filt_static")
     return y
 
 
