@@ -168,8 +168,10 @@ def forms_summary(extra, plain_gsps):
                     "saved_outputs_GSps": g["saved_outputs"]["GSps"],
                     "gx_rel_rms_max": g.get("gx_rel_rms_max"), "gsos_row_err_max": g.get("gsos_row_err_max")},
         "precision": {"workload": "256 x 2^20 float32, K=8, r U[0.9,0.999]; one batched launch per row",
-                      "rows": [{"compute": r["compute"], "solver": r["solver"], "GSps": r["GSps"],
-                                "vs_plain": r["GSps"] / plain_gsps, "rel_rms_max": r.get("rel_rms_max")}
+                      "rows": [dict({"compute": r["compute"], "solver": r["solver"], "GSps": r["GSps"],
+                                     "vs_plain": r["GSps"] / plain_gsps, "rel_rms_max": r.get("rel_rms_max"),
+                                     "fp32_floor_max": r.get("fp32_floor_max")},
+                                    **({"slices": r["slices"]} if "slices" in r else {}))
                                for r in p["rows"]]},
     }
     for f in (out["batched"], out["adjoint"]):
@@ -547,9 +549,14 @@ def bench_precision(S, W, torch, dev, args):
             x_c = xb[c * n:(c + 1) * n].cpu().numpy()
             refs[c] = (oracle.sosfilt(x_c, sos[c]), oracle.sosfilt_f32arith(x_c, sos[c]))
     out = {"channels": C, "samples": C * n, "rows": []}
-    for compute, solver, N in (("f64", "auto", 64), ("f64", "ph", 64), ("f32", "ph", 64), ("f32", "cr", 64),
-                               ("f64", "block", 64), ("f16", "block", 64), ("bf16", "block", 64)):
-        plans = [S.Plan(s_, io_dtype="f32", compute_dtype=compute, solver=solver, N=N) for s_ in sos]
+    rows = [("f64", "auto", 64, 0), ("f64", "ph", 64, 0), ("f32", "ph", 64, 0), ("f32", "cr", 64, 0),
+            ("f64", "block", 64, 0)]
+    # FP16 / BF16 products: one rounding (1 slice), then error-free slices
+    # (the default is 3 for FP16, 4 for BF16)
+    rows += [("f16", "block", 64, s_) for s_ in (1, 2, 3, 4)] + [("bf16", "block", 64, s_) for s_ in (1, 2, 3, 4)]
+    for compute, solver, N, slices in rows:
+        plans = [S.Plan(s_, io_dtype="f32", compute_dtype=compute, solver=solver, N=N, slices=slices)
+                 for s_ in sos]
         yb = torch.empty_like(xb)
         b = S.Batch(plans, [n] * C)
 
@@ -566,6 +573,8 @@ def bench_precision(S, W, torch, dev, args):
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3 / 3
         row = {"compute": compute, "solver": solver, "N": N, "GSps": C * n / sec / 1e9}
+        if solver == "block" and compute != "f64":
+            row["slices"] = plans[0].info().block_slices
         if refs:
             import oracle
             errs = [oracle.rel_rms(yb[c * n:(c + 1) * n].cpu().numpy(), refs[c][0]) for c in pick]
@@ -574,8 +583,10 @@ def bench_precision(S, W, torch, dev, args):
             row.update({"rel_rms_max": max(errs), "rel_rms_median": float(np.median(errs)),
                         "max_rel_max": max(maxs), "fp32_floor_max": max(floor)})
         out["rows"].append(row)
-        log("precision %s/%s N=%d: %.1f GS/s %s" % (compute, solver, N, row["GSps"],
-                                                   {k: v for k, v in row.items() if "rel" in k or "floor" in k}))
+        log("precision %s/%s N=%d slices=%s: %.1f GS/s %s" % (compute, solver, N, row.get("slices", "-"),
+                                                             row["GSps"],
+                                                             {k: v for k, v in row.items()
+                                                              if "rel" in k or "floor" in k}))
     return out
 
 

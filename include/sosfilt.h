@@ -78,7 +78,8 @@ typedef enum {
     SOS_BLOCK = 5        /* block filtering (Section IV, eq. block_filtering_equation):
                             the 16 x 16 Toeplitz product H x on MFMA in the
                             compute_dtype (SOS_F64, SOS_F16 or SOS_BF16; FP32
-                            accumulation for the latter two), the boundary terms, the
+                            accumulation for the latter two, with error-free operand
+                            slices, see SOS_FLAG_SLICES), the boundary terms, the
                             block-to-block recurrence and the carries in FP64;
                             K <= 32, N ignored */
 } sos_solver;
@@ -96,6 +97,17 @@ typedef enum {
 #define SOS_FLAG_ADJ_RECOMPUTE 0x10u /* adjoint: checkpoint the cascade state
                                      per group and recompute section inputs
                                      (not with SOS_FLAG_ADJ_SAVE) */
+/* SOS_BLOCK with compute_dtype SOS_F16 or SOS_BF16: slices per operand of
+ * the Toeplitz products, 1..4 (0 = the default, 3 for FP16 and 4 for BF16).
+ * 1 rounds both operands once to the product type.  S >= 2 cuts both into S
+ * integer slices of W bits (W = 10 for FP16, 8 for BF16) after a
+ * power-of-two scale per 16-sample block (Ozaki et al., 2012): the matrix
+ * cores then accumulate every order of slice products exactly in FP32, and
+ * the product's error is that of the slices cut off, about 2^(-W (S-1)) of
+ * the block's largest value.  Orders a + b < S are formed: S (S + 1) / 2
+ * slice products per section and group of 256 samples. */
+#define SOS_FLAG_SLICES(s) (((uint32_t)(s) & 7u) << 8)
+#define SOS_FLAG_SLICES_MASK 0x700u
 
 typedef struct {
     int32_t io_dtype;       /* sos_dtype of x and y (default SOS_F32) */
@@ -149,6 +161,8 @@ typedef struct {
     double transition_norm_W;   /* infinity norm of the cascade state transition over W samples */
     int32_t simds;              /* SIMDs of the plan's device (0 for a host-only plan) */
     int32_t waves_per_simd;     /* resident wavefronts per SIMD of the plan's kernel (0: host-only) */
+    int32_t block_slices;       /* SOS_BLOCK: slices per operand of the products (1 otherwise) */
+    int32_t reserved;           /* 0 */
 } sos_plan_info;
 
 /* info        host, filled in.

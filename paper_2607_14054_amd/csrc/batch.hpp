@@ -17,6 +17,7 @@ struct sos_batch_s {
   bool b0one = true, host_only = false;
   bool block = false;                     // block-filtering channels (SOS_BLOCK plans)
   int block_pt = 0;                       // their product type
+  int block_slices = 1;                   // and slices per operand
   int device = -1;
   int64_t total = 0, items = 0;
   std::vector<int64_t> n, off, tile;
@@ -51,6 +52,6 @@ namespace sosf {
 // the adjoint schedule, host side (sosfilt_backward.hip)
 sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32_t tile_groups);
 // batched block filtering (sosfilt_block.hip)
-Residency block_batched_residency(int io_dtype, int pt, int kmax);
+Residency block_batched_residency(int io_dtype, int pt, int S, int kmax);
 sos_status launch_block_batched(const sos_batch_s &b, const void *x, void *y, hipStream_t s);
 }

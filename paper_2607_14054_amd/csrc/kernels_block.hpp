@@ -20,9 +20,23 @@
 // * the boundary correction Gx xbar + Gy ybar of every output (4 FMA per
 //   sample, the paper's 4/L block FMAs);
 // * the carries between groups and sections.
-// In the low-precision forms each section's input is scaled by a power of
-// two (the inverse RMS gain of the sections before it for white input)
-// before rounding, and the product is scaled back in FP64.
+// The low-precision forms take one of two routes to the product, set by the
+// number of slices S per operand:
+// * S = 1: each section's input is scaled by a power of two (the inverse RMS
+//   gain of the sections before it for white input) and rounded to the
+//   product type, H is rounded to it, and the FP32 sum is scaled back in
+//   FP64.  Its error is the product type's rounding.
+// * S >= 2: error-free slicing of both operands (the splitting of Ozaki,
+//   Ogita, Oishi and Rump, 2012, used on matrix units with FP16 inputs by
+//   Mukunoki et al., 2020).  Each column of the tile (one block of 16
+//   samples) is scaled by the power of two that puts its largest value
+//   below 2^(W-1), W = 10 (FP16) or 8 (BF16), and cut into S integer slices
+//   of W bits, v = sum_b t_b 2^(-W b) / s_v; H is cut the same way on the
+//   host.  The integers are exact in the product type, their products are
+//   exact in FP32, and the sums of each order a + b = o stay below 2^24, so
+//   every FP32 accumulation of the matrix cores is exact.  The orders
+//   a + b < S are summed in FP64.  The only errors left are the slices cut
+//   off (2^(-W (S-1)) of the column's scale) and the products of order >= S.
 #pragma once
 
 #include "kernels_deferred.hpp"
@@ -30,17 +44,27 @@
 namespace sosf {
 
 typedef _Float16 v4h __attribute__((ext_vector_type(4)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 enum : int { PT_F64 = 0, PT_F16 = 1, PT_BF16 = 2 };
+
+constexpr int kMaxSlices = 4;
+// Bits per slice: a slice is an integer in [-2^(W-1), 2^(W-1)], exact in the
+// product type (FP16 holds integers to 2^11, BF16 to 2^8).
+template <int PT>
+__host__ __device__ constexpr int slice_bits() { return PT == PT_F16 ? 10 : 8; }
 
 // Per-section FP64 block table (kBlockStride doubles).
 enum : int {
   BT_GXT = 0,      // 4: rows 14, 15 of Gx, row-major
   BT_POW = 4,      // 16: M^(2^i), i = 0..3, row-major
-  BT_SCALE = 20,   // input scale before rounding to the product type
+  BT_SCALE = 20,   // S = 1: input scale before rounding to the product type
   BT_ISCALE = 21,  // its inverse
+  BT_HINV = 22,    // S >= 2: inverse of the power-of-two scale of H's slices
   BT_G = 32,       // 64: per lane row q and register r: Gx[m][0..1], Gy[m][0..1] (m per layout)
   BT_HT = 96,      // 32: per lane row q and register r: h[14 - m], h[15 - m] (0 past the diagonal)
   kBlockStride = 128
@@ -93,12 +117,122 @@ __device__ __forceinline__ void store4(double *p, const double (&V)[4]) {
   __builtin_nontemporal_store(v, reinterpret_cast<vd2 *>(p) + 1);
 }
 
+// Maximum over the four lanes of a tile column (lanes j, j + 16, j + 32,
+// j + 48): permlane16 / permlane32 swaps exchange the rows pairwise.
+__device__ __forceinline__ uint32_t column_max_u32(uint32_t v) {
+  auto a = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  v = a[0] > a[1] ? a[0] : a[1];
+  auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return b[0] > b[1] ? b[0] : b[1];
+}
+
+// A slice of this lane's four scaled values (integers of at most W bits, so
+// every conversion below is exact), in the product type.
+template <int PT>
+__device__ __forceinline__ v4s slice_bits_of(const double (&t)[4]) {
+  float f[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) f[r] = (float)t[r];
+  if (PT == PT_F16) {
+    // two per instruction; round-toward-zero packing is exact for these
+    typedef short v2s __attribute__((ext_vector_type(2)));
+    const v2s lo = __builtin_bit_cast(v2s, __builtin_amdgcn_cvt_pkrtz(f[0], f[1]));
+    const v2s hi = __builtin_bit_cast(v2s, __builtin_amdgcn_cvt_pkrtz(f[2], f[3]));
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3);
+  }
+  v4s o;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) o[r] = (short)(__float_as_uint(f[r]) >> 16);   // its low 16 bits are zero
+  return o;
+}
+
+// x16 product of one slice pair, or x32 product of two pairs (the K
+// dimension of a 16x16x32 product is any sum of two 16-deep products).
+template <int PT>
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f acc) {
+  if (PT == PT_F16)
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(v4h, a), __builtin_bit_cast(v4h, b), acc, 0, 0,
+                                                 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+}
+template <int PT>
+__device__ __forceinline__ v4f mfma32(v4s a0, v4s a1, v4s b0, v4s b1, v4f acc) {
+  const v8s a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+  const v8s b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+  if (PT == PT_F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(v8h, a), __builtin_bit_cast(v8h, b), acc, 0, 0,
+                                                  0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), acc, 0,
+                                                 0, 0);
+}
+
+// The product H V of one section with S >= 2 slices per operand (see the
+// top of this file).  Aop: this lane's entry of the section's first slice of
+// H in the 16x16x16 A layout (lane (q, i) holds H-slice[i][4q .. 4q+3]);
+// slice a lies 64 entries (one per lane) after slice a - 1.  V: this lane's
+// four values (rows 4q + r of column j); hinv: the inverse of H's slice
+// scale.
+template <int PT, int S>
+__device__ __forceinline__ void sliced_product(const v4s *__restrict__ Aop, const double (&V)[4], double hinv,
+                                               double (&P)[4]) {
+  v4s A[S];
+#pragma unroll
+  for (int a = 0; a < S; ++a) A[a] = Aop[64 * a];
+  constexpr int W = slice_bits<PT>();
+  // the column's largest magnitude, by the high words (sign cleared)
+  uint32_t mx = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t h = (uint32_t)((uint64_t)__double_as_longlong(V[r]) >> 32) & 0x7fffffffu;
+    mx = h > mx ? h : mx;
+  }
+  mx = column_max_u32(mx);
+  // biased exponent eb: every |v| of the column is below 2^(eb - 1022), so
+  // v 2^(W + 1021 - eb) lies in (-2^(W-1), 2^(W-1))
+  const int eb = (int)(mx >> 20);
+  const double sv = __longlong_as_double((long long)((uint64_t)(W + 2044 - eb) << 52));
+  v4s t[S];
+  {
+    double u[4], tb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r] = V[r] * sv;
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        tb[r] = __builtin_rint(u[r]);
+        if (b + 1 < S) u[r] = (u[r] - tb[r]) * (double)(1 << W);   // both steps exact
+      }
+      t[b] = slice_bits_of<PT>(tb);
+    }
+  }
+  // orders o = a + b (a: slice of H, b: slice of V), each in its own exact
+  // FP32 accumulator; pairs two at a time on 16x16x32, a leftover on x16
+  v4f acc[S];
+#pragma unroll
+  for (int o = 0; o < S; ++o) {
+    v4f c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a + 1 <= o; a += 2) c = mfma32<PT>(A[a], A[a + 1], t[o - a], t[o - a - 1], c);
+    if ((o & 1) == 0) c = mfma16<PT>(A[o], t[0], c);
+    acc[o] = c;
+  }
+  const double inv = __builtin_ldexp(hinv, eb - 1021 - W);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    double sum = (double)acc[S - 1][r];
+#pragma unroll
+    for (int o = S - 2; o >= 0; --o) sum = fma_(sum, 1.0 / (double)(1 << W), (double)acc[o][r]);
+    P[r] = sum * inv;
+  }
+}
+
 // One wavefront's tile: samples [t0, t0 + tile) of a signal of n samples,
 // after a run-in over the warm samples before t0 (samples outside [0, n)
 // read as zero and are not stored).  g_s, a_s: the sections' correction
 // rows and MFMA A operands in LDS; st: the wavefront's 2 + 2K carries (the
 // raw input's last two samples, then each section's last two outputs).
-template <typename TI, int PT>
+template <typename TI, int PT, int S>
 __device__ __forceinline__ void block_rows(const TI *__restrict__ x, TI *__restrict__ y, const double *__restrict__ bt,
                                            const double *g_s, const unsigned char *a_s, double *st, int64_t n,
                                            int64_t t0, int64_t tile, int64_t warm, int K) {
@@ -136,6 +270,8 @@ __device__ __forceinline__ void block_rows(const TI *__restrict__ x, TI *__restr
         for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[s * 64 + lane], V[s], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) P[r] = acc[r];
+      } else if (S >= 2) {
+        sliced_product<PT, S>(reinterpret_cast<const v4s *>(a_s) + (size_t)k * S * 64 + lane, V, c[BT_HINV], P);
       } else {
         const T sc = c[BT_SCALE], isc = c[BT_ISCALE];
         v4f acc = {0.f, 0.f, 0.f, 0.f};
@@ -220,16 +356,17 @@ __device__ __forceinline__ void block_rows(const TI *__restrict__ x, TI *__restr
   }
 }
 
-template <typename TI, int PT>
-__host__ __device__ constexpr int block_aop_bytes() {
-  return PT == PT_F64 ? 256 * 8 : 256 * 2;   // A-operand bytes per section
+// A-operand bytes per section: one 16 x 16 tile of H (FP64), or S slices of
+// it in the product type.
+__host__ __device__ constexpr int block_aop_bytes(int pt, int S) {
+  return pt == PT_F64 ? 256 * 8 : 256 * 2 * S;
 }
 
 // Stage the correction rows and A operands of K sections into LDS.
-template <int PT>
+template <int PT, int S>
 __device__ __forceinline__ void block_stage_tables(const double *__restrict__ bt, const void *__restrict__ aop, int K,
                                                    double *g_s, unsigned char *a_s) {
-  constexpr int AOP = block_aop_bytes<float, PT>();
+  constexpr int AOP = block_aop_bytes(PT, S);
   for (int i = threadIdx.x; i < K * 96; i += kWavesPerBlock * 64)
     g_s[i] = bt[(int64_t)(i / 96) * kBlockStride + BT_G + (i % 96)];
   for (int i = threadIdx.x; i < K * AOP / 16; i += kWavesPerBlock * 64)
@@ -237,7 +374,7 @@ __device__ __forceinline__ void block_stage_tables(const double *__restrict__ bt
 }
 
 // Single signal: wavefront w takes tile w.
-template <typename TI, int PT>
+template <typename TI, int PT, int S>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const double *__restrict__ bt,
     const void *__restrict__ aop, BlockArgs a) {
@@ -245,38 +382,38 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
   // LDS: the block's copies of the per-lane correction rows and of the MFMA
   // A operands (every wavefront reads all of them once per group), then the
   // carries of each wavefront
-  constexpr int AOP = block_aop_bytes<TI, PT>();
+  constexpr int AOP = block_aop_bytes(PT, S);
   double *g_s = reinterpret_cast<double *>(smem);   // per section: G (64), then HT (32)
   unsigned char *a_s = smem + (size_t)a.K * 96 * sizeof(double);
-  block_stage_tables<PT>(bt, aop, a.K, g_s, a_s);
+  block_stage_tables<PT, S>(bt, aop, a.K, g_s, a_s);
   __syncthreads();
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (wave >= a.ntiles) return;
   double *st = reinterpret_cast<double *>(a_s + (size_t)a.K * AOP) + w * (2 + 2 * a.K);
-  block_rows<TI, PT>(x, y, bt, g_s, a_s, st, a.n, wave * a.tile, a.tile, a.warm, a.K);
+  block_rows<TI, PT, S>(x, y, bt, g_s, a_s, st, a.n, wave * a.tile, a.tile, a.warm, a.K);
 }
 
 // Batches: one workgroup per work item, four tiles of one channel (one per
 // wavefront), so that the workgroup stages that channel's tables only.  The
 // channel's tiles cover [-shift, n), which puts every 4-sample vector of x
 // and y on a 16-byte boundary.
-template <typename TI, int PT>
+template <typename TI, int PT, int S>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_batched_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const BatchChan *__restrict__ chans,
     const int32_t *__restrict__ item_chan, int32_t kmax) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  constexpr int AOP = block_aop_bytes<TI, PT>();
+  constexpr int AOP = block_aop_bytes(PT, S);
   const BatchChan &ch = chans[item_chan[blockIdx.x]];
   double *g_s = reinterpret_cast<double *>(smem);
   unsigned char *a_s = smem + (size_t)kmax * 96 * sizeof(double);
-  block_stage_tables<PT>(static_cast<const double *>(ch.tab), ch.aop, ch.K, g_s, a_s);
+  block_stage_tables<PT, S>(static_cast<const double *>(ch.tab), ch.aop, ch.K, g_s, a_s);
   __syncthreads();
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t tile_index = ((int64_t)blockIdx.x - ch.first_item) * kWavesPerBlock + w;
   if (tile_index * ch.tile >= ch.n + ch.shift) return;
   double *st = reinterpret_cast<double *>(a_s + (size_t)kmax * AOP) + w * (2 + 2 * kmax);
-  block_rows<TI, PT>(x + ch.off, y + ch.off, static_cast<const double *>(ch.tab), g_s, a_s, st, ch.n,
+  block_rows<TI, PT, S>(x + ch.off, y + ch.off, static_cast<const double *>(ch.tab), g_s, a_s, st, ch.n,
                      tile_index * ch.tile - ch.shift, ch.tile, ch.warm, ch.K);
 }
 

@@ -70,6 +70,7 @@ struct sos_plan_s {
   // block filtering (solver SOS_BLOCK): product type, FP64 block tables and
   // the MFMA A operands of the Toeplitz products
   int block_pt = 0;
+  int block_slices = 1;            // slices per operand of FP16 / BF16 products (1: rounded once)
   std::vector<double> block_tab;
   std::vector<unsigned char> block_aop;
   void *d_block = nullptr;

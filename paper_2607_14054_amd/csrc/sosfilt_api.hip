@@ -252,7 +252,7 @@ const char *sos_status_string(sos_status s) {
 
 sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan_t *out) {
   constexpr uint32_t known = SOS_FLAG_HOST_ONLY | SOS_FLAG_CARRY_SCAN | SOS_FLAG_CARRY_RUNIN |
-                             SOS_FLAG_ADJ_SAVE | SOS_FLAG_ADJ_RECOMPUTE;
+                             SOS_FLAG_ADJ_SAVE | SOS_FLAG_ADJ_RECOMPUTE | SOS_FLAG_SLICES_MASK;
   if (opts && (opts->flags & ~known)) return SOS_E_ARG;
   if (opts && (opts->flags & SOS_FLAG_CARRY_SCAN) && (opts->flags & SOS_FLAG_CARRY_RUNIN)) return SOS_E_ARG;
   if (opts && (opts->flags & SOS_FLAG_ADJ_SAVE) && (opts->flags & SOS_FLAG_ADJ_RECOMPUTE)) return SOS_E_ARG;
@@ -283,6 +283,9 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   if (o.solver == SOS_PH_DEFERRED && !deferred_ok) return SOS_E_UNSUPPORTED;
   if (o.solver == SOS_SCALAR && K > kScalarKMax) return SOS_E_UNSUPPORTED;
   if (o.solver == SOS_BLOCK && K > kBlockKMax) return SOS_E_UNSUPPORTED;
+  const int slices = (int)((o.flags & SOS_FLAG_SLICES_MASK) >> 8);
+  if (slices > kMaxSlices) return SOS_E_ARG;
+  if (slices > 1 && !low) return SOS_E_UNSUPPORTED;   // FP64 products are not sliced
   sos_plan_s *p = new (std::nothrow) sos_plan_s;
   if (!p) return SOS_E_NOMEM;
   p->K = K;
@@ -294,6 +297,7 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   p->solver_opt = o.solver;
   p->tile_groups = o.tile_groups;
   p->flags = o.flags;
+  p->block_slices = !low ? 1 : (slices ? slices : (o.compute_dtype == SOS_F16 ? 3 : 4));
   sos_status st = build_plan_tables(*p, sos);
   if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED) {
     build_deferred_tables(*p);
@@ -382,6 +386,8 @@ sos_status sos_plan_query(sos_plan_t p, sos_plan_info *info, int32_t *solver) {
     info->transition_norm_W = p->warm_norm;
     info->simds = p->d_table ? p->simds : 0;
     info->waves_per_simd = p->d_table ? p->waves_per_simd : 0;
+    info->block_slices = p->block_slices;
+    info->reserved = 0;
   }
   if (solver)
     for (int k = 0; k < p->K; ++k) solver[k] = p->solver[k];

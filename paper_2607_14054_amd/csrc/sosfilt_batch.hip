@@ -111,7 +111,7 @@ sos_status validate(const sos_plan_t *plans, int32_t C, const int64_t *n, bool h
     if ((p->solver_opt == SOS_BLOCK) != (plans[0]->solver_opt == SOS_BLOCK)) return SOS_E_UNSUPPORTED;
     if (!host_only && p->solver_opt == SOS_BLOCK && (!p->d_block || !p->d_aop)) return SOS_E_ARG;
     if (p->N != plans[0]->N || p->io_dtype != plans[0]->io_dtype ||
-        p->compute_dtype != plans[0]->compute_dtype)
+        p->compute_dtype != plans[0]->compute_dtype || p->block_slices != plans[0]->block_slices)
       return SOS_E_UNSUPPORTED;
   }
   return SOS_OK;
@@ -156,6 +156,7 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   // block filtering: its own kernel, tiles in groups of 16 blocks
   b.block = plans[0]->solver_opt == SOS_BLOCK;
   b.block_pt = plans[0]->block_pt;
+  b.block_slices = plans[0]->block_slices;
   const int64_t G = b.block ? (int64_t)kBlockGroup : (int64_t)b.N * kL;
   for (int c = 0; c < C; ++c) b.total = std::max(b.total, b.off[c] + n[c]);
   // each channel's solver class: SOS_CR or SOS_PH when all its sections use
@@ -176,7 +177,7 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
     if (cls[c] != b.mix) b.mix = SOS_AUTO;
   Residency res;
   if (!b.host_only && b.block)
-    res = block_batched_residency(b.io_dtype, b.block_pt, b.kmax);
+    res = block_batched_residency(b.io_dtype, b.block_pt, b.block_slices, b.kmax);
   else if (!b.host_only)
     dispatch_rows<ResidencyBatched>(b.N, b.io_dtype, b.compute_dtype, b.b0one, b.mix, b.kmax, &res);
   // a channel whose first sample is off a 16-byte boundary is filtered over
@@ -378,7 +379,7 @@ sos_status sos_batch_replan(sos_batch_t b, const sos_plan_t *plans, int32_t C, c
   sos_status st = validate(plans, C, n, b->host_only);
   if (st != SOS_OK) return st;
   if (plans[0]->N != b->N || plans[0]->io_dtype != b->io_dtype || plans[0]->compute_dtype != b->compute_dtype ||
-      (plans[0]->solver_opt == SOS_BLOCK) != b->block)
+      (plans[0]->solver_opt == SOS_BLOCK) != b->block || plans[0]->block_slices != b->block_slices)
     return SOS_E_UNSUPPORTED;
   // schedule into a copy, so that an invalid request leaves the batch as it was
   sos_batch_s t;

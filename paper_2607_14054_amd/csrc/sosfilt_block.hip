@@ -93,23 +93,46 @@ void fill_rows(const double gx[2][16], const double gy[2][16], double *t) {
     }
 }
 
-template <typename TI, int PT>
-const void *block_kernel_ptr() {
-  return reinterpret_cast<const void *>(&sos_block_kernel<TI, PT>);
+// Kernel instances by I/O type, product type and slices per operand.
+template <template <typename, int, int> class KP, typename TI, int PT>
+const void *by_slices(int S) {
+  switch (S) {
+    case 2: return KP<TI, PT, 2>::get();
+    case 3: return KP<TI, PT, 3>::get();
+    case 4: return KP<TI, PT, 4>::get();
+    default: return KP<TI, PT, 1>::get();
+  }
 }
+template <template <typename, int, int> class KP>
+const void *block_instance(int io_dtype, int pt, int S) {
+  const bool f32 = io_dtype == SOS_F32;
+  switch (pt) {
+    case PT_F16: return f32 ? by_slices<KP, float, PT_F16>(S) : by_slices<KP, double, PT_F16>(S);
+    case PT_BF16: return f32 ? by_slices<KP, float, PT_BF16>(S) : by_slices<KP, double, PT_BF16>(S);
+    default: return f32 ? KP<float, PT_F64, 1>::get() : KP<double, PT_F64, 1>::get();
+  }
+}
+template <typename TI, int PT, int S>
+struct SingleKernel {
+  static const void *get() { return reinterpret_cast<const void *>(&sos_block_kernel<TI, PT, S>); }
+};
 
 const void *block_kernel(const sos_plan_s &p) {
-  const bool f32 = p.io_dtype == SOS_F32;
-  switch (p.block_pt) {
-    case PT_F16: return f32 ? block_kernel_ptr<float, PT_F16>() : block_kernel_ptr<double, PT_F16>();
-    case PT_BF16: return f32 ? block_kernel_ptr<float, PT_BF16>() : block_kernel_ptr<double, PT_BF16>();
-    default: return f32 ? block_kernel_ptr<float, PT_F64>() : block_kernel_ptr<double, PT_F64>();
-  }
+  return block_instance<SingleKernel>(p.io_dtype, p.block_pt, p.block_slices);
 }
 
 size_t block_lds(const sos_plan_s &p) {
-  const size_t aop = p.block_pt == PT_F64 ? 256 * 8 : 256 * 2;
+  const size_t aop = (size_t)block_aop_bytes(p.block_pt, p.block_slices);
   return (size_t)p.K * (96 * sizeof(double) + aop) + (size_t)kWavesPerBlock * (2 + 2 * p.K) * sizeof(double);
+}
+
+// Integer slices of u (|u| < 2^(W-1)): u = sum_b t_b 2^(-W b) + a remainder
+// below 2^(-W (S-1)) / 2; every step is exact in FP64.
+void slice(double u, int S, int W, double *t) {
+  for (int b = 0; b < S; ++b) {
+    t[b] = std::nearbyint(u);
+    u = (u - t[b]) * std::ldexp(1.0, W);
+  }
 }
 
 }  // namespace
@@ -118,8 +141,10 @@ namespace sosf {
 
 sos_status build_block_plan(sos_plan_s &p) {
   p.block_pt = p.compute_dtype == SOS_F16 ? PT_F16 : (p.compute_dtype == SOS_BF16 ? PT_BF16 : PT_F64);
+  const int S = p.block_slices;
+  const int W = p.block_pt == PT_F16 ? slice_bits<PT_F16>() : slice_bits<PT_BF16>();
   p.block_tab.assign((size_t)p.K * kBlockStride, 0.0);
-  const size_t aop_bytes = p.block_pt == PT_F64 ? 256 * sizeof(double) : 256 * sizeof(uint16_t);
+  const size_t aop_bytes = (size_t)block_aop_bytes(p.block_pt, S);
   p.block_aop.assign((size_t)p.K * aop_bytes, 0);
   const std::vector<double> gain = prefix_rms_gain(p);
   for (int k = 0; k < p.K; ++k) {
@@ -154,11 +179,30 @@ sos_status build_block_plan(sos_plan_s &p) {
         t[BT_HT + q * 8 + 2 * r] = c <= 14 ? h[14 - c] : 0.0;
         t[BT_HT + q * 8 + 2 * r + 1] = h[15 - c];
       }
+    // S >= 2: H in slices, scaled by the power of two that puts max |h|
+    // below 2^(W-1) (the same rule as the kernel's columns)
+    double hmax = 0.0;
+    for (int i = 0; i < 16; ++i) hmax = std::max(hmax, std::fabs(h[i]));
+    int eh = 0;
+    std::frexp(hmax, &eh);   // hmax < 2^eh
+    const double sh = std::ldexp(1.0, W - 1 - eh);
+    t[BT_HINV] = 1.0 / sh;
     // A operands of H (H[m][c] = h[m - c] for c <= m)
     unsigned char *ao = p.block_aop.data() + (size_t)k * aop_bytes;
     for (int l = 0; l < 64; ++l) {
       const int m = l % 16;
-      if (p.block_pt == PT_F64) {
+      if (p.block_pt != PT_F64 && S >= 2) {
+        // slice a of H[m][4 (l / 16) + i] at ((a * 64 + l) * 4 + i) halves
+        for (int i = 0; i < 4; ++i) {
+          const int c = 4 * (l / 16) + i;
+          double ts[kMaxSlices];
+          slice(c <= m ? h[m - c] * sh : 0.0, S, W, ts);
+          for (int a = 0; a < S; ++a) {
+            const uint16_t b = p.block_pt == PT_F16 ? f16_bits(ts[a]) : bf16_bits(ts[a]);
+            std::memcpy(ao + ((size_t)(a * 64 + l) * 4 + i) * 2, &b, 2);
+          }
+        }
+      } else if (p.block_pt == PT_F64) {
         for (int s = 0; s < 4; ++s) {
           const int c = 4 * s + l / 16;
           const double v = c <= m ? h[m - c] : 0.0;
@@ -229,26 +273,19 @@ sos_status launch_block(const sos_plan_s &p, const void *x, void *y, int64_t n, 
 // Batches of block-filtering channels (sosfilt_batch.hip schedules them):
 // one workgroup per item of four tiles, the channel's tables in LDS.
 namespace {
-template <typename TI, int PT>
-const void *block_batched_ptr() {
-  return reinterpret_cast<const void *>(&sos_block_batched_kernel<TI, PT>);
-}
-const void *block_batched_kernel(int io_dtype, int pt) {
-  const bool f32 = io_dtype == SOS_F32;
-  switch (pt) {
-    case PT_F16: return f32 ? block_batched_ptr<float, PT_F16>() : block_batched_ptr<double, PT_F16>();
-    case PT_BF16: return f32 ? block_batched_ptr<float, PT_BF16>() : block_batched_ptr<double, PT_BF16>();
-    default: return f32 ? block_batched_ptr<float, PT_F64>() : block_batched_ptr<double, PT_F64>();
-  }
-}
-size_t block_batched_lds(int kmax, int pt) {
-  const size_t aop = pt == PT_F64 ? 256 * 8 : 256 * 2;
+template <typename TI, int PT, int S>
+struct BatchedKernel {
+  static const void *get() { return reinterpret_cast<const void *>(&sos_block_batched_kernel<TI, PT, S>); }
+};
+size_t block_batched_lds(int kmax, int pt, int S) {
+  const size_t aop = (size_t)block_aop_bytes(pt, S);
   return (size_t)kmax * (96 * sizeof(double) + aop) + (size_t)kWavesPerBlock * (2 + 2 * kmax) * sizeof(double);
 }
 }  // namespace
 
-Residency block_batched_residency(int io_dtype, int pt, int kmax) {
-  return residency_of(block_batched_kernel(io_dtype, pt), block_batched_lds(kmax, pt), kWavesPerBlock * 64);
+Residency block_batched_residency(int io_dtype, int pt, int S, int kmax) {
+  return residency_of(block_instance<BatchedKernel>(io_dtype, pt, S), block_batched_lds(kmax, pt, S),
+                      kWavesPerBlock * 64);
 }
 
 sos_status launch_block_batched(const sos_batch_s &b, const void *x, void *y, hipStream_t s) {
@@ -256,8 +293,9 @@ sos_status launch_block_batched(const sos_batch_s &b, const void *x, void *y, hi
   void *ya = y;
   int32_t kmax = b.kmax;
   void *args[] = {&xa, &ya, &ca, &ia, &kmax};   // addresses of the kernel's five arguments
-  if (hipLaunchKernel(block_batched_kernel(b.io_dtype, b.block_pt), dim3((unsigned)b.items),
-                      dim3(kWavesPerBlock * 64), args, block_batched_lds(b.kmax, b.block_pt), s) != hipSuccess)
+  if (hipLaunchKernel(block_instance<BatchedKernel>(b.io_dtype, b.block_pt, b.block_slices), dim3((unsigned)b.items),
+                      dim3(kWavesPerBlock * 64), args, block_batched_lds(b.kmax, b.block_pt, b.block_slices),
+                      s) != hipSuccess)
     return SOS_E_DEVICE;
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }

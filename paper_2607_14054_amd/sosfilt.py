@@ -27,6 +27,10 @@ SOS_FLAG_CARRY_RUNIN = 0x4
 _CARRY = {"auto": 0, "scan": SOS_FLAG_CARRY_SCAN, "runin": SOS_FLAG_CARRY_RUNIN}
 SOS_FLAG_ADJ_SAVE = 0x8
 SOS_FLAG_ADJ_RECOMPUTE = 0x10
+
+
+def SOS_FLAG_SLICES(s: int) -> int:
+    return (int(s) & 7) << 8
 _ADJOINT = {"auto": 0, "save": SOS_FLAG_ADJ_SAVE, "recompute": SOS_FLAG_ADJ_RECOMPUTE}
 (SOS_TABLE_ROWS, SOS_TABLE_U1, SOS_TABLE_U2, SOS_TABLE_C, SOS_TABLE_PH_POWERS,
  SOS_TABLE_CR_LEVELS, SOS_TABLE_CR_TERMINAL, SOS_TABLE_CR_POWERS, SOS_TABLE_TRANSITION,
@@ -64,7 +68,8 @@ class _Info(ctypes.Structure):
                 ("io_dtype", ctypes.c_int32), ("compute_dtype", ctypes.c_int32),
                 ("b0_factored", ctypes.c_int32), ("warm_samples", ctypes.c_int64),
                 ("gain", ctypes.c_double), ("transition_norm_W", ctypes.c_double),
-                ("simds", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32)]
+                ("simds", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32),
+                ("block_slices", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _BatchOpts(ctypes.Structure):
@@ -156,6 +161,7 @@ class PlanInfo:
     solver: list
     simds: int
     waves_per_simd: int
+    block_slices: int
 
 
 class Plan:
@@ -166,13 +172,14 @@ class Plan:
     recomputed)."""
 
     def __init__(self, sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=0,
-                 tile_groups=0, host_only=False, carry="auto", adjoint="auto"):
+                 tile_groups=0, host_only=False, carry="auto", adjoint="auto", slices=0):
         s = np.ascontiguousarray(np.asarray(sos, dtype=np.float64))
         if s.ndim != 2 or s.shape[1] != 6:
             raise ValueError("sos must be [K, 6]")
         o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), 16,
                   int(tile_groups),
-                  (SOS_FLAG_HOST_ONLY if host_only else 0) | _CARRY[carry] | _ADJOINT[adjoint])
+                  (SOS_FLAG_HOST_ONLY if host_only else 0) | _CARRY[carry] | _ADJOINT[adjoint]
+                  | SOS_FLAG_SLICES(slices))
         h = ctypes.c_void_p()
         _check(lib().sos_plan(s.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), s.shape[0],
                               ctypes.byref(o), ctypes.byref(h)), "sos_plan")
@@ -205,7 +212,8 @@ class Plan:
         return PlanInfo(inf.K, inf.N, inf.L, _DTYPE_NAMES[inf.io_dtype],
                         _DTYPE_NAMES[inf.compute_dtype], bool(inf.b0_factored),
                         int(inf.warm_samples), float(inf.gain), float(inf.transition_norm_W),
-                        [names[int(v)] for v in sol], int(inf.simds), int(inf.waves_per_simd))
+                        [names[int(v)] for v in sol], int(inf.simds), int(inf.waves_per_simd),
+                        int(inf.block_slices))
 
     def table(self, which: int, section: int = 0) -> np.ndarray:
         size = ctypes.c_int32()

@@ -172,6 +172,46 @@ def test_backward_central_finite_differences_on_gpu_forward():
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("adjoint", ["save", "recompute"])
+def test_backward_finite_differences_differentiation_workload(adjoint):
+    """The differentiation workload's own cascade (channel 0: K = 8, pole
+    radius U[0.5, 0.95], its float32 input and upstream gradient), on its
+    first 2^10 samples: all 48 coefficient gradients of the adjoint, in
+    both modes, against FP64 central differences of L = sum(y * g) with y
+    from the GPU forward.  The differences themselves are good to about
+    3e-7 of a row's largest entry here: the five-point stencil's h^4 term
+    and the forward's FP64 rounding divided by h balance near h = 1e-5 of
+    the coefficient (the two-point stencil's h^2 term alone reaches ~1e-6
+    at these poles).  The adjoint's own error against the oracle adjoint is
+    checked to 1e-10 first."""
+    cfg = W.CONFIGS["grad"]
+    n = 2 ** 10
+    sos = W.make_sos(cfg.K, cfg.r_lo, cfg.r_hi, cfg.seed)
+    x = W.make_signal(cfg.n, cfg.seed, np.float32)[:n].astype(np.float64)
+    g = W.grad_seed_signal(cfg.n, cfg.seed, np.float32)[:n].astype(np.float64)
+    gx, gs = run_backward(sos, x, g, adjoint=adjoint)
+    check_f64(x, sos, g, gx, gs, "differentiation workload, " + adjoint)
+    xt = torch.from_numpy(x).to(DEV)
+
+    def loss(s):
+        y = S.filt(S.Plan(s, io_dtype="f64", compute_dtype="f64", solver="ph", N=8), xt)
+        return float(np.dot(y.cpu().numpy(), g))
+
+    def at(k, j, d):
+        s_ = sos.copy()
+        s_[k, j] += d
+        return loss(s_)
+
+    fd = np.zeros_like(sos)
+    for k in range(sos.shape[0]):
+        for j in range(6):
+            h = 1e-5 * max(abs(sos[k, j]), 1e-3)
+            fd[k, j] = (at(k, j, -2 * h) - 8 * at(k, j, -h) + 8 * at(k, j, h) - at(k, j, 2 * h)) / (12 * h)
+    err = row_err(gs, fd)
+    print("finite differences, K = 8: row err %.2e" % err)
+    assert err < 1e-6
+
+
 def test_autograd_function_gradcheck():
     from paper_2607_14054_amd.autograd import SosFilt
     sos = torch.tensor(W.make_sos(2, 0.5, 0.9, 50), dtype=torch.float64, requires_grad=True)
