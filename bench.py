@@ -315,7 +315,7 @@ def bench_stream(S, W, torch, dev, args):
     yb = torch.empty_like(xb)
     stream = torch.cuda.Stream()
     torch.cuda.synchronize()
-    reuse = S.Batch([pool[0]], [1], max_channels=64, max_samples=cap)
+    reuse = S.Batch([pool[0]], [1], max_channels=64, max_samples=cap, max_sections=16)
 
     def serve_new(lengths, chans):
         b = S.Batch([pool[c] for c in chans], lengths)

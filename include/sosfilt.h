@@ -289,10 +289,21 @@ sos_status sos_filt_static(sos_plan_t plan, const void *x, void *y, int64_t n, s
  *          channel's length, run-in and K, and the kernel's residency);
  *          flags SOS_FLAG_HOST_ONLY
  *          builds the schedule without device memory (queries only, and
- *          host-only plans are then accepted); max_channels and
- *          max_samples reserve room for later sos_batch_replan calls of up
- *          to that many channels and samples in all (0 = this set's size).
+ *          host-only plans are then accepted); max_channels, max_samples
+ *          and max_sections reserve room for later sos_batch_replan calls
+ *          of up to that many channels, samples in all, and sections per
+ *          channel (0 = this set's size).
  * out      host, receives the batch handle (unchanged on error).
+ *
+ * Everything a sos_filt_batched launch depends on is fixed here: its grid
+ * (the most work items the reserved room allows), its LDS (the reserved
+ * sections) and its kernel instance.  A batch created with any of the three
+ * reservations above runs the kernel instance that serves every channel
+ * (sections of both solvers, b0 kept in the numerator); without one, the
+ * instance of this channel set.  So a sos_filt_batched launch captured in a
+ * HIP graph replays correctly after any number of sos_batch_replan calls:
+ * the kernel reads the current channel set and item count from the batch's
+ * device descriptors.
  */
 typedef struct sos_batch_s *sos_batch_t;   /* opaque, owned by the caller */
 
@@ -300,7 +311,8 @@ typedef struct {
     int32_t tile_groups;
     uint32_t flags;
     int32_t max_channels;
-    int32_t reserved;      /* 0 */
+    int32_t max_sections;  /* room for replans: largest K of a later channel set
+                              (0 = this set's largest K) */
     int64_t max_samples;
 } sos_batch_opts;
 
@@ -315,12 +327,20 @@ sos_status sos_batch_destroy(sos_batch_t batch);
  * loop's next request) without allocating: the schedule is rebuilt on the
  * host and copied, asynchronously on `stream`, into the batch's device
  * descriptors through its pinned staging buffer.  Arguments as for
- * sos_batch_plan; the plans must share the batch's N, io_dtype and
- * compute_dtype (SOS_E_UNSUPPORTED).  SOS_E_NOMEM if the new schedule does
- * not fit the room reserved at creation; on any error the batch keeps its
- * previous channel set.  Later launches with the batch must be on `stream`
- * (or ordered after it).  The call waits only for the previous replan's
- * copy, so it never waits for a kernel.
+ * sos_batch_plan; the plans must share the batch's N, io_dtype,
+ * compute_dtype and slices, and (for a batch created without a
+ * reservation) fit its kernel instance: no unfactored b0 where the batch's
+ * channels all had it factored, and the same solver class unless the batch
+ * mixed classes (SOS_E_UNSUPPORTED).  SOS_E_NOMEM if the new schedule does
+ * not fit the room fixed at creation (channels, work items, sections,
+ * adjoint items and rows); on any error the batch keeps its previous
+ * channel set.  Later launches with the batch must be on `stream` (or
+ * ordered after it).  The call waits only for the previous replan's copy,
+ * so it never waits for a kernel.  sos_filt_batched launches captured
+ * before the replan stay valid (see sos_batch_plan); captured launches of
+ * the batched adjoint calls below do not (their grids and workspace follow
+ * the channel set): replayed after a replan they write nothing, and must
+ * be captured again.
  */
 sos_status sos_batch_replan(sos_batch_t batch, const sos_plan_t *plans, int32_t C, const int64_t *n,
                             const int64_t *offsets, sos_stream_t stream);

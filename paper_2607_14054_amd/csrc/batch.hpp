@@ -39,10 +39,22 @@ struct sos_batch_s {
   int32_t *d_adj_item = nullptr;
   int32_t *d_adj_red = nullptr;
   // every device descriptor lives in one allocation (and its pinned host
-  // staging copy, for sos_batch_replan)
+  // staging copy, for sos_batch_replan), at offsets fixed when the batch is
+  // created: a launch captured in a HIP graph stays valid after a replan.
+  // The allocation starts with a header of two int64: the forward launch's
+  // live item count and the schedule's generation.
   unsigned char *d_blob = nullptr, *h_blob = nullptr;
   size_t blob_cap = 0;
   hipEvent_t copied = nullptr;            // the last staging upload has been read
+  // fixed at creation: the room of every descriptor region, the forward
+  // launch's grid (items_cap items), its LDS (kmax_cap sections) and its
+  // kernel instance (b0 factoring, solver class)
+  int32_t C_cap = 0, kmax_cap = 0;
+  int64_t items_cap = 0, adj_items_cap = 0, rows_cap = 0;
+  bool inst_b0one = true;
+  int inst_mix = SOS_PH;
+  int64_t gen = 0;                        // schedule generation (header[1])
+  const int64_t *d_hdr = nullptr;         // the device header
 };
 
 // the descriptor pointers lie inside the device buffer (sosfilt_batch.hip)

@@ -481,16 +481,19 @@ struct BatchChan {
   int32_t mix;              // SOS_CR / SOS_PH when every section uses it, else SOS_AUTO
 };
 
+// hdr: the batch's device header, hdr[0] the live item count (the grid is
+// sized for the batch's room, so that one launch, captured once, serves
+// every channel set the batch is replanned to).
 template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_batched_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const BatchChan *__restrict__ chans,
-    const int32_t *__restrict__ item_chan, int64_t items, int32_t kmax) {
+    const int32_t *__restrict__ item_chan, const int64_t *__restrict__ hdr, int32_t kmax) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   TI *stage = reinterpret_cast<TI *>(smem);
   T *state = reinterpret_cast<T *>(smem + stage_bytes<N, TI>());
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + w;
-  if (item >= items) return;   // uniform per wave
+  if (item >= hdr[0]) return;   // uniform per wave
   const BatchChan &ch = chans[item_chan[item]];
   const int64_t quad = item - ch.first_item;
   // the tiles cover [-shift, n), so that with x and y 16-byte aligned every

@@ -514,11 +514,18 @@ __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
   return v;
 }
 
+// The batched adjoint's launches follow the channel set they were enqueued
+// for (grids, workspace, gsos rows).  hdr[1] is the batch's current
+// schedule generation and gen the one at the launch: a launch replayed
+// from a graph captured before a replan finds them different and writes
+// nothing.
 template <int N, typename TI, bool B0ONE, bool RC, bool STORE_Y>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_save_batched_kernel(
     const TI *__restrict__ x, double *__restrict__ ws, TI *__restrict__ y, const AdjChan *__restrict__ chans,
-    const int32_t *__restrict__ item_chan, int64_t items, int32_t kmax) {
+    const int32_t *__restrict__ item_chan, int64_t items, int32_t kmax, const int64_t *__restrict__ hdr,
+    int64_t gen) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  if (hdr[1] != gen) return;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (item >= items) return;
@@ -536,8 +543,9 @@ template <int N, typename TI, bool B0ONE, bool RC>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_adjoint_batched_kernel(
     const TI *__restrict__ gy, TI *__restrict__ gx, const TI *__restrict__ x, double *__restrict__ ws,
     const AdjChan *__restrict__ chans, const int32_t *__restrict__ item_chan, int64_t items,
-    int32_t kmax) {
+    int32_t kmax, const int64_t *__restrict__ hdr, int64_t gen) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  if (hdr[1] != gen) return;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (item >= items) return;
@@ -603,7 +611,8 @@ __global__ __launch_bounds__(kReduceThreads) void sos_adjoint_reduce_kernel(cons
 // red_chan[b]
 __global__ __launch_bounds__(256) void sos_adjoint_reduce_batched_kernel(
     double *__restrict__ ws, const AdjChan *__restrict__ chans, const int32_t *__restrict__ red_chan,
-    double *__restrict__ gsos) {
+    double *__restrict__ gsos, const int64_t *__restrict__ hdr, int64_t gen) {
+  if (hdr[1] != gen) return;
   const AdjChan &c = chans[red_chan[blockIdx.x]];
   const int k = (int)blockIdx.x - c.gsos_row;
   adjoint_reduce<256>(ws + c.partial_off, c.ntiles, c.K, k, c.bwd, gsos + 6 * (int64_t)blockIdx.x);

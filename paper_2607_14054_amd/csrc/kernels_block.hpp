@@ -398,12 +398,14 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_kernel(
 // wavefront), so that the workgroup stages that channel's tables only.  The
 // channel's tiles cover [-shift, n), which puts every 4-sample vector of x
 // and y on a 16-byte boundary.
+// hdr[0]: the live item count (the grid is sized for the batch's room).
 template <typename TI, int PT, int S>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_block_batched_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const BatchChan *__restrict__ chans,
-    const int32_t *__restrict__ item_chan, int32_t kmax) {
+    const int32_t *__restrict__ item_chan, const int64_t *__restrict__ hdr, int32_t kmax) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   constexpr int AOP = block_aop_bytes(PT, S);
+  if ((int64_t)blockIdx.x >= hdr[0]) return;   // uniform per workgroup
   const BatchChan &ch = chans[item_chan[blockIdx.x]];
   double *g_s = reinterpret_cast<double *>(smem);
   unsigned char *a_s = smem + (size_t)kmax * 96 * sizeof(double);

@@ -246,17 +246,19 @@ void launch_batched(int steps, const sos_batch_s &b, const void *x, void *y, con
     if (y)
       hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, B0ONE, RC, true>), dim3(blocks),
                          dim3(kWavesPerBlock * 64), lds_f, s, static_cast<const TI *>(x), w, static_cast<TI *>(y),
-                         b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+                         b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax, b.d_hdr, b.gen);
     else
       hipLaunchKernelGGL((sos_rows_save_batched_kernel<N, TI, B0ONE, RC, false>), dim3(blocks),
                          dim3(kWavesPerBlock * 64), lds_f, s, static_cast<const TI *>(x), w,
-                         static_cast<TI *>(nullptr), b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+                         static_cast<TI *>(nullptr), b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax,
+                         b.d_hdr, b.gen);
   }
   if (steps & STEP_ADJOINT) {
     const unsigned lds_a = (unsigned)adj_lds_adjoint(b.io_dtype, b.kmax, RC, b.adj_stash);
     hipLaunchKernelGGL((sos_rows_adjoint_batched_kernel<N, TI, B0ONE, RC>), dim3(blocks),
                        dim3(kWavesPerBlock * 64), lds_a, s, static_cast<const TI *>(gy), static_cast<TI *>(gx),
-                       static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax);
+                       static_cast<const TI *>(x), w, b.d_adj, b.d_adj_item, b.adj_items, (int32_t)b.kmax,
+                       b.d_hdr, b.gen);
   }
 }
 
@@ -280,7 +282,7 @@ sos_status launch_adjoint_batched(int steps, const sos_batch_s &b, const void *x
   }
   if (steps & STEP_ADJOINT)
     hipLaunchKernelGGL(sos_adjoint_reduce_batched_kernel, dim3((unsigned)b.adj_rows), dim3(256), 0, s, w, b.d_adj,
-                       b.d_adj_red, gsos);
+                       b.d_adj_red, gsos, b.d_hdr, b.gen);
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }
 

@@ -65,14 +65,16 @@ int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t
   return best_tg;
 }
 
+// The launch depends only on what the batch fixed at creation (grid, LDS,
+// instance); the live item count is read from the device header.
 template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
 struct LaunchBatched {
   static sos_status run(const sos_batch_s &b, const void *x, void *y, hipStream_t s) {
-    const int64_t blocks = (b.items + kWavesPerBlock - 1) / kWavesPerBlock;
-    const unsigned lds = (unsigned)lds_bytes<N, TI, T>(b.kmax);
+    const int64_t blocks = (b.items_cap + kWavesPerBlock - 1) / kWavesPerBlock;
+    const unsigned lds = (unsigned)lds_bytes<N, TI, T>(b.kmax_cap);
     hipLaunchKernelGGL((sos_rows_batched_kernel<N, TI, T, B0ONE, SOLVER>), dim3((unsigned)blocks),
                        dim3(kWavesPerBlock * 64), lds, s, static_cast<const TI *>(x),
-                       static_cast<TI *>(y), b.d_chans, b.d_item_chan, b.items, (int32_t)b.kmax);
+                       static_cast<TI *>(y), b.d_chans, b.d_item_chan, b.d_hdr, (int32_t)b.kmax_cap);
     return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
   }
 };
@@ -244,17 +246,20 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   return SOS_OK;
 }
 
-// The device descriptors of a schedule, packed into one blob: forward
-// channels, forward items, adjoint channels, adjoint items, gsos rows.
+// The device descriptors of a schedule, packed into one blob: the header
+// (live item count, generation), forward channels, forward items, adjoint
+// channels, adjoint items, gsos rows.  The regions are sized by the batch's
+// room, fixed at creation.
 struct BlobLayout {
-  size_t chans, items, adj, adj_items, red, bytes;
+  size_t hdr, chans, items, adj, adj_items, red, bytes;
 };
 
 size_t up16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 BlobLayout blob_layout(size_t C, size_t items, size_t adj_items, size_t rows) {
   BlobLayout l;
-  l.chans = 0;
+  l.hdr = 0;
+  l.chans = 16;
   l.items = up16(l.chans + C * sizeof(BatchChan));
   l.adj = up16(l.items + items * sizeof(int32_t));
   l.adj_items = up16(l.adj + C * sizeof(AdjChan));
@@ -263,11 +268,14 @@ BlobLayout blob_layout(size_t C, size_t items, size_t adj_items, size_t rows) {
   return l;
 }
 
+// The layout of the batch's room.
 BlobLayout blob_layout(const sos_batch_s &b) {
-  return blob_layout(b.C, b.item_chan.size(), b.adj ? b.adj_item_chan.size() : 0, b.adj ? b.adj_red.size() : 0);
+  return blob_layout((size_t)b.C_cap, (size_t)b.items_cap, (size_t)b.adj_items_cap, (size_t)b.rows_cap);
 }
 
 void pack(const sos_batch_s &b, const BlobLayout &l, unsigned char *dst) {
+  const int64_t hdr[2] = {b.items, b.gen};
+  std::memcpy(dst + l.hdr, hdr, sizeof(hdr));
   std::memcpy(dst + l.chans, b.chans.data(), b.chans.size() * sizeof(BatchChan));
   std::memcpy(dst + l.items, b.item_chan.data(), b.item_chan.size() * sizeof(int32_t));
   if (b.adj) {
@@ -279,6 +287,7 @@ void pack(const sos_batch_s &b, const BlobLayout &l, unsigned char *dst) {
 
 void point(sos_batch_s &b, const BlobLayout &l) {
   if (!b.d_blob) {
+    b.d_hdr = nullptr;
     b.d_chans = nullptr;
     b.d_item_chan = nullptr;
     b.d_adj = nullptr;
@@ -286,6 +295,7 @@ void point(sos_batch_s &b, const BlobLayout &l) {
     b.d_adj_red = nullptr;
     return;
   }
+  b.d_hdr = reinterpret_cast<const int64_t *>(b.d_blob + l.hdr);
   b.d_chans = reinterpret_cast<BatchChan *>(b.d_blob + l.chans);
   b.d_item_chan = reinterpret_cast<int32_t *>(b.d_blob + l.items);
   b.d_adj = reinterpret_cast<AdjChan *>(b.d_blob + l.adj);
@@ -293,13 +303,32 @@ void point(sos_batch_s &b, const BlobLayout &l) {
   b.d_adj_red = reinterpret_cast<int32_t *>(b.d_blob + l.red);
 }
 
-// Capacity for channel sets of up to C channels and `samples` samples in
-// all: tiles of at least one group give at most total / (4 G) + 2 C items.
-size_t capacity_bytes(const sos_batch_s &b, int64_t C, int64_t samples) {
+// Room for channel sets of up to C channels and `samples` samples in all:
+// tiles of at least one group give at most samples / (4 G) + 2 C work items
+// (a channel's span has at most n / G + 2 groups, in quads of four tiles),
+// and likewise for the adjoint's items.
+void reserve_room(sos_batch_s &b, int64_t C, int64_t samples, int kmax) {
   const int64_t G = b.block ? std::min<int64_t>((int64_t)b.N * kL, kBlockGroup) : (int64_t)b.N * kL;
   const int64_t Gb = (int64_t)kBwdN * kL;
-  const int64_t items = samples / (4 * G) + 2 * C + 1, adj_items = (samples + 3 * C) / (4 * Gb) + 2 * C + 1;
-  return blob_layout((size_t)C, (size_t)items, (size_t)adj_items, (size_t)C * SOS_MAX_SECTIONS).bytes;
+  b.C_cap = (int32_t)std::max<int64_t>(C, b.C);
+  b.items_cap = std::max<int64_t>(samples / (4 * G) + 2 * C + 1, b.items);
+  b.adj_items_cap = std::max<int64_t>((samples + 3 * C) / (4 * Gb) + 2 * C + 1, b.adj ? (int64_t)b.adj_item_chan.size() : 0);
+  b.kmax_cap = std::max(kmax, b.kmax);
+  b.rows_cap = std::max<int64_t>(C * (int64_t)b.kmax_cap, b.adj ? (int64_t)b.adj_red.size() : 0);
+}
+
+// The schedule t fits the room of batch b, and b's forward kernel instance
+// serves every channel of t.
+sos_status fits(const sos_batch_s &b, const sos_batch_s &t) {
+  // an instance with b0 factored out cannot run a channel that keeps b0;
+  // one specialised on a solver class runs only that class
+  if (b.inst_b0one && !t.b0one) return SOS_E_UNSUPPORTED;
+  if (b.inst_mix != SOS_AUTO && t.mix != b.inst_mix) return SOS_E_UNSUPPORTED;
+  if (t.C > b.C_cap || t.items > b.items_cap || t.kmax > b.kmax_cap) return SOS_E_NOMEM;
+  if (t.adj != b.adj) return SOS_E_UNSUPPORTED;
+  if (t.adj && ((int64_t)t.adj_item_chan.size() > b.adj_items_cap || (int64_t)t.adj_red.size() > b.rows_cap))
+    return SOS_E_NOMEM;
+  return SOS_OK;
 }
 
 }  // namespace
@@ -312,7 +341,7 @@ bool batch_descriptors_valid(const sos_batch_s &b) {
     const unsigned char *q = static_cast<const unsigned char *>(p);
     return q >= b.d_blob && q < b.d_blob + b.blob_cap;
   };
-  return inside(b.d_chans) && inside(b.d_item_chan) && inside(b.d_adj) && inside(b.d_adj_item) &&
+  return inside(b.d_hdr) && inside(b.d_chans) && inside(b.d_item_chan) && inside(b.d_adj) && inside(b.d_adj_item) &&
          inside(b.d_adj_red);
 }
 
@@ -336,10 +365,30 @@ sos_status sos_batch_plan(const sos_plan_t *plans, int32_t C, const int64_t *n,
     delete b;
     return st;
   }
+  // the room and the forward launch, fixed from here on
+  const bool reserve = o.max_channels > 0 || o.max_samples > 0 || o.max_sections > 0;
+  if (o.max_sections < 0 || o.max_sections > SOS_MAX_SECTIONS) {
+    delete b;
+    return SOS_E_ARG;
+  }
+  if (reserve) {
+    reserve_room(*b, std::max<int64_t>(o.max_channels, C), std::max<int64_t>(o.max_samples, b->total),
+                 o.max_sections);
+    // the kernel instance that serves every channel a replan may bring
+    b->inst_b0one = false;
+    b->inst_mix = SOS_AUTO;
+  } else {
+    b->C_cap = C;
+    b->items_cap = b->items;
+    b->adj_items_cap = b->adj ? (int64_t)b->adj_item_chan.size() : 0;
+    b->kmax_cap = b->kmax;
+    b->rows_cap = b->adj ? (int64_t)b->adj_red.size() : 0;
+    b->inst_b0one = b->b0one;
+    b->inst_mix = b->mix;
+  }
   if (!host_only) {
     const BlobLayout l = blob_layout(*b);
-    b->blob_cap = std::max(l.bytes, capacity_bytes(*b, std::max<int64_t>(o.max_channels, C),
-                                                    std::max<int64_t>(o.max_samples, b->total)));
+    b->blob_cap = l.bytes;
     if (hipGetDevice(&b->device) != hipSuccess) {
       delete b;
       return SOS_E_DEVICE;
@@ -387,13 +436,38 @@ sos_status sos_batch_replan(sos_batch_t b, const sos_plan_t *plans, int32_t C, c
   t.tile_groups = b->tile_groups;
   st = schedule(t, plans, C, n, offsets, b->tile_groups);
   if (st != SOS_OK) return st;
-  // t keeps the device resources of b (the descriptor pointers of t are
-  // then derived from b's buffer below; a host-only batch has none)
+  // a device batch keeps its room and its launch; a host-only batch is only
+  // a schedule, and takes the new set's
+  if (!b->host_only) {
+    st = fits(*b, t);
+    if (st != SOS_OK) return st;
+  }
+  // t keeps the device resources of b, its room and its launch (the
+  // descriptor pointers of t are then derived from b's buffer below; a
+  // host-only batch has none)
   t.device = b->device;
   t.d_blob = b->d_blob;
   t.h_blob = b->h_blob;
   t.blob_cap = b->blob_cap;
   t.copied = b->copied;
+  if (b->host_only) {
+    t.C_cap = t.C;
+    t.kmax_cap = t.kmax;
+    t.items_cap = t.items;
+    t.adj_items_cap = 0;
+    t.rows_cap = 0;
+    t.inst_b0one = t.b0one;
+    t.inst_mix = t.mix;
+  } else {
+    t.C_cap = b->C_cap;
+    t.kmax_cap = b->kmax_cap;
+    t.items_cap = b->items_cap;
+    t.adj_items_cap = b->adj_items_cap;
+    t.rows_cap = b->rows_cap;
+    t.inst_b0one = b->inst_b0one;
+    t.inst_mix = b->inst_mix;
+  }
+  t.gen = b->gen + 1;
   if (!b->host_only) {
     const BlobLayout l = blob_layout(t);
     if (l.bytes > b->blob_cap) return SOS_E_NOMEM;
@@ -435,7 +509,7 @@ sos_status sos_filt_batched(sos_batch_t b, const void *x, void *y, void *workspa
   (void)workspace;
   if (!b) return SOS_E_ARG;
   if (b->host_only || !batch_descriptors_valid(*b)) return SOS_E_ARG;
-  if (b->items == 0) return SOS_OK;
+  if (b->items_cap == 0) return SOS_OK;
   if (!x || !y) return SOS_E_ARG;
   const size_t esz = b->io_dtype == SOS_F64 ? 8 : 4;
   const uintptr_t xb = (uintptr_t)x, yb = (uintptr_t)y, bytes = (uintptr_t)b->total * esz;
@@ -443,7 +517,8 @@ sos_status sos_filt_batched(sos_batch_t b, const void *x, void *y, void *workspa
   if ((xb | yb) & 15) return SOS_E_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (b->block) return launch_block_batched(*b, x, y, s);
-  return dispatch_rows<LaunchBatched>(b->N, b->io_dtype, b->compute_dtype, b->b0one, b->mix, *b, x, y, s);
+  return dispatch_rows<LaunchBatched>(b->N, b->io_dtype, b->compute_dtype, b->inst_b0one, b->inst_mix, *b, x, y,
+                                      s);
 }
 
 sos_status sos_batch_tune(const double *const *sos, const int32_t *K, int32_t C, const int64_t *n,

@@ -289,13 +289,13 @@ Residency block_batched_residency(int io_dtype, int pt, int S, int kmax) {
 }
 
 sos_status launch_block_batched(const sos_batch_s &b, const void *x, void *y, hipStream_t s) {
-  const void *xa = x, *ca = b.d_chans, *ia = b.d_item_chan;
+  const void *xa = x, *ca = b.d_chans, *ia = b.d_item_chan, *ha = b.d_hdr;
   void *ya = y;
-  int32_t kmax = b.kmax;
-  void *args[] = {&xa, &ya, &ca, &ia, &kmax};   // addresses of the kernel's five arguments
-  if (hipLaunchKernel(block_instance<BatchedKernel>(b.io_dtype, b.block_pt, b.block_slices), dim3((unsigned)b.items),
-                      dim3(kWavesPerBlock * 64), args, block_batched_lds(b.kmax, b.block_pt, b.block_slices),
-                      s) != hipSuccess)
+  int32_t kmax = b.kmax_cap;
+  void *args[] = {&xa, &ya, &ca, &ia, &ha, &kmax};   // addresses of the kernel's six arguments
+  if (hipLaunchKernel(block_instance<BatchedKernel>(b.io_dtype, b.block_pt, b.block_slices),
+                      dim3((unsigned)b.items_cap), dim3(kWavesPerBlock * 64), args,
+                      block_batched_lds(b.kmax_cap, b.block_pt, b.block_slices), s) != hipSuccess)
     return SOS_E_DEVICE;
   return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
 }

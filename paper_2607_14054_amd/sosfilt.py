@@ -74,7 +74,7 @@ class _Info(ctypes.Structure):
 
 class _BatchOpts(ctypes.Structure):
     _fields_ = [("tile_groups", ctypes.c_int32), ("flags", ctypes.c_uint32),
-                ("max_channels", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("max_channels", ctypes.c_int32), ("max_sections", ctypes.c_int32),
                 ("max_samples", ctypes.c_int64)]
 
 
@@ -301,12 +301,12 @@ class Batch:
     plans[c], at offsets[c] of the concatenated buffers (None: dense)."""
 
     def __init__(self, plans, lengths, offsets=None, tile_groups=0, host_only=False,
-                 max_channels=0, max_samples=0):
+                 max_channels=0, max_samples=0, max_sections=0):
         plans, n, off = self._args(plans, lengths, offsets)
         C = len(plans)
         hs = (ctypes.c_void_p * C)(*[p.handle.value for p in plans])
-        o = _BatchOpts(int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0, int(max_channels), 0,
-                       int(max_samples))
+        o = _BatchOpts(int(tile_groups), SOS_FLAG_HOST_ONLY if host_only else 0, int(max_channels),
+                       int(max_sections), int(max_samples))
         h = ctypes.c_void_p()
         _check(lib().sos_batch_plan(hs, C, _i64p(n), _i64p(off) if off is not None else None,
                                     ctypes.byref(o), ctypes.byref(h)), "sos_batch_plan")

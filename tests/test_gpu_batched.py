@@ -225,7 +225,7 @@ def test_replan_serves_requests_without_reallocating():
     pool = [S.Plan(W.make_sos(int(rng.integers(1, 17)), 0.5, 0.95, 800 + i), io_dtype="f32",
                    compute_dtype="f64", N=16) for i in range(16)]
     first = [pool[0], pool[1]]
-    b = S.Batch(first, [1000, 2000], max_channels=64, max_samples=2 ** 20)
+    b = S.Batch(first, [1000, 2000], max_channels=64, max_samples=2 ** 20, max_sections=16)
     stream = torch.cuda.Stream()
     xb = torch.from_numpy(W.make_signal(2 ** 20, 701, np.float32)).to(DEV)
     yb = torch.zeros_like(xb)
@@ -251,3 +251,123 @@ def test_replan_serves_requests_without_reallocating():
     assert e.value.code == S.SOS_E_NOMEM
     q = b.query()
     assert q["total"] == prev_total and len(q["offsets"]) == prev_C
+
+
+def _pool_for_graphs():
+    """Plans of both solvers, factored and unfactored b0, K 1..16."""
+    rng = np.random.default_rng(710)
+    pool = []
+    for i in range(12):
+        sos = W.make_sos(int(rng.integers(1, 17)), 0.5, 0.95, 810 + i)
+        if i % 4 == 1:
+            sos[0, 0:3] = [0.0, 0.6, -0.2]          # b0 = 0: b0 stays in the numerator
+        pool.append(S.Plan(sos, io_dtype="f32", compute_dtype="f64", N=16,
+                           solver="cr" if i % 3 == 2 else "ph"))
+    return pool, rng
+
+
+def test_graph_captured_before_replan_serves_later_sets():
+    """A sos_filt_batched launch captured in a HIP graph once, then replayed
+    after each of several replans (channel counts, lengths, sections,
+    solver classes and b0 factoring all changing): every replay equals an
+    eager launch bit for bit and the oracle within 1e-6."""
+    pool, rng = _pool_for_graphs()
+    b = S.Batch([pool[0]], [5000], max_channels=32, max_samples=2 ** 19, max_sections=16)
+    s = torch.cuda.Stream()
+    xb = torch.from_numpy(W.make_signal(2 ** 19, 711, np.float32)).to(DEV)
+    yb = torch.zeros_like(xb)
+    S.filt_batched(b, xb, yb)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        S.filt_batched(b, xb, yb, stream=torch.cuda.current_stream())
+    for req in range(4):
+        C = int(rng.integers(1, 33))
+        lengths = np.floor(2.0 ** rng.uniform(4, 14, size=C)).astype(np.int64)
+        chans = rng.integers(0, len(pool), size=C)
+        with torch.cuda.stream(s):
+            b.replan([pool[c] for c in chans], lengths, stream=s)
+            yb.fill_(-3.0)
+            g.replay()
+            eager = torch.full_like(yb, -3.0)
+            S.filt_batched(b, xb, eager, stream=s)
+        s.synchronize()
+        assert torch.equal(yb, eager), req
+        x, y = xb.cpu().numpy(), yb.cpu().numpy()
+        for i, c in enumerate(chans):
+            o, n = int(b.offsets[i]), int(lengths[i])
+            ref = oracle.sosfilt(x[o:o + n], pool[c]._sos)
+            assert oracle.rel_rms(y[o:o + n], ref) < 1e-6, (req, i)
+
+
+def test_replan_limits_of_the_room_and_instance():
+    """A replan beyond the reserved sections is refused (SOS_E_NOMEM); a
+    batch created without a reservation runs its own set's kernel instance
+    and refuses a set that needs another (an unfactored b0, another solver
+    class: SOS_E_UNSUPPORTED)."""
+    pool, _ = _pool_for_graphs()
+    ph = [p for p in pool if p.info().b0_factored and "cr" not in p.info().solver]
+    b = S.Batch([ph[0]], [1000], max_channels=4, max_samples=10 ** 5, max_sections=ph[0].K)
+    big = [p for p in pool if p.K > ph[0].K][0]
+    with pytest.raises(S.SosError) as e:
+        b.replan([big], [100])
+    assert e.value.code == S.SOS_E_NOMEM
+    plain = S.Batch([ph[0], ph[1]], [1000, 2000])
+    unfactored = [p for p in pool if not p.info().b0_factored][0]
+    with pytest.raises(S.SosError) as e:
+        plain.replan([unfactored], [500])
+    assert e.value.code == S.SOS_E_UNSUPPORTED
+    cr = [p for p in pool if p.info().b0_factored and p.info().solver[0] == "cr"
+          and all(v == "cr" for v in p.info().solver)]
+    if cr:
+        with pytest.raises(S.SosError) as e:
+            plain.replan([cr[0]], [500])
+        assert e.value.code == S.SOS_E_UNSUPPORTED
+    # the same instance, within the room of the set it was created for
+    plain.replan([ph[1]], [2000])
+    x = W.make_signal(2000, 712, np.float32)
+    y = S.filt_batched(plain, torch.from_numpy(x).to(DEV))
+    torch.cuda.synchronize()
+    assert oracle.rel_rms(y.cpu().numpy()[:2000], oracle.sosfilt(x, ph[1]._sos)) < 1e-6
+
+
+def test_adjoint_graph_replayed_after_replan_writes_nothing():
+    """A captured batched adjoint follows the channel set it was captured
+    for: replayed after a replan, its kernels find a newer schedule
+    generation and write nothing (gx and gsos keep their contents)."""
+    import ctypes
+    pool, _ = _pool_for_graphs()
+    b = S.Batch([pool[0], pool[3]], [3000, 7000], max_channels=8, max_samples=2 ** 16, max_sections=16)
+    L = S.lib()
+    ws_bytes = b.backward_workspace_size()
+    rows = ctypes.c_int64()
+    L.sos_batch_query_adjoint(b.handle, ctypes.byref(rows), None)
+    x = torch.from_numpy(W.make_signal(2 ** 16, 713, np.float32)).to(DEV)
+    gy = torch.from_numpy(W.grad_seed_signal(2 ** 16, 713, np.float32)).to(DEV)
+    gx = torch.zeros_like(x)
+    gsos = torch.zeros((64, 6), dtype=torch.float64, device=DEV)
+    ws = torch.zeros(max(ws_bytes, 16) + (1 << 20), dtype=torch.uint8, device=DEV)
+    s = torch.cuda.Stream()
+    vp = ctypes.c_void_p
+
+    def call(stream):
+        st = L.sos_filt_backward_batched(b.handle, vp(x.data_ptr()), vp(gy.data_ptr()), vp(gx.data_ptr()),
+                                         vp(gsos.data_ptr()), vp(ws.data_ptr()), vp(stream.cuda_stream))
+        assert st == S.SOS_OK
+    call(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        call(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        gx.fill_(0.0)
+        g.replay()
+    s.synchronize()
+    assert float(gx.abs().max()) > 0   # the replay before any replan works
+    with torch.cuda.stream(s):
+        b.replan([pool[1]], [4000], stream=s)
+        gx.fill_(7.0)
+        gsos.fill_(7.0)
+        g.replay()
+    s.synchronize()
+    assert bool((gx == 7.0).all()) and bool((gsos == 7.0).all())
