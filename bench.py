@@ -101,13 +101,15 @@ def bench_batch(S, W, torch, dev, args):
     yb = torch.empty_like(xb)
     log("batch: %d channels, %d samples, generated in %.1f s" % (cfg.channels, total, time.time() - t))
     t = time.time()
-    best, rows = S.batch_tune(sos, lengths, xb, yb, Ns=(16, 32, 64), tiles=(0, 8, 16, 32), reps=3)
-    log("batch autotune (%.1f s): best N=%d tile_groups=%d %.3f ms" %
-        (time.time() - t, best["N"], best["tile_groups"], best["seconds"] * 1e3))
+    best, rows = S.batch_tune(sos, lengths, xb, yb, Ns=(16, 32, 64), Ls=(16, 32, 64), tiles=(0, 8, 16, 32),
+                              reps=3)
+    log("batch autotune (%.1f s): best N=%d L=%d tile_groups=%d %.3f ms" %
+        (time.time() - t, best["N"], best["L"], best["tile_groups"], best["seconds"] * 1e3))
     for r in rows:
-        log("  tune N=%2d tile_groups=%2d: %.3f ms  %.1f GS/s" %
-            (r["N"], r["tile_groups"], r["seconds"] * 1e3, total / r["seconds"] / 1e9))
-    plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver="ph", N=best["N"]) for s_ in sos]
+        log("  tune N=%2d L=%2d tile_groups=%2d: %.3f ms  %.1f GS/s" %
+            (r["N"], r["L"], r["tile_groups"], r["seconds"] * 1e3, total / r["seconds"] / 1e9))
+    plans = [S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver="ph", N=best["N"], L=best["L"])
+             for s_ in sos]
     b = S.Batch(plans, lengths, tile_groups=best["tile_groups"])
     stream = torch.cuda.Stream()
     S.filt_batched(b, xb, yb)
@@ -130,7 +132,7 @@ def bench_batch(S, W, torch, dev, args):
     sec = e0.elapsed_time(e1) / 1e3 / steps
     gsps = total / sec / 1e9
     log("batch graph replay: %.3f ms  %.1f GS/s  %.0f GB/s" % (sec * 1e3, gsps, 8.0 * total / sec / 1e9))
-    out = {"channels": cfg.channels, "samples": total, "mean_K": float(Ks.mean()), "N": best["N"],
+    out = {"channels": cfg.channels, "samples": total, "mean_K": float(Ks.mean()), "N": best["N"], "L": best["L"],
            "tile_groups": best["tile_groups"], "ms": sec * 1e3, "GSps": gsps,
            "frac_hbm": 8.0 * total / sec / 1e9 / HBM_PEAK_GBS, "tune": rows}
     if not args.no_cpu:
@@ -159,7 +161,7 @@ def forms_summary(extra, plain_gsps):
     out = {
         "batched": {"workload": "4096 channels, lengths log-uniform in [2^10, 2^22] float32, K ~ U{1..16}, "
                                 "r U[0.5,0.95]; one graph-replayed launch, autotuned",
-                    "GSps": b["GSps"], "vs_plain": b["GSps"] / plain_gsps, "N": b["N"],
+                    "GSps": b["GSps"], "vs_plain": b["GSps"] / plain_gsps, "N": b["N"], "L": b.get("L"),
                     "rel_rms_max": b.get("rel_rms_max_sampled")},
         "adjoint": {"workload": "64 x 2^18 float32, K=8, r U[0.5,0.95]; training step: batched forward that "
                                 "fills the adjoint's workspace, then the batched adjoint from it",

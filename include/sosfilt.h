@@ -8,9 +8,10 @@
  *   y_k[n] = b0 x_k[n] + b1 x_k[n-1] + b2 x_k[n-2] - a1 y_k[n-1] - a2 y_k[n-2],
  *   x_1 = x,  x_k = y_{k-1},  y = y_K,  zero initial state.
  *
- * Each group of N*L samples (L = 16) is taken in the stride-N layout of
- * Section V: lane l of a 16-lane DPP row holds x[m + l N] for block m, and a
- * 64-wide wavefront carries four such groups from four different tiles.
+ * Each group of N*L samples is taken in the stride-N layout of Section V:
+ * lane l of a group of L lanes holds x[m + l N] for block m.  With L = 16 (a
+ * DPP row, the default) a 64-wide wavefront carries four such groups from
+ * four different tiles; with L = 32 two, with L = 64 one.
  * This turns each group into the block-tridiagonal system of eq.
  * multi_block_A.  That
  * system is solved per section by the PH factorisation (Section VI-B) or by
@@ -115,7 +116,9 @@ typedef struct {
                                and SOS_BF16 only with SOS_BLOCK */
     int32_t solver;         /* sos_solver (default SOS_AUTO) */
     int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32) */
-    int32_t L;              /* samples per block = lanes of a DPP row: 16 (0 = 16) */
+    int32_t L;              /* samples per block = lanes per group: 16 (a DPP row), 32 or 64
+                               (the whole wavefront); 32 and 64 with SOS_AUTO, SOS_PH and
+                               SOS_CR only (0 = 16) */
     int32_t tile_groups;    /* groups per tile (0 = chosen per call from n) */
     uint32_t flags;         /* SOS_FLAG_* */
 } sos_opts;
@@ -486,20 +489,21 @@ sos_status sos_filt_backward_batched_stored(sos_batch_t batch, const void *x, co
 
 /*
  * sos_batch_tune -- autotuner for batches: times sos_filt_batched for every
- * candidate (N, tile_groups) on the caller's own buffers and reports the
- * fastest.  L is not a candidate: it is fixed by the 16-lane DPP row.
+ * candidate (N, L, tile_groups) on the caller's own buffers and reports the
+ * fastest.
  *
  * sos, K     host [C]: channel c's [K[c]][6] coefficient rows (as sos_plan).
  * n, offsets as sos_batch_plan.
- * base       host, may be NULL: dtypes and solver of the plans (its N and
+ * base       host, may be NULL: dtypes and solver of the plans (its N, L and
  *            tile_groups are ignored).
- * Ns, nN     host: candidate N values; tiles, nt: candidate tile_groups
- *            (0 = the library's choice).
+ * Ns, nN     host: candidate N values; Ls, nL: candidate L values (16, 32,
+ *            64); tiles, nt: candidate tile_groups (0 = the library's
+ *            choice).
  * x, y       device buffers laid out as the batch (y is overwritten).
  * reps       timed launches per candidate, after untimed launches for at
  *            least 30 ms (code load, clocks after the host-side planning).
- * results    host [nN * nt] or NULL: every candidate's seconds per launch,
- *            N-major.
+ * results    host [nN * nL * nt] or NULL: every candidate's seconds per
+ *            launch, N-major, then L.
  * best       host: the fastest candidate.
  * Synchronous: it creates and destroys plans and batches (allocates) and
  * waits for its own launches on `stream`.  Errors from any candidate's plan
@@ -507,14 +511,16 @@ sos_status sos_filt_backward_batched_stored(sos_batch_t batch, const void *x, co
  */
 typedef struct {
     int32_t N;
+    int32_t L;
     int32_t tile_groups;
+    int32_t reserved;   /* 0 */
     double seconds;
 } sos_tune_result;
 
 sos_status sos_batch_tune(const double *const *sos, const int32_t *K, int32_t C, const int64_t *n,
                           const int64_t *offsets, const sos_opts *base, const int32_t *Ns, int32_t nN,
-                          const int32_t *tiles, int32_t nt, const void *x, void *y, int32_t reps,
-                          sos_stream_t stream, sos_tune_result *results, sos_tune_result *best);
+                          const int32_t *Ls, int32_t nL, const int32_t *tiles, int32_t nt, const void *x, void *y,
+                          int32_t reps, sos_stream_t stream, sos_tune_result *results, sos_tune_result *best);
 
 const char *sos_status_string(sos_status s);
 

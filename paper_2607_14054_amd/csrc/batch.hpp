@@ -11,7 +11,7 @@
 #include "dispatch.hpp"
 
 struct sos_batch_s {
-  int C = 0, N = 0, io_dtype = SOS_F32, compute_dtype = SOS_F64;
+  int C = 0, N = 0, L = 16, io_dtype = SOS_F32, compute_dtype = SOS_F64;
   int kmax = 0, mix = SOS_PH;
   int32_t tile_groups = 0;
   bool b0one = true, host_only = false;

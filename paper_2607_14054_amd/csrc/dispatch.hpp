@@ -46,6 +46,24 @@ sos_status dispatch_rows(int N, int io, int cd, bool b0one, int mix, A &&...args
   return SOS_E_UNSUPPORTED;
 }
 
+// The same for kernels that also take the block size L (16, 32 or 64):
+// Op<N, TI, T, B0ONE, SOLVER, L>.
+template <template <int, typename, typename, bool, int, int> class Op, int L>
+struct BindL {
+  template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+  struct type : Op<N, TI, T, B0ONE, SOLVER, L> {};
+};
+
+template <template <int, typename, typename, bool, int, int> class Op, typename... A>
+sos_status dispatch_rows_l(int N, int L, int io, int cd, bool b0one, int mix, A &&...args) {
+  switch (L) {
+    case 16: return dispatch_rows<BindL<Op, 16>::template type>(N, io, cd, b0one, mix, args...);
+    case 32: return dispatch_rows<BindL<Op, 32>::template type>(N, io, cd, b0one, mix, args...);
+    case 64: return dispatch_rows<BindL<Op, 64>::template type>(N, io, cd, b0one, mix, args...);
+    default: return SOS_E_UNSUPPORTED;
+  }
+}
+
 // Resident capacity of the device for one kernel: SIMDs and wavefronts per
 // SIMD (from the kernel's registers and LDS).
 struct Residency {
@@ -65,18 +83,18 @@ inline Residency residency_of(const void *kernel, size_t lds, int block_threads)
   return r;
 }
 
-// Groups per tile for a signal of `groups` groups.  Four rows (tiles) make
-// one wavefront.  Measured on the 2^28-sample cascade, launches are fastest
-// when every SIMD receives the same number of wavefronts m, and m is the
-// largest power of two the kernel keeps resident per SIMD: fewer leaves
-// the recurrences' latency exposed, and counts that do not divide evenly
-// (or odd multiples) leave part of the chip idle at the end.  So the tile is
-// the shortest that gives at most m wavefronts per SIMD.
-inline int64_t model_tile_groups(int64_t groups, int64_t warm_groups, const Residency &r) {
+// Groups per tile for a signal of `groups` groups.  64 / L rows (tiles)
+// make one wavefront.  Measured on the 2^28-sample cascade, launches are
+// fastest when every SIMD receives the same number of wavefronts m, and m
+// is the largest power of two the kernel keeps resident per SIMD: fewer
+// leaves the recurrences' latency exposed, and counts that do not divide
+// evenly (or odd multiples) leave part of the chip idle at the end.  So the
+// tile is the shortest that gives at most m wavefronts per SIMD.
+inline int64_t model_tile_groups(int64_t groups, int64_t warm_groups, const Residency &r, int rows_per_wave = 4) {
   (void)warm_groups;
   int64_t m = 1;
   while (2 * m <= r.waves_per_simd) m *= 2;
-  const int64_t rows = 4 * (int64_t)r.simds * m;
+  const int64_t rows = (int64_t)rows_per_wave * r.simds * m;
   return std::max<int64_t>((groups + rows - 1) / rows, 1);
 }
 

@@ -1,17 +1,20 @@
-// Device code: the multi-block filter on 16-lane DPP rows.
+// Device code: the multi-block filter on lane groups of L = 16, 32 or 64.
 //
-// Layout (Section V, with block size L = 16): a 64-wide wavefront holds four
-// independent signal block groups, one per DPP row of 16 lanes.  In row r,
-// lane l (0..15) holds the l-th run of N consecutive samples of that row's
-// group in registers X[0..N-1]; X[m] on lane l is x[m + l N], the l-th
-// element of the stride-N block xbar_m.  Moving a register one lane down
-// inside the row (lane l receives lane l-1, lane 0 a fill value) is the
-// shift matrix R.  Every cross-lane step is a DPP row operation.  The layout
-// is kept across all K sections (Section VII-B): one permutation when a
-// group is loaded, one de-permutation when it is stored.
+// Layout (Section V, block size L): a 64-wide wavefront holds 64 / L
+// independent signal block groups, one per group of L lanes ("row": for
+// L = 16 a DPP row).  In row r, lane l (0..L-1) holds the l-th run of N
+// consecutive samples of that row's group in registers X[0..N-1]; X[m] on
+// lane l is x[m + l N], the l-th element of the stride-N block xbar_m.
+// Moving a register one lane down inside the row (lane l receives lane
+// l-1, lane 0 a fill value) is the shift matrix R.  With L = 16 every
+// cross-lane step is a DPP row operation; with L = 32 or 64 the one-lane
+// shift is a DPP wave shift and the longer shifts of the log-depth scans go
+// through ds_bpermute.  The layout is kept across all K sections (Section
+// VII-B): one permutation when a group is loaded, one de-permutation when
+// it is stored.
 //
-// The four rows of a wavefront work on four different tiles of the signal,
-// so nothing couples them; groups inside a tile are chained through the
+// The rows of a wavefront work on different tiles of the signal, so
+// nothing couples them; groups inside a tile are chained through the
 // sections' boundary values (Section V), kept per row in LDS.
 #pragma once
 
@@ -45,7 +48,8 @@ __device__ __forceinline__ ctab<T> as_ctab(const T *p) {
 // ------------------------------------------------------------ lane moves
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-__device__ __forceinline__ int row_lane() { return (int)(threadIdx.x & 15); }
+template <int L = kL>
+__device__ __forceinline__ int row_lane() { return (int)(threadIdx.x & (L - 1)); }
 
 // DPP controls (GFX9 encoding): row_shr:d = 0x110 + d, row_newbcast:15 = 0x15f.
 template <int CTRL, bool ZERO>
@@ -60,51 +64,93 @@ __device__ __forceinline__ double dpp(double v) {
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Row shift by d with zeros entering the first d lanes of the row.
-template <int D, typename T>
-__device__ __forceinline__ T shr(T v) { return dpp<0x110 + D, true>(v); }
-
-// R with a fill value for lane 0 of the row: without bound_ctrl the DPP
-// move leaves a lane whose source is outside the row (lane 0 for row_shr:1)
-// at its old value, which is the fill.
-__device__ __forceinline__ float shift_r(float v, float fill) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), 0x111, 0xf, 0xf,
-                                                    false));
+// 32 bits from lane (lane - D) of the same row; lanes whose source lies
+// before the row's first lane take `fill`.  L = 16: DPP row_shr:D, whose
+// keep-old form leaves exactly those lanes at the old value, the fill.
+// L = 32, 64: D = 1 is the DPP wave shift (a lane at a row start takes the
+// fill by a select), longer shifts go through ds_bpermute (no LDS memory
+// is touched; a negative source wraps inside the wavefront and is then
+// replaced by the fill).
+template <int L, int D>
+__device__ __forceinline__ uint32_t lane_shift_u32(uint32_t v, uint32_t fill) {
+  if constexpr (L == 16) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x110 + D, 0xf, 0xf, false);
+  } else if constexpr (D == 1) {
+    const uint32_t s = (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, 0x138, 0xf, 0xf, false);
+    return row_lane<L>() == 0 ? fill : s;
+  } else {
+    const uint32_t s = (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() - D) << 2, (int)v);
+    return row_lane<L>() < D ? fill : s;
+  }
 }
-__device__ __forceinline__ double shift_r(double v, double fill) {
+template <int L, int D>
+__device__ __forceinline__ float lane_shift(float v, float fill) {
+  return __uint_as_float(lane_shift_u32<L, D>(__float_as_uint(v), __float_as_uint(fill)));
+}
+template <int L, int D>
+__device__ __forceinline__ double lane_shift(double v, double fill) {
   const uint64_t b = (uint64_t)__double_as_longlong(v), f = (uint64_t)__double_as_longlong(fill);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)f, (int)(uint32_t)b, 0x111, 0xf, 0xf, false);
-  const uint32_t hi =
-      (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(f >> 32), (int)(uint32_t)(b >> 32), 0x111, 0xf, 0xf, false);
+  const uint32_t lo = lane_shift_u32<L, D>((uint32_t)b, (uint32_t)f);
+  const uint32_t hi = lane_shift_u32<L, D>((uint32_t)(b >> 32), (uint32_t)(f >> 32));
   return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// Lane 15 of the row in every lane of the row (a 64-bit value moves in one
-// row_newbcast).
-__device__ __forceinline__ float last_of_row(float v) { return dpp<0x15f, false>(v); }
+// Row shift by D with zeros entering the first D lanes of the row.
+template <int D, typename T, int L = kL>
+__device__ __forceinline__ T shr(T v) {
+  if constexpr (L == 16) return dpp<0x110 + D, true>(v);
+  else return lane_shift<L, D>(v, T(0));
+}
+
+// R with a fill value for lane 0 of the row.
+template <int L = kL, typename T>
+__device__ __forceinline__ T shift_r(T v, T fill) { return lane_shift<L, 1>(v, fill); }
+
+// The row's last lane in every lane of the row.  L = 16: row_newbcast:15
+// (a 64-bit value moves in one instruction); L = 64: the wavefront's lane
+// 63, read into scalar registers; L = 32: lane 31 or 63 by half.
+template <int L = kL>
+__device__ __forceinline__ float last_of_row(float v) {
+  if constexpr (L == 16) return dpp<0x15f, false>(v);
+  const int a = __builtin_amdgcn_readlane(__float_as_int(v), 63);
+  if constexpr (L == 64) return __int_as_float(a);
+  const int b = __builtin_amdgcn_readlane(__float_as_int(v), 31);
+  return __int_as_float(lane_id() < 32 ? b : a);
+}
+template <int L = kL>
 __device__ __forceinline__ double last_of_row(double v) {
-  return __longlong_as_double(__builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x15f, 0xf, 0xf, false));
+  if constexpr (L == 16)
+    return __longlong_as_double(__builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x15f, 0xf, 0xf, false));
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo63 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+  const uint32_t hi63 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+  if constexpr (L == 64) return __longlong_as_double((long long)(((uint64_t)hi63 << 32) | lo63));
+  const uint32_t lo31 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 31);
+  const uint32_t hi31 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 31);
+  const bool first = lane_id() < 32;
+  return __longlong_as_double(
+      (long long)(((uint64_t)(first ? hi31 : hi63) << 32) | (first ? lo31 : lo63)));
 }
 
 // 1 in lane 0 of the row, 0 elsewhere: multiplies the previous group's
 // boundary values into the first lane only.
-template <typename T>
-__device__ __forceinline__ T lane0_mask() { return row_lane() == 0 ? T(1) : T(0); }
+template <typename T, int L = kL>
+__device__ __forceinline__ T lane0_mask() { return row_lane<L>() == 0 ? T(1) : T(0); }
 
 // Log-depth solve along the row of z_l = A z_{l-1} + z_l (z_{-1} = 0) for
 // 2-vectors z = (p, q): round j adds A^(2^j) times the value 2^j lanes below
-// (Kogge-Stone doubling).  pw holds A^(2^j) row-major for j = 0..3.
-template <typename T>
+// (Kogge-Stone doubling).  pw holds A^(2^j) row-major for j = 0..log2(L)-1.
+template <typename T, int L = kL>
 __device__ __forceinline__ void row_scan_2x2(T &p, T &q, ctab<T> pw) {
 #define SOSF_ROUND(J, D)                                                          \
-  {                                                                               \
+  if constexpr (D < L) {                                                          \
     const T m00 = pw[4 * J], m01 = pw[4 * J + 1], m10 = pw[4 * J + 2], m11 = pw[4 * J + 3]; \
-    const T ps = shr<D>(p), qs = shr<D>(q);                                       \
+    const T ps = shr<D, T, L>(p), qs = shr<D, T, L>(q);                           \
     const T np = fma_(m00, ps, fma_(m01, qs, p));               \
     q = fma_(m10, ps, fma_(m11, qs, q));                        \
     p = np;                                                                       \
   }
-  SOSF_ROUND(0, 1) SOSF_ROUND(1, 2) SOSF_ROUND(2, 4) SOSF_ROUND(3, 8)
+  SOSF_ROUND(0, 1) SOSF_ROUND(1, 2) SOSF_ROUND(2, 4) SOSF_ROUND(3, 8) SOSF_ROUND(4, 16) SOSF_ROUND(5, 32)
 #undef SOSF_ROUND
 }
 
@@ -165,33 +211,33 @@ __device__ __forceinline__ void particular_pass(T (&X)[N], T a1, T a2, T w1, T w
 // entry; ys = (y[-2], y[-1]) of its output, read and then replaced by the
 // group's last two outputs.  Section k's input is section k-1's output, so
 // on exit (xs2, xs1) holds the old ys: the next section's input state.
-template <int N, typename T, bool B0ONE>
+template <int N, typename T, bool B0ONE, int L = kL>
 __device__ __forceinline__ void ph_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1, T *ys) {
   const T a1 = c[OFF_A1], a2 = c[OFF_A2];
   const T ys2 = ys[0], ys1 = ys[1];
-  fir_pass<N, T, B0ONE>(X, c, shift_r(X[N - 1], xs1), shift_r(X[N - 2], xs2));
+  fir_pass<N, T, B0ONE>(X, c, shift_r<L>(X[N - 1], xs1), shift_r<L>(X[N - 2], xs2));
   __builtin_amdgcn_sched_barrier(0);
   // step 1, eq. particular_recurrence: every lane a zero-state recurrence
   // over its own N samples.  On lane 0 of the row the recurrence starts from
   // the previous group's outputs, which is the same arithmetic as the state
   // correction of v_0[0] and v_1[0].
-  const T m0 = lane0_mask<T>();
+  const T m0 = lane0_mask<T, L>();
   particular_pass<N, T>(X, a1, a2, m0 * ys1, m0 * ys2);
   // step 2, eq. recursive_doubling_equation: y_e[l] = w_e[l] - C y_e[l-1]
   // along the row, with y_e[l] = (y[(l+1)N-2], y[(l+1)N-1])
   T p = X[N - 2], q = X[N - 1];
-  row_scan_2x2(p, q, c + OFF_PH_POW);
+  row_scan_2x2<T, L>(p, q, c + OFF_PH_POW);
   X[N - 2] = p;
   X[N - 1] = q;
   // step 3, eq. PH_forward: the homogeneous correction from the true
   // terminal values of the preceding lane (R y_{N-2}, R y_{N-1})
-  const T pr = shr<1>(p), qr = shr<1>(q);
+  const T pr = shr<1, T, L>(p), qr = shr<1, T, L>(q);
   const ctab<T> u1 = c + OFF_U1;
   const ctab<T> u2 = c + OFF_U1 + N;
 #pragma unroll
   for (int m = 0; m < N - 2; ++m) X[m] = fma_(-u2[m], pr, fma_(-u1[m], qr, X[m]));
-  ys[0] = last_of_row(p);
-  ys[1] = last_of_row(q);
+  ys[0] = last_of_row<L>(p);
+  ys[1] = last_of_row<L>(q);
   xs2 = ys2;
   xs1 = ys1;
 }
@@ -201,15 +247,15 @@ __device__ __forceinline__ void ph_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
 // are eliminated, odd j retained.  A reference below j = 0 wraps to the last
 // blocks through R.
 // Boundary values as for ph_section.
-template <int N, typename T, bool B0ONE>
+template <int N, typename T, bool B0ONE, int L = kL>
 __device__ __forceinline__ void cr_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1, T *ys) {
   constexpr int LG = __builtin_ctz(N);
   const T a1 = c[OFF_A1], a2 = c[OFF_A2];
   const T ys2 = ys[0], ys1 = ys[1];
-  fir_pass<N, T, B0ONE>(X, c, shift_r(X[N - 1], xs1), shift_r(X[N - 2], xs2));
+  fir_pass<N, T, B0ONE>(X, c, shift_r<L>(X[N - 1], xs1), shift_r<L>(X[N - 2], xs2));
   __builtin_amdgcn_sched_barrier(0);
   // the previous group's outputs enter the first element of blocks 0 and 1
-  const T m0 = lane0_mask<T>(), z1 = m0 * ys1, z2 = m0 * ys2;
+  const T m0 = lane0_mask<T, L>(), z1 = m0 * ys1, z2 = m0 * ys2;
   X[0] = fma_(-a1, z1, fma_(-a2, z2, X[0]));
   X[1] = fma_(-a2, z1, X[1]);
   // reduction, eq. cr_coeff_update coefficients per level
@@ -217,7 +263,7 @@ __device__ __forceinline__ void cr_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
   for (int i = 0; i < LG; ++i) {
     const int s = 1 << i, ni = N >> i;
     const T fe = c[OFF_CR_LVL + 4 * i], e = c[OFF_CR_LVL + 4 * i + 1];
-    const T wrap = shr<1>(X[N - 1]);
+    const T wrap = shr<1, T, L>(X[N - 1]);
 #pragma unroll
     for (int j = 0; j < ni; j += 2) {
       const int m = s * (j + 1) - 1;
@@ -234,18 +280,18 @@ __device__ __forceinline__ void cr_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
   // scan of z_l = (y_{l-1}, y_l) = T z_{l-1} + (0, v'_l)
   {
     T p = T(0), q = X[N - 1];
-    row_scan_2x2(p, q, c + OFF_CR_POW);
+    row_scan_2x2<T, L>(p, q, c + OFF_CR_POW);
     X[N - 1] = q;
   }
   // back substitution, eqs. cr_companion_block .. cr_backsub_final
-  const T r1 = shr<1>(X[N - 1]);   // R y_{N-1}, reused at every level
+  const T r1 = shr<1, T, L>(X[N - 1]);   // R y_{N-1}, reused at every level
 #pragma unroll
   for (int i = LG - 1; i >= 0; --i) {
     const int s = 1 << i, ni = N >> i;
     const T cc = c[OFF_CR_LVL + 4 * i + 2], dd = c[OFF_CR_LVL + 4 * i + 3];
     T w3;   // the once-wrapped block for j = 0
-    if (ni == 2) w3 = shr<1>(r1);                 // R^2 y_{N-1}
-    else w3 = shr<1>(X[N - 2 * s - 1]);           // R y at position ni-3
+    if (ni == 2) w3 = shr<1, T, L>(r1);                 // R^2 y_{N-1}
+    else w3 = shr<1, T, L>(X[N - 2 * s - 1]);           // R y at position ni-3
 #pragma unroll
     for (int j = 0; j < ni; j += 2) {
       const int m = s * (j + 1) - 1;
@@ -254,8 +300,8 @@ __device__ __forceinline__ void cr_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
       X[m] = fma_(-cc, y1, fma_(-dd, y3, X[m]));
     }
   }
-  ys[0] = last_of_row(X[N - 2]);
-  ys[1] = last_of_row(X[N - 1]);
+  ys[0] = last_of_row<L>(X[N - 2]);
+  ys[1] = last_of_row<L>(X[N - 1]);
   xs2 = ys2;
   xs1 = ys1;
 }
@@ -272,26 +318,27 @@ struct Vec16<float> { typedef vf4 type; static constexpr int n = 4; };
 template <>
 struct Vec16<double> { typedef vd2 type; static constexpr int n = 2; };
 
-// A group (16 N samples per row) is moved between HBM and registers through
-// a per-wave LDS buffer.  Global accesses are 16-byte vectors, 16 lanes of a
-// row covering 256 consecutive bytes of that row's group per instruction;
-// the stride-N permutation happens in LDS, where lane l reads or writes its
-// own run of N samples.  Each run is padded by 16 bytes so that the 16-byte
-// LDS accesses of a row fall on distinct banks.
-template <int N, typename TI>
+// A group (L N samples per row) is moved between HBM and registers through
+// a per-wave LDS buffer.  Global accesses are 16-byte vectors, the L lanes
+// of a row covering 16 L consecutive bytes of that row's group per
+// instruction; the stride-N permutation happens in LDS, where lane l reads
+// or writes its own run of N samples.  Each run is padded by 16 bytes so
+// that the 16-byte LDS accesses of 16 lanes fall on distinct banks.
+template <int N, typename TI, int L = kL>
 struct Stage {
   static constexpr int V = Vec16<TI>::n;        // elements per 16-byte vector
   static constexpr int RUN = N + V;             // padded run length (elements)
-  static constexpr int ROWBUF = kL * RUN;       // per row
-  static constexpr int ELEMS = kRows * ROWBUF;  // per wave
+  static constexpr int ROWBUF = L * RUN;        // per row
+  static constexpr int ROWS = 64 / L;           // rows per wave
+  static constexpr int ELEMS = ROWS * ROWBUF;   // per wave
 };
 
 // Lane l's run of the row's staged group <-> its N registers.
-template <int N, typename TI, typename T>
+template <int N, typename TI, typename T, int L = kL>
 __device__ __forceinline__ void stage_to_regs(T (&X)[N], const TI *__restrict__ buf) {
   typedef typename Vec16<TI>::type VT;
-  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
-  const int rl = row_lane();
+  constexpr int V = Stage<N, TI, L>::V, RUN = Stage<N, TI, L>::RUN;
+  const int rl = row_lane<L>();
 #pragma unroll
   for (int j = 0; j < N / V; ++j) {
     VT v = *reinterpret_cast<const VT *>(buf + rl * RUN + j * V);
@@ -299,11 +346,11 @@ __device__ __forceinline__ void stage_to_regs(T (&X)[N], const TI *__restrict__ 
     for (int i = 0; i < V; ++i) X[j * V + i] = T(v[i]);
   }
 }
-template <int N, typename TI, typename T>
+template <int N, typename TI, typename T, int L = kL>
 __device__ __forceinline__ void regs_to_stage(const T (&X)[N], T gain, TI *__restrict__ buf) {
   typedef typename Vec16<TI>::type VT;
-  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
-  const int rl = row_lane();
+  constexpr int V = Stage<N, TI, L>::V, RUN = Stage<N, TI, L>::RUN;
+  const int rl = row_lane<L>();
 #pragma unroll
   for (int j = 0; j < N / V; ++j) {
     VT v;
@@ -316,53 +363,53 @@ __device__ __forceinline__ void regs_to_stage(const T (&X)[N], T gain, TI *__res
 // g: this row's group start (may be negative or run past n in the run-in
 // and at the end; those samples read as zero).  full: every row of the wave
 // has a whole group inside [0, n).
-template <int N, typename TI, typename T>
+template <int N, typename TI, typename T, int L = kL>
 __device__ __forceinline__ void load_group(T (&X)[N], const TI *__restrict__ x, int64_t g,
                                            int64_t n, bool full, TI *__restrict__ buf) {
   typedef typename Vec16<TI>::type VT;
-  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
-  const int rl = row_lane();
+  constexpr int V = Stage<N, TI, L>::V, RUN = Stage<N, TI, L>::RUN;
+  const int rl = row_lane<L>();
   if (full) {
     const VT *src = reinterpret_cast<const VT *>(x + g);
 #pragma unroll
     for (int j = 0; j < N / V; ++j) {
-      const int e = (j * kL + rl) * V;            // element of the row's group
-      VT v = __builtin_nontemporal_load(src + j * kL + rl);
+      const int e = (j * L + rl) * V;             // element of the row's group
+      VT v = __builtin_nontemporal_load(src + j * L + rl);
       *reinterpret_cast<VT *>(buf + (e / N) * RUN + (e % N)) = v;
     }
   } else {
 #pragma unroll 1
     for (int j = 0; j < N; ++j) {
-      const int e = j * kL + rl;
+      const int e = j * L + rl;
       const int64_t i = g + e;
       buf[(e / N) * RUN + (e % N)] = (i >= 0 && i < n) ? x[i] : TI(0);
     }
   }
   __builtin_amdgcn_wave_barrier();
-  stage_to_regs<N, TI, T>(X, buf);
+  stage_to_regs<N, TI, T, L>(X, buf);
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int N, typename TI, typename T>
+template <int N, typename TI, typename T, int L = kL>
 __device__ __forceinline__ void store_group(const T (&X)[N], TI *__restrict__ y, int64_t g,
                                             int64_t n, bool full, T gain, TI *__restrict__ buf) {
   typedef typename Vec16<TI>::type VT;
-  constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN;
-  const int rl = row_lane();
-  regs_to_stage<N, TI, T>(X, gain, buf);
+  constexpr int V = Stage<N, TI, L>::V, RUN = Stage<N, TI, L>::RUN;
+  const int rl = row_lane<L>();
+  regs_to_stage<N, TI, T, L>(X, gain, buf);
   __builtin_amdgcn_wave_barrier();
   if (full) {
     VT *dst = reinterpret_cast<VT *>(y + g);
 #pragma unroll
     for (int j = 0; j < N / V; ++j) {
-      const int e = (j * kL + rl) * V;
+      const int e = (j * L + rl) * V;
       VT v = *reinterpret_cast<const VT *>(buf + (e / N) * RUN + (e % N));
-      __builtin_nontemporal_store(v, dst + j * kL + rl);
+      __builtin_nontemporal_store(v, dst + j * L + rl);
     }
   } else {
 #pragma unroll 1
     for (int j = 0; j < N; ++j) {
-      const int e = j * kL + rl;
+      const int e = j * L + rl;
       const int64_t i = g + e;
       if (i >= 0 && i < n) y[i] = buf[(e / N) * RUN + (e % N)];
     }
@@ -384,16 +431,16 @@ struct FiltArgs {
 
 constexpr int kWavesPerBlock = 4;
 
-template <int N, typename TI>
+template <int N, typename TI, int L = kL>
 __host__ __device__ constexpr int stage_bytes() {
-  return kWavesPerBlock * Stage<N, TI>::ELEMS * (int)sizeof(TI);
+  return kWavesPerBlock * Stage<N, TI, L>::ELEMS * (int)sizeof(TI);
 }
 // Boundary values per row: the raw input's (x[-2], x[-1]), then every
 // section's (y[-2], y[-1]).
 __host__ __device__ constexpr int state_elems(int K) { return 2 + 2 * K; }
-template <int N, typename TI, typename T>
+template <int N, typename TI, typename T, int L = kL>
 __host__ __device__ constexpr int lds_bytes(int K) {
-  return stage_bytes<N, TI>() + kWavesPerBlock * kRows * state_elems(K) * (int)sizeof(T);
+  return stage_bytes<N, TI, L>() + kWavesPerBlock * (64 / L) * state_elems(K) * (int)sizeof(T);
 }
 
 // One wavefront filters four tiles, one per row: row r's tile starts at
@@ -407,31 +454,31 @@ __host__ __device__ constexpr int lds_bytes(int K) {
 //
 // SOLVER: SOS_PH or SOS_CR when every section uses that solver (no branch
 // in the section loop), SOS_AUTO for a per-section choice.
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER, int L = kL>
 __device__ __forceinline__ void filter_rows(const TI *__restrict__ x, TI *__restrict__ y,
                                             ctab<T> tab, const int32_t *__restrict__ solver,
                                             int64_t n, int K,
                                             int stride, int64_t t0, int64_t warm, int64_t tile,
                                             bool aligned, T gain, T *st, TI *buf) {
   for (int i = 0; i < state_elems(K); ++i) st[i] = T(0);   // the row's lanes write the same value
-  const int64_t G = (int64_t)N * kL;
+  const int64_t G = (int64_t)N * L;
   const int64_t warm_groups = warm / G, steps = warm_groups + tile / G;
   T X[N];
   for (int64_t it = 0; it < steps; ++it) {
     const int64_t g = t0 - warm + it * G;
     const bool full = aligned && __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= n)) == 0;
-    load_group<N, TI, T>(X, x, g, n, full, buf);
+    load_group<N, TI, T, L>(X, x, g, n, full, buf);
     T xs2 = st[0], xs1 = st[1];
-    st[0] = last_of_row(X[N - 2]);
-    st[1] = last_of_row(X[N - 1]);
+    st[0] = last_of_row<L>(X[N - 2]);
+    st[1] = last_of_row<L>(X[N - 1]);
     for (int k = 0; k < K; ++k) {
       const ctab<T> c = tab + (int64_t)k * stride;
       if (SOLVER == SOS_CR || (SOLVER == SOS_AUTO && solver[k] == SOS_CR))
-        cr_section<N, T, B0ONE>(X, c, xs2, xs1, st + 2 + 2 * k);
+        cr_section<N, T, B0ONE, L>(X, c, xs2, xs1, st + 2 + 2 * k);
       else
-        ph_section<N, T, B0ONE>(X, c, xs2, xs1, st + 2 + 2 * k);
+        ph_section<N, T, B0ONE, L>(X, c, xs2, xs1, st + 2 + 2 * k);
     }
-    if (it >= warm_groups) store_group<N, TI, T>(X, y, g, n, full, gain, buf);
+    if (it >= warm_groups) store_group<N, TI, T, L>(X, y, g, n, full, gain, buf);
   }
 }
 
@@ -441,26 +488,27 @@ __device__ __forceinline__ void filter_rows(const TI *__restrict__ x, TI *__rest
 // The pointers are separate restrict-qualified arguments so that the
 // compiler may read the coefficient table (uniform addresses, never
 // written here) through the scalar cache.
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER, int L = kL>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const T *__restrict__ tab,
     const int32_t *__restrict__ solver, FiltArgs a) {
+  constexpr int R = 64 / L;   // rows (tiles) per wave
   // dynamic LDS: the staging buffers, then the boundary values of every
   // section of every row (sized for the plan's K at launch)
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   TI *stage = reinterpret_cast<TI *>(smem);
-  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, TI>());
+  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, TI, L>());
   // the wave index is uniform across the wave; say so, so that everything
   // derived from it stays in scalar registers
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + w;
-  if (wave * kRows >= a.ntiles) return;   // uniform per wave
-  const int row = lane_id() >> 4;
-  const int64_t t0 = (wave * kRows + row) * a.tile;   // this row's tile
-  T *st = state + (int64_t)(w * kRows + row) * state_elems(a.K);
-  TI *buf = stage + (w * kRows + row) * Stage<N, TI>::ROWBUF;
-  filter_rows<N, TI, T, B0ONE, SOLVER>(x, y, as_ctab(tab), solver, a.n, a.K, a.stride, t0, a.warm, a.tile,
-                                       true, (T)a.gain, st, buf);
+  if (wave * R >= a.ntiles) return;   // uniform per wave
+  const int row = lane_id() / L;
+  const int64_t t0 = (wave * R + row) * a.tile;   // this row's tile
+  T *st = state + (int64_t)(w * R + row) * state_elems(a.K);
+  TI *buf = stage + (w * R + row) * Stage<N, TI, L>::ROWBUF;
+  filter_rows<N, TI, T, B0ONE, SOLVER, L>(x, y, as_ctab(tab), solver, a.n, a.K, a.stride, t0, a.warm, a.tile,
+                                          true, (T)a.gain, st, buf);
 }
 
 // Batched ragged channels.  Each channel c has its own plan (K, tables, b0
@@ -484,13 +532,14 @@ struct BatchChan {
 // hdr: the batch's device header, hdr[0] the live item count (the grid is
 // sized for the batch's room, so that one launch, captured once, serves
 // every channel set the batch is replanned to).
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER, int L = kL>
 __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_batched_kernel(
     const TI *__restrict__ x, TI *__restrict__ y, const BatchChan *__restrict__ chans,
     const int32_t *__restrict__ item_chan, const int64_t *__restrict__ hdr, int32_t kmax) {
+  constexpr int R = 64 / L;   // rows (tiles) per wave
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   TI *stage = reinterpret_cast<TI *>(smem);
-  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, TI>());
+  T *state = reinterpret_cast<T *>(smem + stage_bytes<N, TI, L>());
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t item = (int64_t)blockIdx.x * kWavesPerBlock + w;
   if (item >= hdr[0]) return;   // uniform per wave
@@ -500,18 +549,18 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_batched_kernel(
   // group starts on a 16-byte boundary; samples before 0 read as zeros and
   // are not stored
   const int64_t ntiles = (ch.n + ch.shift + ch.tile - 1) / ch.tile;
-  const int row = lane_id() >> 4;
-  const int64_t t0 = (quad * kRows + row) * ch.tile - ch.shift;
+  const int row = lane_id() / L;
+  const int64_t t0 = (quad * R + row) * ch.tile - ch.shift;
   // rows past the channel's end idle; the run-in never reaches before the
   // channel's start (the state there is zero)
-  const int64_t last = (quad * kRows + kRows - 1 < ntiles - 1 ? quad * kRows + kRows - 1 : ntiles - 1);
+  const int64_t last = (quad * R + R - 1 < ntiles - 1 ? quad * R + R - 1 : ntiles - 1);
   const int64_t warm = ch.warm < last * ch.tile ? ch.warm : last * ch.tile;
-  T *st = state + (int64_t)(w * kRows + row) * state_elems(kmax);
-  TI *buf = stage + (w * kRows + row) * Stage<N, TI>::ROWBUF;
+  T *st = state + (int64_t)(w * R + row) * state_elems(kmax);
+  TI *buf = stage + (w * R + row) * Stage<N, TI, L>::ROWBUF;
   const ctab<T> tab = as_ctab(static_cast<const T *>(ch.tab));
 #define SOSF_BATCH_ROWS(S)                                                                       \
-  filter_rows<N, TI, T, B0ONE, S>(x + ch.off, y + ch.off, tab, ch.solver, ch.n, ch.K, ch.stride, t0, warm, \
-                                  ch.tile, true, (T)ch.gain, st, buf)
+  filter_rows<N, TI, T, B0ONE, S, L>(x + ch.off, y + ch.off, tab, ch.solver, ch.n, ch.K, ch.stride, t0, warm, \
+                                     ch.tile, true, (T)ch.gain, st, buf)
   if (SOLVER != SOS_AUTO) {
     SOSF_BATCH_ROWS(SOLVER);
   } else {

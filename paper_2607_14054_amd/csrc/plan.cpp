@@ -117,7 +117,7 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
     p.C[4 * k + 0] = C.a; p.C[4 * k + 1] = C.b; p.C[4 * k + 2] = C.c; p.C[4 * k + 3] = C.d;
     // terminal-block scan y_e[l] = w_e[l] - C y_e[l-1] with powers of A = -C
     Mat2 A{-C.a, -C.b, -C.c, -C.d};
-    for (int j = 0; j < kLogL; ++j) {
+    for (int j = 0; j < kMaxLogL; ++j) {
       double *q = t + OFF_PH_POW + 4 * j;
       q[0] = A.a; q[1] = A.b; q[2] = A.c; q[3] = A.d;
       A = mul(A, A);
@@ -151,7 +151,7 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
     p.cr_term[2 * k] = e;
     p.cr_term[2 * k + 1] = f;
     Mat2 T{0.0, 1.0, -f, -e};
-    for (int j = 0; j < kLogL; ++j) {
+    for (int j = 0; j < kMaxLogL; ++j) {
       double *q = t + OFF_CR_POW + 4 * j;
       q[0] = T.a; q[1] = T.b; q[2] = T.c; q[3] = T.d;
       T = mul(T, T);
@@ -200,7 +200,7 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
     }
   }
   int64_t W = lo + 1;
-  const int64_t NL = (int64_t)N * kL;
+  const int64_t NL = (int64_t)N * p.L;
   p.warm = ((W + NL - 1) / NL) * NL;
   // the norm over the rounded length, for reporting
   {

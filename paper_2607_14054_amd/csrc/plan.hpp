@@ -11,9 +11,10 @@
 
 namespace sosf {
 
-constexpr int kL = 16;           // block size L = lanes of one DPP row
+constexpr int kL = 16;           // default block size L = lanes of one DPP row
 constexpr int kLogL = 4;
-constexpr int kRows = 4;         // independent blocks (rows) per 64-wide wavefront
+constexpr int kRows = 4;         // independent blocks (rows) per 64-wide wavefront at L = 16
+constexpr int kMaxLogL = 6;      // largest L is 64, a whole wavefront
 constexpr int kMaxLevels = 10;   // log2 of the largest N the tables hold
 constexpr int kBwdN = 16;        // N of the adjoint kernels
 constexpr int kBwdRow = 8;       // doubles per section in the adjoint rows
@@ -22,9 +23,9 @@ constexpr int kBwdRow = 8;       // doubles per section in the adjoint rows
 // device table.  Row length = tab_stride(N).
 enum : int {
   OFF_B0 = 0, OFF_B1 = 1, OFF_B2 = 2, OFF_A1 = 3, OFF_A2 = 4,
-  OFF_PH_POW = 8,                              // 4 x 4: (-C)^(2^j)
-  OFF_CR_POW = OFF_PH_POW + 4 * kLogL,         // 4 x 4: T^(2^j)
-  OFF_CR_LVL = OFF_CR_POW + 4 * kLogL,         // 10 x 4: f/e, e, c, d
+  OFF_PH_POW = 8,                              // 6 x 4: (-C)^(2^j), j < log2 L
+  OFF_CR_POW = OFF_PH_POW + 4 * kMaxLogL,      // 6 x 4: T^(2^j), j < log2 L
+  OFF_CR_LVL = OFF_CR_POW + 4 * kMaxLogL,      // 10 x 4: f/e, e, c, d
   OFF_U1 = OFF_CR_LVL + 4 * kMaxLevels,        // N
 };
 inline int off_u2(int N) { return OFF_U1 + N; }

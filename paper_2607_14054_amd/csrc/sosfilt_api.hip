@@ -60,13 +60,13 @@ struct Ptrs {
   const int32_t *solver;
 };
 
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER, int L>
 struct LaunchRows {
   static sos_status run(const Ptrs &q, const FiltArgs &a, hipStream_t s) {
-    const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
+    const int64_t per_block = (int64_t)kWavesPerBlock * (64 / L);
     const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
-    const unsigned lds = (unsigned)lds_bytes<N, TI, T>(a.K);
-    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, B0ONE, SOLVER>), dim3((unsigned)blocks),
+    const unsigned lds = (unsigned)lds_bytes<N, TI, T, L>(a.K);
+    hipLaunchKernelGGL((sos_rows_kernel<N, TI, T, B0ONE, SOLVER, L>), dim3((unsigned)blocks),
                        dim3(kWavesPerBlock * 64), lds, s,
                        static_cast<const TI *>(q.x), static_cast<TI *>(q.y),
                        static_cast<const T *>(q.tab), q.solver, a);
@@ -74,11 +74,11 @@ struct LaunchRows {
   }
 };
 
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER, int L>
 struct ResidencyRows {
   static sos_status run(int K, Residency *r) {
-    *r = residency_of(reinterpret_cast<const void *>(&sos_rows_kernel<N, TI, T, B0ONE, SOLVER>),
-                      (size_t)lds_bytes<N, TI, T>(K), kWavesPerBlock * 64);
+    *r = residency_of(reinterpret_cast<const void *>(&sos_rows_kernel<N, TI, T, B0ONE, SOLVER, L>),
+                      (size_t)lds_bytes<N, TI, T, L>(K), kWavesPerBlock * 64);
     return SOS_OK;
   }
 };
@@ -208,13 +208,13 @@ sos_status launch_scalar(const sos_plan_s &p, const void *x, void *y, int64_t n,
 // Tile length for n samples: the plan's fixed choice, or the launch-shape
 // model for the kernel the plan runs.
 int64_t choose_tile(const sos_plan_s &p, int64_t n) {
-  const int64_t G = (int64_t)p.N * kL;
+  const int64_t G = (int64_t)p.N * p.L;
   if (p.tile_groups > 0) return (int64_t)p.tile_groups * G;
   const int64_t groups = (n + G - 1) / G;
   Residency r;
   r.simds = p.simds;
   r.waves_per_simd = p.waves_per_simd;
-  return model_tile_groups(groups, p.warm / G, r) * G;
+  return model_tile_groups(groups, p.warm / G, r, 64 / p.L) * G;
 }
 
 }  // namespace
@@ -277,7 +277,10 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   if (low && o.solver != SOS_BLOCK) return SOS_E_UNSUPPORTED;
   if (o.solver == SOS_BLOCK && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
   if (o.tile_groups < 0) return SOS_E_ARG;
-  if (!pow2_in(o.N, 8, 64) || o.L != kL) return SOS_E_UNSUPPORTED;
+  if (!pow2_in(o.N, 8, 64) || !pow2_in(o.L, 16, 64)) return SOS_E_UNSUPPORTED;
+  // the block sizes L = 32, 64 exist for PH and CR (the other solvers work
+  // on 16-lane rows or single lanes)
+  if (o.L != kL && !(o.solver == SOS_AUTO || o.solver == SOS_PH || o.solver == SOS_CR)) return SOS_E_UNSUPPORTED;
   if (o.io_dtype == SOS_F64 && (o.compute_dtype == SOS_F32 || low)) return SOS_E_UNSUPPORTED;
   const bool deferred_ok = o.compute_dtype == SOS_F64 && o.N >= 16 && K <= 16;
   if (o.solver == SOS_PH_DEFERRED && !deferred_ok) return SOS_E_UNSUPPORTED;
@@ -335,8 +338,8 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
       r.simds = p->simds;
       r.waves_per_simd = p->waves_per_simd;
     } else if (st == SOS_OK)
-      dispatch_rows<ResidencyRows>(p->N, p->io_dtype, p->compute_dtype, p->b0_factored, solver_mix(*p),
-                                   p->K, &r);
+      dispatch_rows_l<ResidencyRows>(p->N, p->L, p->io_dtype, p->compute_dtype, p->b0_factored, solver_mix(*p),
+                                     p->K, &r);
     p->simds = r.simds;
     p->waves_per_simd = r.waves_per_simd;
     if (st == SOS_OK && adjoint) st = attach_adjoint(*p, sos);
@@ -406,10 +409,10 @@ sos_status sos_plan_table(sos_plan_t p, int32_t table, int32_t section, double *
     case SOS_TABLE_U1: buf.assign(t + OFF_U1, t + OFF_U1 + p->N); break;
     case SOS_TABLE_U2: buf.assign(t + off_u2(p->N), t + off_u2(p->N) + p->N); break;
     case SOS_TABLE_C: buf.assign(p->C.begin() + 4 * section, p->C.begin() + 4 * section + 4); break;
-    case SOS_TABLE_PH_POWERS: buf.assign(t + OFF_PH_POW, t + OFF_PH_POW + 4 * kLogL); break;
+    case SOS_TABLE_PH_POWERS: buf.assign(t + OFF_PH_POW, t + OFF_PH_POW + 4 * __builtin_ctz((unsigned)p->L)); break;
     case SOS_TABLE_CR_LEVELS: buf.assign(t + OFF_CR_LVL, t + OFF_CR_LVL + 4 * p->lgN); break;
     case SOS_TABLE_CR_TERMINAL: buf.assign(p->cr_term.begin() + 2 * section, p->cr_term.begin() + 2 * section + 2); break;
-    case SOS_TABLE_CR_POWERS: buf.assign(t + OFF_CR_POW, t + OFF_CR_POW + 4 * kLogL); break;
+    case SOS_TABLE_CR_POWERS: buf.assign(t + OFF_CR_POW, t + OFF_CR_POW + 4 * __builtin_ctz((unsigned)p->L)); break;
     case SOS_TABLE_TRANSITION: buf = p->phi; break;
     case SOS_TABLE_THETA:
       if (p->theta.empty()) return SOS_E_ARG;
@@ -472,7 +475,7 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
     if (p->flags & SOS_FLAG_CARRY_SCAN) return SOS_E_ARG;   // asked for, but no workspace
   }
   // one solver for every section lets the kernel drop the per-section branch
-  return dispatch_rows<LaunchRows>(p->N, p->io_dtype, p->compute_dtype, b0one, solver_mix(*p), q, a, s);
+  return dispatch_rows_l<LaunchRows>(p->N, p->L, p->io_dtype, p->compute_dtype, b0one, solver_mix(*p), q, a, s);
 }
 
 }  // extern "C"

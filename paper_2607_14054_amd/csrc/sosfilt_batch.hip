@@ -29,7 +29,8 @@ struct ChanWork {
 
 // Groups per tile (the cap every channel's tile stays under), from a
 // makespan model.  Each candidate cap gives every channel's work items
-// (quads of four equal row tiles, each preceded by its run-in, clamped at
+// (items of 64 / L equal row tiles, or four for block filtering, each
+// preceded by its run-in, clamped at
 // the channel start) and their cost in group-sections, K (tile + run-in).
 // In SIMD time, with a = total / simds and b = (longest item) *
 // waves_per_simd, the launch takes between max(a, b) and a + b (the
@@ -40,7 +41,8 @@ struct ChanWork {
 // parallelism even at the cost of run-in many times its tile.  Ties go to
 // the longer tile.
 int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t waves_per_simd,
-                          int64_t waves_per_item = 1) {
+                          int64_t waves_per_item, int64_t tiles_per_item) {
+  const int64_t R = tiles_per_item;
   int64_t best_tg = 8;
   double best = -1.0;
   for (int e = 12; e >= 0; --e) {
@@ -48,8 +50,8 @@ int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t
     double total = 0.0, longest = 0.0;
     for (const ChanWork &c : w) {
       if (c.groups == 0) continue;
-      const int64_t quads = (c.groups + 4 * tg - 1) / (4 * tg);
-      const int64_t tgc = (c.groups + 4 * quads - 1) / (4 * quads);
+      const int64_t quads = (c.groups + R * tg - 1) / (R * tg);
+      const int64_t tgc = (c.groups + R * quads - 1) / (R * quads);
       const int64_t wc = std::min<int64_t>(c.warm_groups, (c.groups - 1) / tgc * tgc);
       const double item = (double)c.K * (double)(tgc + wc);
       total += (double)(quads * waves_per_item) * item;
@@ -67,23 +69,23 @@ int64_t batch_tile_groups(const std::vector<ChanWork> &w, int64_t simds, int64_t
 
 // The launch depends only on what the batch fixed at creation (grid, LDS,
 // instance); the live item count is read from the device header.
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER, int L>
 struct LaunchBatched {
   static sos_status run(const sos_batch_s &b, const void *x, void *y, hipStream_t s) {
     const int64_t blocks = (b.items_cap + kWavesPerBlock - 1) / kWavesPerBlock;
-    const unsigned lds = (unsigned)lds_bytes<N, TI, T>(b.kmax_cap);
-    hipLaunchKernelGGL((sos_rows_batched_kernel<N, TI, T, B0ONE, SOLVER>), dim3((unsigned)blocks),
+    const unsigned lds = (unsigned)lds_bytes<N, TI, T, L>(b.kmax_cap);
+    hipLaunchKernelGGL((sos_rows_batched_kernel<N, TI, T, B0ONE, SOLVER, L>), dim3((unsigned)blocks),
                        dim3(kWavesPerBlock * 64), lds, s, static_cast<const TI *>(x),
                        static_cast<TI *>(y), b.d_chans, b.d_item_chan, b.d_hdr, (int32_t)b.kmax_cap);
     return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
   }
 };
 
-template <int N, typename TI, typename T, bool B0ONE, int SOLVER>
+template <int N, typename TI, typename T, bool B0ONE, int SOLVER, int L>
 struct ResidencyBatched {
   static sos_status run(int kmax, Residency *r) {
-    *r = residency_of(reinterpret_cast<const void *>(&sos_rows_batched_kernel<N, TI, T, B0ONE, SOLVER>),
-                      (size_t)lds_bytes<N, TI, T>(kmax), kWavesPerBlock * 64);
+    *r = residency_of(reinterpret_cast<const void *>(&sos_rows_batched_kernel<N, TI, T, B0ONE, SOLVER, L>),
+                      (size_t)lds_bytes<N, TI, T, L>(kmax), kWavesPerBlock * 64);
     return SOS_OK;
   }
 };
@@ -112,7 +114,7 @@ sos_status validate(const sos_plan_t *plans, int32_t C, const int64_t *n, bool h
     // block filtering batches only with block filtering (its own kernel)
     if ((p->solver_opt == SOS_BLOCK) != (plans[0]->solver_opt == SOS_BLOCK)) return SOS_E_UNSUPPORTED;
     if (!host_only && p->solver_opt == SOS_BLOCK && (!p->d_block || !p->d_aop)) return SOS_E_ARG;
-    if (p->N != plans[0]->N || p->io_dtype != plans[0]->io_dtype ||
+    if (p->N != plans[0]->N || p->L != plans[0]->L || p->io_dtype != plans[0]->io_dtype ||
         p->compute_dtype != plans[0]->compute_dtype || p->block_slices != plans[0]->block_slices)
       return SOS_E_UNSUPPORTED;
   }
@@ -125,6 +127,7 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
                     const int64_t *offsets, int32_t tile_groups) {
   b.C = C;
   b.N = plans[0]->N;
+  b.L = plans[0]->L;
   b.io_dtype = plans[0]->io_dtype;
   b.compute_dtype = plans[0]->compute_dtype;
   b.n.assign(n, n + C);
@@ -159,7 +162,10 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   b.block = plans[0]->solver_opt == SOS_BLOCK;
   b.block_pt = plans[0]->block_pt;
   b.block_slices = plans[0]->block_slices;
-  const int64_t G = b.block ? (int64_t)kBlockGroup : (int64_t)b.N * kL;
+  const int64_t G = b.block ? (int64_t)kBlockGroup : (int64_t)b.N * b.L;
+  // tiles per work item: the rows of one wavefront, or (block filtering)
+  // the four wavefronts of a workgroup
+  const int64_t R = b.block ? 4 : 64 / b.L;
   for (int c = 0; c < C; ++c) b.total = std::max(b.total, b.off[c] + n[c]);
   // each channel's solver class: SOS_CR or SOS_PH when all its sections use
   // that solver, SOS_AUTO otherwise; the batch takes a specialised kernel
@@ -181,7 +187,7 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   if (!b.host_only && b.block)
     res = block_batched_residency(b.io_dtype, b.block_pt, b.block_slices, b.kmax);
   else if (!b.host_only)
-    dispatch_rows<ResidencyBatched>(b.N, b.io_dtype, b.compute_dtype, b.b0one, b.mix, b.kmax, &res);
+    dispatch_rows_l<ResidencyBatched>(b.N, b.L, b.io_dtype, b.compute_dtype, b.b0one, b.mix, b.kmax, &res);
   // a channel whose first sample is off a 16-byte boundary is filtered over
   // [-shift, n): the shift samples before it read as zeros (zero state stays
   // zero) and are not stored, and every group then starts on a boundary.
@@ -196,8 +202,8 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
   // an item is four row tiles in one wavefront, or (block filtering) four
   // tiles in the four wavefronts of a workgroup
   const int64_t tg = tile_groups > 0 ? tile_groups
-                                     : batch_tile_groups(work, res.simds, res.waves_per_simd, b.block ? 4 : 1);
-  // per-channel tiles: quads of four row tiles under the cap, as even as
+                                     : batch_tile_groups(work, res.simds, res.waves_per_simd, b.block ? 4 : 1, R);
+  // per-channel tiles: items of R row tiles under the cap, as even as
   // the length allows
   b.tile.assign(C, 0);
   std::vector<int64_t> quads(C, 0);
@@ -209,8 +215,8 @@ sos_status schedule(sos_batch_s &b, const sos_plan_t *plans, int32_t C, const in
       b.tile[c] = G;
       continue;
     }
-    quads[c] = (groups + 4 * tg - 1) / (4 * tg);
-    const int64_t tgc = (groups + 4 * quads[c] - 1) / (4 * quads[c]);
+    quads[c] = (groups + R * tg - 1) / (R * tg);
+    const int64_t tgc = (groups + R * quads[c] - 1) / (R * quads[c]);
     b.tile[c] = tgc * G;
     const int64_t warm = std::min<int64_t>(p->warm, (groups - 1) / tgc * tgc * G);
     cost[c] = (double)p->K * (double)(warm + b.tile[c]);
@@ -305,13 +311,14 @@ void point(sos_batch_s &b, const BlobLayout &l) {
 
 // Room for channel sets of up to C channels and `samples` samples in all:
 // tiles of at least one group give at most samples / (4 G) + 2 C work items
-// (a channel's span has at most n / G + 2 groups, in quads of four tiles),
+// (a channel's span has at most n / G + 2 groups, in items of R tiles),
 // and likewise for the adjoint's items.
 void reserve_room(sos_batch_s &b, int64_t C, int64_t samples, int kmax) {
-  const int64_t G = b.block ? std::min<int64_t>((int64_t)b.N * kL, kBlockGroup) : (int64_t)b.N * kL;
+  const int64_t G = b.block ? (int64_t)kBlockGroup : (int64_t)b.N * b.L;
+  const int64_t R = b.block ? 4 : 64 / b.L;
   const int64_t Gb = (int64_t)kBwdN * kL;
   b.C_cap = (int32_t)std::max<int64_t>(C, b.C);
-  b.items_cap = std::max<int64_t>(samples / (4 * G) + 2 * C + 1, b.items);
+  b.items_cap = std::max<int64_t>(samples / (R * G) + 2 * C + 1, b.items);
   b.adj_items_cap = std::max<int64_t>((samples + 3 * C) / (4 * Gb) + 2 * C + 1, b.adj ? (int64_t)b.adj_item_chan.size() : 0);
   b.kmax_cap = std::max(kmax, b.kmax);
   b.rows_cap = std::max<int64_t>(C * (int64_t)b.kmax_cap, b.adj ? (int64_t)b.adj_red.size() : 0);
@@ -427,7 +434,8 @@ sos_status sos_batch_replan(sos_batch_t b, const sos_plan_t *plans, int32_t C, c
   if (!b) return SOS_E_ARG;
   sos_status st = validate(plans, C, n, b->host_only);
   if (st != SOS_OK) return st;
-  if (plans[0]->N != b->N || plans[0]->io_dtype != b->io_dtype || plans[0]->compute_dtype != b->compute_dtype ||
+  if (plans[0]->N != b->N || plans[0]->L != b->L || plans[0]->io_dtype != b->io_dtype ||
+      plans[0]->compute_dtype != b->compute_dtype ||
       (plans[0]->solver_opt == SOS_BLOCK) != b->block || plans[0]->block_slices != b->block_slices)
     return SOS_E_UNSUPPORTED;
   // schedule into a copy, so that an invalid request leaves the batch as it was
@@ -517,15 +525,15 @@ sos_status sos_filt_batched(sos_batch_t b, const void *x, void *y, void *workspa
   if ((xb | yb) & 15) return SOS_E_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   if (b->block) return launch_block_batched(*b, x, y, s);
-  return dispatch_rows<LaunchBatched>(b->N, b->io_dtype, b->compute_dtype, b->inst_b0one, b->inst_mix, *b, x, y,
-                                      s);
+  return dispatch_rows_l<LaunchBatched>(b->N, b->L, b->io_dtype, b->compute_dtype, b->inst_b0one, b->inst_mix, *b,
+                                        x, y, s);
 }
 
 sos_status sos_batch_tune(const double *const *sos, const int32_t *K, int32_t C, const int64_t *n,
                           const int64_t *offsets, const sos_opts *base, const int32_t *Ns, int32_t nN,
-                          const int32_t *tiles, int32_t nt, const void *x, void *y, int32_t reps,
-                          sos_stream_t stream, sos_tune_result *results, sos_tune_result *best) {
-  if (!sos || !K || !n || !Ns || !tiles || nN < 1 || nt < 1 || reps < 1 || !best || C < 1)
+                          const int32_t *Ls, int32_t nL, const int32_t *tiles, int32_t nt, const void *x, void *y,
+                          int32_t reps, sos_stream_t stream, sos_tune_result *results, sos_tune_result *best) {
+  if (!sos || !K || !n || !Ns || !Ls || !tiles || nN < 1 || nL < 1 || nt < 1 || reps < 1 || !best || C < 1)
     return SOS_E_ARG;
   sos_opts o{SOS_F32, SOS_F64, SOS_AUTO, 0, 0, 0, 0};
   if (base) o = *base;
@@ -537,12 +545,15 @@ sos_status sos_batch_tune(const double *const *sos, const int32_t *K, int32_t C,
     return SOS_E_DEVICE;
   }
   best->N = 0;
+  best->L = 0;
   best->tile_groups = 0;
   best->seconds = 0.0;
   sos_status st = SOS_OK;
-  for (int iN = 0; iN < nN && st == SOS_OK; ++iN) {
+  for (int iNL = 0; iNL < nN * nL && st == SOS_OK; ++iNL) {
+    const int iN = iNL / nL, iL = iNL % nL;
     sos_opts on = o;
     on.N = Ns[iN];
+    on.L = Ls[iL];
     std::vector<sos_plan_t> plans(C, nullptr);
     for (int c = 0; c < C && st == SOS_OK; ++c) st = sos_plan(sos[c], K[c], &on, &plans[c]);
     for (int it = 0; it < nt && st == SOS_OK; ++it) {
@@ -566,8 +577,8 @@ sos_status sos_batch_tune(const double *const *sos, const int32_t *K, int32_t C,
       sos_batch_destroy(b);
       if (st != SOS_OK) break;
       const double sec = (double)ms * 1e-3 / reps;
-      if (results) results[iN * nt + it] = sos_tune_result{Ns[iN], tiles[it], sec};
-      if (best->N == 0 || sec < best->seconds) *best = sos_tune_result{Ns[iN], tiles[it], sec};
+      if (results) results[iNL * nt + it] = sos_tune_result{Ns[iN], Ls[iL], tiles[it], 0, sec};
+      if (best->N == 0 || sec < best->seconds) *best = sos_tune_result{Ns[iN], Ls[iL], tiles[it], 0, sec};
     }
     for (int c = 0; c < C; ++c) sos_plan_destroy(plans[c]);
   }

@@ -79,7 +79,8 @@ class _BatchOpts(ctypes.Structure):
 
 
 class _TuneResult(ctypes.Structure):
-    _fields_ = [("N", ctypes.c_int32), ("tile_groups", ctypes.c_int32), ("seconds", ctypes.c_double)]
+    _fields_ = [("N", ctypes.c_int32), ("L", ctypes.c_int32), ("tile_groups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -114,7 +115,7 @@ def lib():
         L.sos_filt_batched.argtypes = [vp, vp, vp, vp, vp]
         pi32 = ctypes.POINTER(ctypes.c_int32)
         L.sos_batch_tune.argtypes = [ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), pi32, i32, p64, p64,
-                                     ctypes.POINTER(_Opts), pi32, i32, pi32, i32, vp, vp, i32, vp,
+                                     ctypes.POINTER(_Opts), pi32, i32, pi32, i32, pi32, i32, vp, vp, i32, vp,
                                      ctypes.POINTER(_TuneResult), ctypes.POINTER(_TuneResult)]
         L.sos_backward_workspace_size.argtypes = [vp, i64]
         L.sos_backward_workspace_size.restype = ctypes.c_size_t
@@ -172,11 +173,11 @@ class Plan:
     recomputed)."""
 
     def __init__(self, sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=0,
-                 tile_groups=0, host_only=False, carry="auto", adjoint="auto", slices=0):
+                 tile_groups=0, host_only=False, carry="auto", adjoint="auto", slices=0, L=16):
         s = np.ascontiguousarray(np.asarray(sos, dtype=np.float64))
         if s.ndim != 2 or s.shape[1] != 6:
             raise ValueError("sos must be [K, 6]")
-        o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), 16,
+        o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], int(N), int(L),
                   int(tile_groups),
                   (SOS_FLAG_HOST_ONLY if host_only else 0) | _CARRY[carry] | _ADJOINT[adjoint]
                   | SOS_FLAG_SLICES(slices))
@@ -401,8 +402,8 @@ def filt_batched(batch: Batch, x, y=None, stream=None):
 
 
 def batch_tune(sos_list, lengths, x, y, offsets=None, io_dtype="f32", compute_dtype="f64",
-               solver="ph", Ns=(16, 32, 64), tiles=(0, 8, 16, 32), reps=3, stream=None):
-    """sos_batch_tune: the fastest (N, tile_groups) for this batch on the
+               solver="ph", Ns=(16, 32, 64), Ls=(16,), tiles=(0, 8, 16, 32), reps=3, stream=None):
+    """sos_batch_tune: the fastest (N, L, tile_groups) for this batch on the
     given device buffers.  Returns (best, rows) with rows one dict per
     candidate."""
     C = len(sos_list)
@@ -414,17 +415,19 @@ def batch_tune(sos_list, lengths, x, y, offsets=None, io_dtype="f32", compute_dt
     off = None if offsets is None else np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
     o = _Opts(_DTYPES[io_dtype], _DTYPES[compute_dtype], _SOLVERS[solver], 0, 16, 0, 0)
     Na = np.asarray(Ns, dtype=np.int32)
+    La = np.asarray(Ls, dtype=np.int32)
     Ta = np.asarray(tiles, dtype=np.int32)
-    res = (_TuneResult * (len(Na) * len(Ta)))()
+    res = (_TuneResult * (len(Na) * len(La) * len(Ta)))()
     best = _TuneResult()
     pi32 = ctypes.POINTER(ctypes.c_int32)
     _check(lib().sos_batch_tune(ptrs, K.ctypes.data_as(pi32), C, _i64p(n),
                                 _i64p(off) if off is not None else None, ctypes.byref(o),
-                                Na.ctypes.data_as(pi32), len(Na), Ta.ctypes.data_as(pi32), len(Ta),
+                                Na.ctypes.data_as(pi32), len(Na), La.ctypes.data_as(pi32), len(La),
+                                Ta.ctypes.data_as(pi32), len(Ta),
                                 ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), int(reps),
                                 _stream_ptr(stream), res, ctypes.byref(best)), "sos_batch_tune")
-    rows = [{"N": r.N, "tile_groups": r.tile_groups, "seconds": r.seconds} for r in res]
-    return {"N": best.N, "tile_groups": best.tile_groups, "seconds": best.seconds}, rows
+    rows = [{"N": r.N, "L": r.L, "tile_groups": r.tile_groups, "seconds": r.seconds} for r in res]
+    return {"N": best.N, "L": best.L, "tile_groups": best.tile_groups, "seconds": best.seconds}, rows
 
 
 def filt_backward(plan: Plan, x, gy, gx=None, stream=None):
