@@ -115,7 +115,10 @@ typedef struct {
     int32_t compute_dtype;  /* sos_dtype of the in-kernel arithmetic (default SOS_F64); SOS_F16
                                and SOS_BF16 only with SOS_BLOCK */
     int32_t solver;         /* sos_solver (default SOS_AUTO) */
-    int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32) */
+    int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32); also 128, 256, 512
+                               and 1024 for single signals with SOS_AUTO, SOS_PH or SOS_CR, FP64
+                               arithmetic and L = 16, whose lane runs (N doubles per lane) do not
+                               fit on chip and live in the workspace (sos_workspace_size) */
     int32_t L;              /* samples per block = lanes per group: 16 (a DPP row), 32 or 64
                                (the whole wavefront); 32 and 64 with SOS_AUTO, SOS_PH and
                                SOS_CR only (0 = 16) */
@@ -204,9 +207,11 @@ sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
                           double *out, int32_t count, int32_t *size);
 
 /*
- * Device workspace bytes sos_filt uses for n samples: 0 when it carries the
- * state between tiles by the run-in, else the size of the exact carry's
- * buffers.  The exact carry (FP64 arithmetic, solvers AUTO, PH or CR,
+ * Device workspace bytes sos_filt uses for n samples.  For N > 64: the lane
+ * runs of every wavefront of the launch (N x 64 doubles per wavefront, one
+ * wavefront per SIMD; 512 MB on MI355X at N = 1024), required.  Otherwise
+ * 0 when it carries the state between tiles by the run-in, else the size
+ * of the exact carry's buffers.  The exact carry (FP64 arithmetic, solvers AUTO, PH or CR,
  * K <= 16) runs every tile twice, once from zero section states to get its
  * end state c_t and once from the scanned true state, with a log-depth scan
  * S_t = c_t + Phi^T S_{t-1} in between (Phi the cascade's one-step state
@@ -228,7 +233,7 @@ size_t sos_workspace_size(sos_plan_t plan, int64_t n);
  * workspace  device, at least sos_workspace_size(plan, n) bytes, 16-byte
  *            aligned, contents on entry irrelevant; may be NULL, which keeps
  *            the run-in carry (SOS_E_ARG if the plan has SOS_FLAG_CARRY_SCAN
- *            and the size is not 0).
+ *            and the size is not 0, or N > 64).
  * stream     HIP stream the kernels are enqueued on.
  * No allocation and no synchronisation in either carry.
  */

@@ -98,4 +98,7 @@ inline int64_t model_tile_groups(int64_t groups, int64_t warm_groups, const Resi
   return std::max<int64_t>((groups + rows - 1) / rows, 1);
 }
 
+// residency of a wide plan's kernel (sosfilt_wide.hip)
+Residency wide_residency(const sos_plan_s &p);
+
 }  // namespace sosf

@@ -111,6 +111,11 @@ sos_status launch_carry(const sos_plan_s &p, const CarryLayout &l, const void *x
 }
 namespace sosf {
 sos_status check_filt_args(const sos_plan_s &p, const void *x, const void *y, int64_t n);
+// wide groups, N > 64 (sosfilt_wide.hip): the lane runs live in the caller's workspace
+bool wide_plan(const sos_plan_s &p);
+int64_t wide_tile(const sos_plan_s &p, int64_t n);
+size_t wide_workspace(const sos_plan_s &p, int64_t n);
+sos_status launch_wide(const sos_plan_s &p, const void *x, void *y, int64_t n, void *ws, hipStream_t s);
 }
 sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
                        sos_plan_t *out);

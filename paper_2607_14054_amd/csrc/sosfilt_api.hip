@@ -12,6 +12,7 @@
 #include "kernels_deferred.hpp"
 #include "kernels_scalar.hpp"
 #include "kernels_block.hpp"
+#include "kernels_wide.hpp"
 #include "plan.hpp"
 
 using namespace sosf;
@@ -277,7 +278,12 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   if (low && o.solver != SOS_BLOCK) return SOS_E_UNSUPPORTED;
   if (o.solver == SOS_BLOCK && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
   if (o.tile_groups < 0) return SOS_E_ARG;
-  if (!pow2_in(o.N, 8, 64) || !pow2_in(o.L, 16, 64)) return SOS_E_UNSUPPORTED;
+  if (!pow2_in(o.N, 8, kWideMaxN) || !pow2_in(o.L, 16, 64)) return SOS_E_UNSUPPORTED;
+  // N = 128 .. 1024: the lane runs live in the workspace (kernels_wide.hpp),
+  // for PH and CR with FP64 arithmetic and 16-lane rows
+  if (o.N > 64 && (o.L != kL || o.compute_dtype != SOS_F64 ||
+                   !(o.solver == SOS_AUTO || o.solver == SOS_PH || o.solver == SOS_CR)))
+    return SOS_E_UNSUPPORTED;
   // the block sizes L = 32, 64 exist for PH and CR (the other solvers work
   // on 16-lane rows or single lanes)
   if (o.L != kL && !(o.solver == SOS_AUTO || o.solver == SOS_PH || o.solver == SOS_CR)) return SOS_E_UNSUPPORTED;
@@ -337,6 +343,8 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
       st = upload_block_plan(*p);
       r.simds = p->simds;
       r.waves_per_simd = p->waves_per_simd;
+    } else if (st == SOS_OK && wide_plan(*p)) {
+      r = wide_residency(*p);
     } else if (st == SOS_OK)
       dispatch_rows_l<ResidencyRows>(p->N, p->L, p->io_dtype, p->compute_dtype, p->b0_factored, solver_mix(*p),
                                      p->K, &r);
@@ -436,11 +444,13 @@ int64_t sos_plan_tile(sos_plan_t p, int64_t n) {
   if (p->solver_opt == SOS_SCALAR)
     return p->tile_groups > 0 ? (int64_t)p->tile_groups * kScalarChunk : scalar_segment(*p, n);
   if (p->solver_opt == SOS_BLOCK) return block_tile(*p, n);
+  if (wide_plan(*p)) return wide_tile(*p, n);
   return choose_tile(*p, n);
 }
 
 size_t sos_workspace_size(sos_plan_t p, int64_t n) {
   if (!p || n <= 0) return 0;
+  if (wide_plan(*p)) return p->d_table ? wide_workspace(*p, n) : 0;
   return carry_layout(*p, n, choose_tile(*p, n)).bytes;
 }
 
@@ -463,6 +473,11 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
   const bool b0one = p->b0_factored;
   if (p->solver_opt == SOS_SCALAR) return launch_scalar(*p, x, y, n, s);
   if (p->solver_opt == SOS_BLOCK) return launch_block(*p, x, y, n, s);
+  if (wide_plan(*p)) {
+    // the lane runs of N > 64 live in the caller's workspace
+    if (!workspace || ((uintptr_t)workspace & 15)) return SOS_E_ARG;
+    return launch_wide(*p, x, y, n, workspace, s);
+  }
   if (p->solver_opt == SOS_PH_DEFERRED) {
     if (p->io_dtype == SOS_F32) return launch_deferred<float>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);
     return launch_deferred<double>(p->N, q, p->d_coupling, p->d_theta, a, b0one, s);

@@ -1,0 +1,96 @@
+// Wide groups (N = 128 .. 1024, kernels_wide.hpp): the plan's kernel
+// instance, its residency, the tiles and the workspace that holds the lane
+// runs, and the launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "dispatch.hpp"
+#include "kernels_wide.hpp"
+#include "plan.hpp"
+
+using namespace sosf;
+
+namespace {
+
+template <typename TI>
+const void *wide_kernel_t(bool b0one, int mix) {
+#define SOSF_W(B, S) reinterpret_cast<const void *>(&sos_rows_wide_kernel<TI, B, S>)
+  if (mix == SOS_PH) return b0one ? SOSF_W(true, SOS_PH) : SOSF_W(false, SOS_PH);
+  if (mix == SOS_CR) return b0one ? SOSF_W(true, SOS_CR) : SOSF_W(false, SOS_CR);
+  return b0one ? SOSF_W(true, SOS_AUTO) : SOSF_W(false, SOS_AUTO);
+#undef SOSF_W
+}
+
+int mix_of(const sos_plan_s &p) {
+  int mix = p.solver[0];
+  for (int k = 1; k < p.K; ++k)
+    if (p.solver[k] != mix) mix = SOS_AUTO;
+  return mix;
+}
+
+const void *wide_kernel(const sos_plan_s &p) {
+  return p.io_dtype == SOS_F32 ? wide_kernel_t<float>(p.b0_factored, mix_of(p))
+                               : wide_kernel_t<double>(p.b0_factored, mix_of(p));
+}
+
+size_t wide_lds(const sos_plan_s &p) {
+  return p.io_dtype == SOS_F32 ? (size_t)lds_bytes<kWideChunk, float, double>(p.K)
+                               : (size_t)lds_bytes<kWideChunk, double, double>(p.K);
+}
+
+}  // namespace
+
+namespace sosf {
+
+bool wide_plan(const sos_plan_s &p) { return p.N > 64; }
+
+Residency wide_residency(const sos_plan_s &p) {
+  return residency_of(wide_kernel(p), wide_lds(p), kWavesPerBlock * 64);
+}
+
+// Tiles of a wide plan: every SIMD gets one wavefront (four row tiles).  The
+// workspace holds N x 64 doubles per wavefront of the launch, so the launch
+// keeps to one wavefront per SIMD: at N = 1024 that is 512 KB per wavefront
+// and 512 MB for the whole device.
+int64_t wide_tile(const sos_plan_s &p, int64_t n) {
+  const int64_t G = (int64_t)p.N * kL;
+  if (p.tile_groups > 0) return (int64_t)p.tile_groups * G;
+  Residency r;
+  r.simds = p.simds;
+  r.waves_per_simd = 1;
+  return model_tile_groups((n + G - 1) / G, p.warm / G, r) * G;
+}
+
+size_t wide_workspace(const sos_plan_s &p, int64_t n) {
+  if (n <= 0) return 0;
+  const int64_t tile = wide_tile(p, n);
+  const int64_t ntiles = (n + tile - 1) / tile;
+  const int64_t waves = (ntiles + kRows - 1) / kRows;
+  return (size_t)waves * (size_t)p.N * 64 * sizeof(double);
+}
+
+sos_status launch_wide(const sos_plan_s &p, const void *x, void *y, int64_t n, void *ws, hipStream_t s) {
+  WideArgs a;
+  a.n = n;
+  a.K = p.K;
+  a.stride = p.stride;
+  a.N = p.N;
+  a.lgN = p.lgN;
+  a.tile = wide_tile(p, n);
+  a.warm = p.warm;
+  a.ntiles = (n + a.tile - 1) / a.tile;
+  a.gain = p.gain;
+  a.ws = static_cast<double *>(ws);
+  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
+  const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
+  const void *xa = x, *ta = p.d_table, *sa = p.d_solver;
+  void *ya = y;
+  void *args[] = {&xa, &ya, &ta, &sa, &a};   // addresses of the kernel's five arguments
+  if (hipLaunchKernel(wide_kernel(p), dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), args, wide_lds(p), s) !=
+      hipSuccess)
+    return SOS_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+}
+
+}  // namespace sosf

@@ -1,0 +1,135 @@
+"""GPU parity of wide groups, N = 128 .. 1024 blocks per lane run (the upper
+half of the paper's N sweep), whose lane runs live in the caller's
+workspace, against the FP64 oracle through the C ABI.  PH and cyclic
+reduction (log2 N = 7 .. 10 levels).  Bars as for N <= 64: FP64 in/out
+within 1e-12 relative RMS (or four times the FP64 oracle's own error
+against its extended-precision twin where that is larger), FP32 in/out
+within 1e-6.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_14054_amd import sosfilt as S
+from paper_2607_14054_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = "cuda:0"
+WIDE_N = [128, 256, 512, 1024]
+
+
+def filt(p, x_np):
+    y = S.filt(p, torch.from_numpy(x_np).to(DEV))
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def check(y, x, sos, io, what=""):
+    if io == "f32":
+        err = oracle.rel_rms(y, oracle.sosfilt(x, sos))
+        assert err < 1e-6, (what, err)
+        return err
+    ld = oracle.sosfilt_ld(x.astype(np.float64), sos)
+    err, own = oracle.rel_rms(y, ld), oracle.rel_rms(oracle.sosfilt(x, sos), ld)
+    assert err <= max(1e-12, 4 * own), (what, err, own)
+    return err
+
+
+@pytest.mark.parametrize("io", ["f64", "f32"])
+@pytest.mark.parametrize("N", WIDE_N)
+@pytest.mark.parametrize("solver", ["ph", "cr"])
+def test_wide_groups(solver, N, io):
+    """K = 8, r in [0.8, 0.98], several groups per tile plus a ragged tail."""
+    sos = W.make_sos(8, 0.8, 0.98, 930 + N)
+    dt = np.float64 if io == "f64" else np.float32
+    n = 9 * 16 * N + 4321
+    x = W.make_signal(n, 931, dt)
+    p = S.Plan(sos, io_dtype=io, compute_dtype="f64", solver=solver, N=N, tile_groups=2)
+    info = p.info()
+    assert info.N == N and p.workspace_size(n) > 0
+    check(filt(p, x), x, sos, io, "%s N=%d %s" % (solver, N, io))
+
+
+@pytest.mark.parametrize("N", WIDE_N)
+def test_wide_tiny_and_ragged(N):
+    """Lengths below one group and around group boundaries, K = 1 and 3."""
+    for K, n in ((1, 1), (3, 17), (3, 16 * N - 1), (1, 16 * N + 1), (3, 3 * 16 * N + 5)):
+        sos = W.make_sos(K, 0.5, 0.95, 932 + K)
+        x = W.make_signal(n, 933, np.float64)
+        p = S.Plan(sos, io_dtype="f64", compute_dtype="f64", solver="auto", N=N, tile_groups=1)
+        check(filt(p, x), x, sos, "f64", "N=%d K=%d n=%d" % (N, K, n))
+
+
+@pytest.mark.parametrize("solver", ["ph", "cr"])
+def test_wide_impulses_across_tiles(solver):
+    """Impulses one sample before and at group and tile boundaries, N = 256."""
+    N = 256
+    sos = W.make_sos(4, 0.9, 0.98, 934)
+    p = S.Plan(sos, io_dtype="f64", compute_dtype="f64", solver=solver, N=N, tile_groups=2)
+    n = 7 * 16 * N + 11
+    tile = p.tile(n)
+    x = np.zeros(n)
+    for pos in (16 * N - 1, 16 * N, tile - 1, tile, 2 * tile - 1, N - 1, N):
+        x[pos] = 1.0
+    check(filt(p, x), x, sos, "f64")
+
+
+def test_wide_cr_guard_routes_to_ph():
+    """The CR hazard angles at N = 1024 (ten levels): the guard sends those
+    sections to PH, the rest run CR, and the result is the oracle's."""
+    rows = []
+    for th in (np.pi / 2, np.pi / 4, np.pi / 8, 1.0, 2.0):
+        r = 0.9
+        rows.append([0.3, 0.1, 0.2, 1.0, -2 * r * np.cos(th), r * r])
+    sos = np.array(rows)
+    p = S.Plan(sos, io_dtype="f64", compute_dtype="f64", solver="cr", N=1024)
+    assert "ph" in p.info().solver and "cr" in p.info().solver
+    x = W.make_signal(5 * 16 * 1024 + 3, 935, np.float64)
+    check(filt(p, x), x, sos, "f64")
+
+
+def test_wide_needs_its_workspace():
+    """N > 64 without a workspace (or a misaligned one): SOS_E_ARG and no
+    launch; the static-scratch entry point refuses the size."""
+    p = S.Plan(W.make_sos(2, 0.5, 0.9, 936), io_dtype="f32", compute_dtype="f64", N=512)
+    n = 2 ** 24   # 2048 groups, 512 wavefronts of 256 KB
+    assert p.workspace_size(n) > S.SOS_STATIC_SCRATCH_BYTES
+    x = torch.zeros(n, dtype=torch.float32, device=DEV)
+    y = torch.full_like(x, 3.0)
+    vp = ctypes.c_void_p
+    assert S.lib().sos_filt(p.handle, vp(x.data_ptr()), vp(y.data_ptr()), n, None,
+                            S._stream_ptr(None)) == S.SOS_E_ARG
+    assert S.lib().sos_filt_static(p.handle, vp(x.data_ptr()), vp(y.data_ptr()), n,
+                                   S._stream_ptr(None)) == S.SOS_E_SCRATCH
+    torch.cuda.synchronize()
+    assert bool((y == 3.0).all())
+
+
+@pytest.mark.parametrize("solver", ["ph", "cr"])
+@pytest.mark.parametrize("N", [128, 1024])
+def test_wide_headline_full_size_sampled(N, solver):
+    """The full headline workload (2^28 float32 samples, K = 8, r in
+    [0.8, 0.98], seed 0) at N = 128 and 1024 in the launch shape the bench
+    sweep times, on windows at the start, across tile boundaries, in the
+    middle and at the end (each against the oracle run from four run-ins
+    before it)."""
+    c = W.CONFIGS["scale"]
+    sos = W.make_sos(c.K, c.r_lo, c.r_hi, c.seed)
+    x_np = W.make_signal(c.n, c.seed, np.float32)
+    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=solver, N=N)
+    tile, W_run = p.tile(c.n), p.info().warm_samples
+    x = torch.from_numpy(x_np).to(DEV)
+    y = S.filt(p, x)
+    torch.cuda.synchronize()
+    for start in (0, tile - 7, 100 * tile - 3, c.n // 2 + 123, c.n - 3000):
+        lo = max(0, start - 4 * W_run)
+        hi = min(start + 3000, c.n)
+        ref = oracle.sosfilt(x_np[lo:hi], sos)[start - lo:]
+        err = oracle.rel_rms(y[start:hi].cpu().numpy(), ref)
+        assert err < 1e-6, (N, solver, start, err)

@@ -65,7 +65,10 @@ def test_coefficient_validation(bad, code):
 
 @pytest.mark.parametrize("kw,code", [
     (dict(N=4), S.SOS_E_UNSUPPORTED), (dict(N=24), S.SOS_E_UNSUPPORTED),
-    (dict(N=128), S.SOS_E_UNSUPPORTED), (dict(io_dtype="f64", compute_dtype="f32"), S.SOS_E_UNSUPPORTED),
+    (dict(N=2048), S.SOS_E_UNSUPPORTED), (dict(io_dtype="f64", compute_dtype="f32"), S.SOS_E_UNSUPPORTED),
+    # wide groups (N > 64): FP64 arithmetic, 16-lane rows, PH or CR only
+    (dict(N=128, compute_dtype="f32"), S.SOS_E_UNSUPPORTED), (dict(N=256, L=32), S.SOS_E_UNSUPPORTED),
+    (dict(N=512, solver="scalar"), S.SOS_E_UNSUPPORTED),
 ])
 def test_option_validation(kw, code):
     with pytest.raises(S.SosError) as e:
@@ -394,3 +397,14 @@ def test_carry_flags():
     assert rc(0x40) == S.SOS_E_ARG
     p = S.Plan(W.make_sos(4, 0.9, 0.999, 1), host_only=True, carry="scan")
     assert p.workspace_size(1 << 20) == 0
+
+
+@pytest.mark.parametrize("N", [128, 256, 512, 1024])
+def test_wide_plan_tables(N):
+    """Wide groups build the same tables at their N: u closed forms up to
+    N, CR levels up to log2 N = 10 (the guard and flush included)."""
+    sos = W.make_sos(3, 0.5, 0.95, 7)
+    p = plan(sos, N=N, solver="cr")
+    assert p.info().N == N
+    assert p.table(S.SOS_TABLE_U1, 0).shape == (N,)
+    assert p.table(S.SOS_TABLE_CR_LEVELS, 0).shape == (4 * int(np.log2(N)),)
