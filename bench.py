@@ -43,22 +43,29 @@ def log(*a):
 
 
 def timed_filter(S, torch, plan, x, y, steps, warmup):
-    """Median-free total over `steps` back-to-back launches, HIP events on the
-    launch stream; returns seconds per step."""
+    """Seconds per step: `steps` back-to-back sos_filt launches between HIP
+    events on the launch stream, the plan's workspace (if it needs one)
+    allocated once beforehand."""
     stream = torch.cuda.current_stream()
+    ws = plan.workspace_size(x.numel())
+    wsb = torch.empty(ws, dtype=torch.uint8, device=x.device) if ws else None
+
+    def once():
+        _check_call(S, plan, x, y, wsb, stream)
+
     for _ in range(warmup):
-        S.filt(plan, x, y, stream=stream)
+        once()
     torch.cuda.synchronize()
     # bring the clocks up before the first timed configuration
     t_end = time.time() + 0.3
     while time.time() < t_end:
-        S.filt(plan, x, y, stream=stream)
+        once()
         torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
-        S.filt(plan, x, y, stream=stream)
+        once()
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3 / steps
@@ -95,9 +102,13 @@ def bench_batch(S, W, torch, dev, args):
     t = time.time()
     xb = torch.empty(total, dtype=torch.float32, device=dev)
     off = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    # the CPU leg's sample: every other channel, kept on the host as drawn
+    kept = {}
     for c in range(cfg.channels):
-        xb[off[c]:off[c] + lengths[c]] = torch.from_numpy(
-            W.make_signal(int(lengths[c]), cfg.seed + c, np.float32)).to(dev)
+        x_c = W.make_signal(int(lengths[c]), cfg.seed + c, np.float32)
+        xb[off[c]:off[c] + lengths[c]] = torch.from_numpy(x_c).to(dev)
+        if not args.no_cpu and c % 2 == 0:
+            kept[c] = x_c
     yb = torch.empty_like(xb)
     log("batch: %d channels, %d samples, generated in %.1f s" % (cfg.channels, total, time.time() - t))
     t = time.time()
@@ -137,16 +148,35 @@ def bench_batch(S, W, torch, dev, args):
            "frac_hbm": 8.0 * total / sec / 1e9 / HBM_PEAK_GBS, "tune": rows}
     if not args.no_cpu:
         import oracle
-        pick = np.unique(np.concatenate([np.argsort(lengths)[[0, -1]], np.arange(0, cfg.channels, 512)]))
-        worst = 0.0
-        for c in pick:
-            x_c = W.make_signal(int(lengths[c]), cfg.seed + c, np.float32)
-            ref = oracle.sosfilt(x_c, sos[c])
+        # the oracle on the host's cores, one thread per channel at a time
+        # (channels are independent), on every other channel of the batch
+        cpu = host_cpu()
+        threads = max(1, min(16, cpu["available"]))
+        chans = sorted(kept)
+        t = time.time()
+        refs = oracle.sosfilt_batch([kept[c] for c in chans], [sos[c] for c in chans], threads=threads)
+        tc = time.time() - t
+        m = int(sum(lengths[c] for c in chans))
+        out["cpu_baseline"] = {"value": m / tc / 1e9, "unit": "GS/s", "cores": threads, "kind": "oracle",
+                               "sample": "every other channel of the batch (%d channels, %d samples), FP64 "
+                                         "direct form I, one host thread per channel" % (len(chans), m),
+                               "nproc": cpu["nproc"], "cpu_model": cpu["cpu_model"]}
+        log("batch oracle: %d channels, %d samples on %d threads in %.2f s (%.2f GS/s)"
+            % (len(chans), m, threads, tc, m / tc / 1e9))
+        # every channel of that sample against the oracle, element by element
+        errs = np.empty(len(chans))
+        for i, c in enumerate(chans):
             got = yb[off[c]:off[c] + lengths[c]].cpu().numpy()
-            worst = max(worst, oracle.rel_rms(got, ref))
-        out["rel_rms_max_sampled"] = worst
-        out["checked_channels"] = [int(c) for c in pick]
-        log("batch: worst rel_rms over %d sampled channels %.3e" % (len(pick), worst))
+            errs[i] = oracle.rel_rms(got, refs[i])
+            refs[i] = None
+        worst = int(np.argmax(errs))
+        out["rel_rms_max_sampled"] = float(errs.max())
+        out["rel_rms_median_sampled"] = float(np.median(errs))
+        out["checked_channels"] = len(chans)
+        out["worst_channel"] = int(chans[worst])
+        log("batch: rel_rms over %d channels median %.3e max %.3e (channel %d)"
+            % (len(chans), out["rel_rms_median_sampled"], errs.max(), chans[worst]))
+        del refs, kept
     del xb, yb
     torch.cuda.empty_cache()
     return out
@@ -162,7 +192,9 @@ def forms_summary(extra, plain_gsps):
         "batched": {"workload": "4096 channels, lengths log-uniform in [2^10, 2^22] float32, K ~ U{1..16}, "
                                 "r U[0.5,0.95]; one graph-replayed launch, autotuned",
                     "GSps": b["GSps"], "vs_plain": b["GSps"] / plain_gsps, "N": b["N"], "L": b.get("L"),
-                    "rel_rms_max": b.get("rel_rms_max_sampled")},
+                    "rel_rms_max": b.get("rel_rms_max_sampled"),
+                    "checked_channels": b.get("checked_channels"),
+                    "cpu_baseline": b.get("cpu_baseline")},
         "adjoint": {"workload": "64 x 2^18 float32, K=8, r U[0.5,0.95]; training step: batched forward that "
                                 "fills the adjoint's workspace, then the batched adjoint from it",
                     "GSps": g["GSps"], "vs_plain": g["GSps"] / plain_gsps,
@@ -215,6 +247,75 @@ def measured_traffic(N, solver_opt, solvers, n):
             or t.get("solvers") != solvers or t.get("n") != n):
         return None
     return t.get("bytes_per_launch")
+
+
+def host_cpu():
+    """The host's logical CPU count, the CPUs this process may run on, and
+    the CPU model name."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "available": avail, "cpu_model": model}
+
+
+SWEEP_NS = (8, 16, 32, 64, 128, 256, 512, 1024)
+
+
+def bench_sweep(S, torch, sos, x, y, n, steps, ref_dev, full):
+    """PH and CR at every N of the paper's sweep (8 .. 1024 blocks per lane
+    run, L = 16) and at L = 32 and 64 for N <= 64, on the headline signal
+    with FP64 arithmetic.  Each point: time per launch, GS/s, its fraction
+    of HBM and of the FP64 vector roofline, and (when the oracle's output is
+    given) its relative RMS error against the oracle over the whole signal.
+    With `full`, also FP32 arithmetic, the deferred-correction PH and the
+    scalar and block-filtering variants."""
+    cases = [(s_, NN, 16, "f64") for s_ in ("ph", "cr") for NN in SWEEP_NS]
+    cases += [(s_, NN, L, "f64") for s_ in ("ph", "cr") for L in (32, 64) for NN in (8, 16, 32, 64)]
+    if full:
+        cases += [(s_, NN, 16, "f32") for s_ in ("ph", "cr") for NN in (8, 16, 32, 64)]
+        cases += [("phd", NN, 16, "f64") for NN in (16, 32, 64)]
+        # comparison points: scalar filtering, block filtering (Toeplitz on MFMA)
+        cases += [("scalar", 64, 16, "f64"), ("scalar", 64, 16, "f32"), ("block", 64, 16, "f64"),
+                  ("block", 64, 16, "f16"), ("block", 64, 16, "bf16")]
+    rows = []
+    for solver, NN, L, cd in cases:
+        p2 = S.Plan(sos, io_dtype="f32", compute_dtype=cd, solver=solver, N=NN, L=L)
+        y.fill_(float("nan"))
+        s2 = timed_filter(S, torch, p2, x, y, steps, 2)
+        i2 = p2.info()
+        gbs = 8.0 * n / s2 / 1e9
+        row = {"solver": solver, "solvers": sorted(set(i2.solver)), "N": NN, "L": L, "compute": cd,
+               "tile": p2.tile(n), "waves_per_simd": i2.waves_per_simd, "ms": s2 * 1e3, "GSps": n / s2 / 1e9,
+               "frac_hbm": gbs / HBM_PEAK_GBS}
+        if cd == "f64" and solver in ("ph", "cr"):
+            fma = algorithmic_fma_per_sample(i2.solver, NN, L)
+            row["frac_fp64_alu"] = 2.0 * fma * n / s2 / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+        if ref_dev is not None:
+            d = y.double() - ref_dev
+            row["rel_rms"] = float(torch.sqrt((d * d).sum() / (ref_dev * ref_dev).sum()))
+            del d
+        rows.append(row)
+        log("sweep %-6s N=%4d L=%2d %s: tile=%d occ=%d %.3f ms %.1f GS/s  frac_hbm %.3f%s"
+            % (solver, NN, L, cd, row["tile"], i2.waves_per_simd, s2 * 1e3, row["GSps"], row["frac_hbm"],
+               "  rel_rms %.2e" % row["rel_rms"] if "rel_rms" in row else ""))
+    return rows
+
+
+def sweep_summary(rows):
+    """The sweep's points in the bench line: solver, N, L, GS/s, HBM and
+    FP64-ALU fractions and error against the oracle."""
+    keep = ("solver", "N", "L", "compute", "GSps", "frac_hbm", "frac_fp64_alu", "rel_rms")
+    return [{k: r[k] for k in keep if k in r} for r in rows]
 
 
 def bench_grad(S, W, torch, dev, args):
@@ -506,10 +607,11 @@ def bench_carry(S, W, torch, dev, args):
     return out
 
 
-def _check_call(S, plan, x, y, wsb):
+def _check_call(S, plan, x, y, wsb, stream=None):
     import ctypes
     rc = S.lib().sos_filt(plan.handle, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.numel(),
-                          ctypes.c_void_p(wsb.data_ptr()) if wsb is not None else None, None)
+                          ctypes.c_void_p(wsb.data_ptr()) if wsb is not None else None,
+                          S._stream_ptr(stream) if stream is not None else None)
     if rc != 0:
         raise RuntimeError("sos_filt: status %d" % rc)
 
@@ -602,7 +704,11 @@ def main():
     ap.add_argument("--N", type=int, default=0)
     ap.add_argument("--tile", type=int, default=0, help="groups per tile (0: the library's choice)")
     ap.add_argument("--tile-sweep", action="store_true", help="time the main plan at several tile sizes")
-    ap.add_argument("--sweep", action="store_true", help="also time PH and CR at every N")
+    ap.add_argument("--sweep", action="store_true",
+                    help="widen the N sweep with FP32 arithmetic, the deferred PH and the scalar and block "
+                         "variants")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the sweep of PH and CR over N = 8 .. 1024 (and L = 32, 64)")
     ap.add_argument("--batch", action="store_true",
                     help="also time the batched ragged workload (4096 channels), autotuned, graph-replayed")
     ap.add_argument("--grad", action="store_true",
@@ -619,8 +725,8 @@ def main():
                     help="also the small FP64 workload's latency")
     ap.add_argument("--carry", action="store_true",
                     help="also the run-in against the exact scan carry on long-run-in single signals")
-    ap.add_argument("--draws", action="store_true",
-                    help="also the kernel's and the FP32 floor's error over 16 coefficient draws")
+    ap.add_argument("--no-draws", action="store_true",
+                    help="skip the kernel's and the FP32 floor's error over 16 coefficient draws")
     ap.add_argument("--no-cpu", action="store_true",
                     help="skip the CPU leg: the oracle's timing and every accuracy check that runs the oracle")
     ap.add_argument("--no-forms", action="store_true",
@@ -677,6 +783,45 @@ def main():
     extra["copy_GBps"] = copy_gbs
     log("copy ceiling: %.0f GB/s" % copy_gbs)
 
+    # the CPU leg: the oracle's time on the headline signal (one channel: the
+    # recursion is sequential, one thread) and the headline's error
+    cpu = None
+    comparator = None
+    accuracy = {}
+    ref_dev = None
+    if not args.no_cpu:
+        import oracle
+        hc = host_cpu()
+        t = time.time()
+        ref = oracle.sosfilt(x_np, sos)
+        tc = time.time() - t
+        cpu = {"value": n / tc / 1e9, "unit": "GS/s", "cores": 1, "kind": "oracle",
+               "sample": "the full 2^%d-sample signal, FP64 direct form I, one thread" % args.log2n,
+               "nproc": hc["nproc"], "cpu_model": hc["cpu_model"]}
+        accuracy["rel_rms"] = oracle.rel_rms(y_np, ref)
+        accuracy["max_rel"] = oracle.max_rel(y_np, ref)
+        # the FP32 floor: a plain sequential FP32 cascade on the same draw
+        accuracy["fp32_floor_rel_rms"] = oracle.rel_rms(oracle.sosfilt_f32arith(x_np, sos), ref)
+        log("oracle: %.2f s (%.1f MS/s); rel_rms=%.3e max_rel=%.3e; FP32 floor %.3e"
+            % (tc, n / tc / 1e6, accuracy["rel_rms"], accuracy["max_rel"], accuracy["fp32_floor_rel_rms"]))
+        ref_dev = torch.from_numpy(ref).to(dev)
+        del ref
+        # the paper's CPU comparator, scipy.signal.sosfilt in FP64 on one
+        # thread, timed on the first 2^26 samples
+        try:
+            import scipy.signal as ss
+            m = min(n, 1 << 26)
+            x64 = x_np[:m].astype(np.float64)
+            t = time.time()
+            ss.sosfilt(np.asarray(sos, dtype=np.float64), x64)
+            tc = time.time() - t
+            comparator = {"kind": "scipy.signal.sosfilt", "value": m / tc / 1e9, "unit": "GS/s", "cores": 1,
+                          "sample": "the first 2^%d samples as FP64" % (m.bit_length() - 1)}
+            log("scipy.signal.sosfilt: %.2f s for %d samples (%.1f MS/s)" % (tc, m, m / tc / 1e6))
+        except ImportError:
+            comparator = None
+    del y_np
+
     if args.tile_sweep:
         rows = []
         for solver, NN in (("ph", 32), ("ph", 64), ("cr", 64), ("ph", 16)):
@@ -688,24 +833,12 @@ def main():
                 log("tile %s N=%2d tile_groups=%3d: %.3f ms %.1f GS/s" % (solver, NN, tg, s2 * 1e3, n / s2 / 1e9))
         extra["tile_sweep"] = rows
 
-    if args.sweep:
-        rows = []
-        cases = [(s_, NN, cd) for s_ in ("ph", "cr", "phd") for NN in (8, 16, 32, 64)
-                 for cd in ("f64", "f32") if not (s_ == "phd" and (NN < 16 or cd == "f32"))]
-        # comparison points: scalar filtering, block filtering (Toeplitz on MFMA)
-        cases += [("scalar", 64, "f64"), ("scalar", 64, "f32"), ("block", 64, "f64"),
-                  ("block", 64, "f16"), ("block", 64, "bf16")]
-        for solver, NN, cd in cases:
-            p2 = S.Plan(sos, io_dtype="f32", compute_dtype=cd, solver=solver, N=NN)
-            s2 = timed_filter(S, torch, p2, x, y, max(3, args.steps // 2), 2)
-            i2 = p2.info()
-            rows.append({"solver": solver, "N": NN, "compute": cd, "tile": p2.tile(n),
-                         "waves_per_simd": i2.waves_per_simd,
-                         "ms": s2 * 1e3, "GSps": n / s2 / 1e9,
-                         "frac_hbm": 8.0 * n / s2 / 1e9 / HBM_PEAK_GBS})
-            log("sweep %s N=%2d %s: tile=%d samples occ=%d %.3f ms %.1f GS/s"
-                % (solver, NN, cd, p2.tile(n), i2.waves_per_simd, s2 * 1e3, n / s2 / 1e9))
-        extra["sweep"] = rows
+    # PH and CR over the paper's N sweep (and L = 32, 64), run by default
+    sweep = None
+    if not args.no_sweep:
+        sweep = bench_sweep(S, torch, sos, x, y, n, max(3, args.steps // 4), ref_dev, args.sweep)
+        extra["sweep"] = sweep
+    del ref_dev
 
     # the forms the metric reports beside the plain one, run by default
     forms = not args.no_forms and not args.copy_only
@@ -724,45 +857,16 @@ def main():
         extra["stream"] = bench_stream(S, W, torch, dev, args)
     if args.precision:
         extra["precision"] = bench_precision(S, W, torch, dev, args)
-    if args.draws and not args.no_cpu:   # an accuracy-only leg: part of the CPU leg
+    if not args.no_cpu and not args.no_draws:   # an accuracy-only leg: part of the CPU leg
         extra["draws"] = bench_draws(S, W, torch, dev, args)
+        d = extra["draws"]
+        accuracy["draws"] = {"n": d["n"], "count": len(d["draws"]), "rel_rms_median": d["rel_rms_median"],
+                             "rel_rms_max": d["rel_rms_max"], "fp32_floor_median": d["fp32_floor_median"],
+                             "fp32_floor_max": d["fp32_floor_max"]}
     if args.carry:
         extra["carry"] = bench_carry(S, W, torch, dev, args)
     if args.tiny:
         extra["tiny"] = bench_tiny(S, W, torch, dev, args)
-
-    cpu = None
-    comparator = None
-    accuracy = {}
-    if not args.no_cpu:
-        import oracle
-        threads = 1
-        t = time.time()
-        ref = oracle.sosfilt(x_np, sos)
-        tc = time.time() - t
-        cpu = {"value": n / tc / 1e9, "unit": "GS/s", "cores": threads, "kind": "oracle",
-               "sample": "the full 2^28-sample signal, FP64 direct form I, one thread"}
-        accuracy["rel_rms"] = oracle.rel_rms(y_np, ref)
-        accuracy["max_rel"] = oracle.max_rel(y_np, ref)
-        # the FP32 floor: a plain sequential FP32 cascade on the same draw
-        accuracy["fp32_floor_rel_rms"] = oracle.rel_rms(oracle.sosfilt_f32arith(x_np, sos), ref)
-        log("oracle: %.2f s (%.1f MS/s); rel_rms=%.3e max_rel=%.3e; FP32 floor %.3e"
-            % (tc, n / tc / 1e6, accuracy["rel_rms"], accuracy["max_rel"], accuracy["fp32_floor_rel_rms"]))
-        del ref
-        # the paper's CPU comparator, scipy.signal.sosfilt in FP64 on one
-        # thread, timed on the first 2^26 samples
-        try:
-            import scipy.signal as ss
-            m = min(n, 1 << 26)
-            x64 = x_np[:m].astype(np.float64)
-            t = time.time()
-            ss.sosfilt(np.asarray(sos, dtype=np.float64), x64)
-            tc = time.time() - t
-            comparator = {"kind": "scipy.signal.sosfilt", "value": m / tc / 1e9, "unit": "GS/s", "cores": 1,
-                          "sample": "the first 2^%d samples as FP64" % (m.bit_length() - 1)}
-            log("scipy.signal.sosfilt: %.2f s for %d samples (%.1f MS/s)" % (tc, m, m / tc / 1e6))
-        except ImportError:
-            comparator = None
 
     line = {
         "metric": "GS/s filtered (K=8, FP32) + % HBM roofline; forms vs plain at <=1e-4 rel RMS",
@@ -790,6 +894,8 @@ def main():
         "cpu_comparator": comparator,
         "accuracy": accuracy,
     }
+    if sweep is not None:
+        line["sweep"] = sweep_summary(sweep)
     if forms:
         line["forms"] = forms_summary(extra, gsps)
     print(json.dumps(line), flush=True)
