@@ -117,8 +117,10 @@ typedef struct {
     int32_t solver;         /* sos_solver (default SOS_AUTO) */
     int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32); also 128, 256, 512
                                and 1024 for single signals with SOS_AUTO, SOS_PH or SOS_CR, FP64
-                               arithmetic and L = 16, whose lane runs (N doubles per lane) do not
-                               fit on chip and live in the workspace (sos_workspace_size) */
+                               arithmetic and L = 16.  At N = 128 with FP32 I/O a lane's run
+                               (128 doubles) stays in registers, one wavefront per SIMD; the
+                               other wide runs do not fit on chip and live in the workspace
+                               (sos_workspace_size) */
     int32_t L;              /* samples per block = lanes per group: 16 (a DPP row), 32 or 64
                                (the whole wavefront); 32 and 64 with SOS_AUTO, SOS_PH and
                                SOS_CR only (0 = 16) */
@@ -207,9 +209,10 @@ sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
                           double *out, int32_t count, int32_t *size);
 
 /*
- * Device workspace bytes sos_filt uses for n samples.  For N > 64: the lane
- * runs of every wavefront of the launch (N x 64 doubles per wavefront, one
- * wavefront per SIMD; 512 MB on MI355X at N = 1024), required.  Otherwise
+ * Device workspace bytes sos_filt uses for n samples.  For N = 256 .. 1024,
+ * and N = 128 with FP64 I/O: the lane runs of every wavefront of the launch
+ * (N x 64 doubles per wavefront, one wavefront per SIMD; 512 MB on MI355X
+ * at N = 1024), required.  N = 128 with FP32 I/O needs none.  Otherwise
  * 0 when it carries the state between tiles by the run-in, else the size
  * of the exact carry's buffers.  The exact carry (FP64 arithmetic, solvers AUTO, PH or CR,
  * K <= 16) runs every tile twice, once from zero section states to get its
@@ -232,8 +235,8 @@ size_t sos_workspace_size(sos_plan_t plan, int64_t n);
  *            zero-padded and only n outputs are written.
  * workspace  device, at least sos_workspace_size(plan, n) bytes, 16-byte
  *            aligned, contents on entry irrelevant; may be NULL, which keeps
- *            the run-in carry (SOS_E_ARG if the plan has SOS_FLAG_CARRY_SCAN
- *            and the size is not 0, or N > 64).
+ *            the run-in carry (SOS_E_ARG if the size is not 0 and the plan
+ *            has SOS_FLAG_CARRY_SCAN or N > 64).
  * stream     HIP stream the kernels are enqueued on.
  * No allocation and no synchronisation in either carry.
  */

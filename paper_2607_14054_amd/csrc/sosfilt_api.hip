@@ -474,8 +474,8 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
   if (p->solver_opt == SOS_SCALAR) return launch_scalar(*p, x, y, n, s);
   if (p->solver_opt == SOS_BLOCK) return launch_block(*p, x, y, n, s);
   if (wide_plan(*p)) {
-    // the lane runs of N > 64 live in the caller's workspace
-    if (!workspace || ((uintptr_t)workspace & 15)) return SOS_E_ARG;
+    // the lane runs of N = 256 .. 1024 live in the caller's workspace
+    if (wide_workspace(*p, n) > 0 && (!workspace || ((uintptr_t)workspace & 15))) return SOS_E_ARG;
     return launch_wide(*p, x, y, n, workspace, s);
   }
   if (p->solver_opt == SOS_PH_DEFERRED) {

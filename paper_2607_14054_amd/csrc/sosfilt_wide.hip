@@ -1,6 +1,10 @@
-// Wide groups (N = 128 .. 1024, kernels_wide.hpp): the plan's kernel
-// instance, its residency, the tiles and the workspace that holds the lane
-// runs, and the launch.
+// Wide groups (N = 128 .. 1024): the plan's kernel instance, its residency,
+// the tiles and the workspace that holds the lane runs, and the launch.
+// At N = 128 a lane's run (128 doubles) still fits in one wavefront's
+// registers when the wavefront has its SIMD to itself (256 architectural
+// plus 256 accumulation registers), so with FP32 I/O that width runs the
+// register tile kernel of kernels.hpp; the other wide plans keep the runs in
+// the workspace (kernels_wide.hpp).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,9 +17,21 @@ using namespace sosf;
 
 namespace {
 
+constexpr int kRegN = 128;   // the widest run kept in registers
+
+constexpr size_t kLdsPerCu = 160 * 1024;
+
+// FP32 I/O only: the four wavefronts' staging of a 128-block group in FP64
+// would take 266 KB of LDS
+bool in_registers(const sos_plan_s &p) {
+  return p.N == kRegN && p.io_dtype == SOS_F32 && (size_t)lds_bytes<kRegN, float, double>(p.K) <= kLdsPerCu;
+}
+
 template <typename TI>
-const void *wide_kernel_t(bool b0one, int mix) {
-#define SOSF_W(B, S) reinterpret_cast<const void *>(&sos_rows_wide_kernel<TI, B, S>)
+const void *wide_kernel_t(bool regs, bool b0one, int mix) {
+#define SOSF_W(B, S)                                                                               \
+  (regs ? reinterpret_cast<const void *>(&sos_rows_kernel<kRegN, TI, double, B, S, kL>)            \
+        : reinterpret_cast<const void *>(&sos_rows_wide_kernel<TI, B, S>))
   if (mix == SOS_PH) return b0one ? SOSF_W(true, SOS_PH) : SOSF_W(false, SOS_PH);
   if (mix == SOS_CR) return b0one ? SOSF_W(true, SOS_CR) : SOSF_W(false, SOS_CR);
   return b0one ? SOSF_W(true, SOS_AUTO) : SOSF_W(false, SOS_AUTO);
@@ -30,11 +46,14 @@ int mix_of(const sos_plan_s &p) {
 }
 
 const void *wide_kernel(const sos_plan_s &p) {
-  return p.io_dtype == SOS_F32 ? wide_kernel_t<float>(p.b0_factored, mix_of(p))
-                               : wide_kernel_t<double>(p.b0_factored, mix_of(p));
+  return p.io_dtype == SOS_F32 ? wide_kernel_t<float>(in_registers(p), p.b0_factored, mix_of(p))
+                               : wide_kernel_t<double>(in_registers(p), p.b0_factored, mix_of(p));
 }
 
 size_t wide_lds(const sos_plan_s &p) {
+  if (in_registers(p))
+    return p.io_dtype == SOS_F32 ? (size_t)lds_bytes<kRegN, float, double>(p.K)
+                                 : (size_t)lds_bytes<kRegN, double, double>(p.K);
   return p.io_dtype == SOS_F32 ? (size_t)lds_bytes<kWideChunk, float, double>(p.K)
                                : (size_t)lds_bytes<kWideChunk, double, double>(p.K);
 }
@@ -63,7 +82,7 @@ int64_t wide_tile(const sos_plan_s &p, int64_t n) {
 }
 
 size_t wide_workspace(const sos_plan_s &p, int64_t n) {
-  if (n <= 0) return 0;
+  if (n <= 0 || in_registers(p)) return 0;
   const int64_t tile = wide_tile(p, n);
   const int64_t ntiles = (n + tile - 1) / tile;
   const int64_t waves = (ntiles + kRows - 1) / kRows;
@@ -71,6 +90,25 @@ size_t wide_workspace(const sos_plan_s &p, int64_t n) {
 }
 
 sos_status launch_wide(const sos_plan_s &p, const void *x, void *y, int64_t n, void *ws, hipStream_t s) {
+  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
+  const void *xa = x, *ta = p.d_table, *sa = p.d_solver;
+  void *ya = y;
+  if (in_registers(p)) {
+    FiltArgs f;
+    f.n = n;
+    f.K = p.K;
+    f.stride = p.stride;
+    f.tile = wide_tile(p, n);
+    f.warm = p.warm;
+    f.ntiles = (n + f.tile - 1) / f.tile;
+    f.gain = p.gain;
+    const int64_t blocks = (f.ntiles + per_block - 1) / per_block;
+    void *args[] = {&xa, &ya, &ta, &sa, &f};   // addresses of the kernel's five arguments
+    if (hipLaunchKernel(wide_kernel(p), dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), args, wide_lds(p),
+                        s) != hipSuccess)
+      return SOS_E_DEVICE;
+    return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+  }
   WideArgs a;
   a.n = n;
   a.K = p.K;
@@ -82,10 +120,7 @@ sos_status launch_wide(const sos_plan_s &p, const void *x, void *y, int64_t n, v
   a.ntiles = (n + a.tile - 1) / a.tile;
   a.gain = p.gain;
   a.ws = static_cast<double *>(ws);
-  const int64_t per_block = (int64_t)kWavesPerBlock * kRows;
   const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
-  const void *xa = x, *ta = p.d_table, *sa = p.d_solver;
-  void *ya = y;
   void *args[] = {&xa, &ya, &ta, &sa, &a};   // addresses of the kernel's five arguments
   if (hipLaunchKernel(wide_kernel(p), dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), args, wide_lds(p), s) !=
       hipSuccess)

@@ -1,6 +1,7 @@
 """GPU parity of wide groups, N = 128 .. 1024 blocks per lane run (the upper
-half of the paper's N sweep), whose lane runs live in the caller's
-workspace, against the FP64 oracle through the C ABI.  PH and cyclic
+half of the paper's N sweep), against the FP64 oracle through the C ABI.
+N = 128 with FP32 I/O keeps a lane's run in registers (a wavefront alone
+on its SIMD); the other wide plans keep the runs in the caller's workspace.  PH and cyclic
 reduction (log2 N = 7 .. 10 levels).  Bars as for N <= 64: FP64 in/out
 within 1e-12 relative RMS (or four times the FP64 oracle's own error
 against its extended-precision twin where that is larger), FP32 in/out
@@ -52,7 +53,9 @@ def test_wide_groups(solver, N, io):
     x = W.make_signal(n, 931, dt)
     p = S.Plan(sos, io_dtype=io, compute_dtype="f64", solver=solver, N=N, tile_groups=2)
     info = p.info()
-    assert info.N == N and p.workspace_size(n) > 0
+    # N = 128 with FP32 I/O keeps its lane runs in registers, the other wide
+    # plans keep them in the workspace
+    assert info.N == N and (p.workspace_size(n) > 0) == (N > 128 or io == "f64")
     check(filt(p, x), x, sos, io, "%s N=%d %s" % (solver, N, io))
 
 
