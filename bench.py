@@ -268,12 +268,13 @@ def host_cpu():
     return {"nproc": os.cpu_count(), "available": avail, "cpu_model": model}
 
 
-SWEEP_NS = (8, 16, 32, 64, 128, 256, 512, 1024)
+SWEEP_NS = (4, 8, 16, 32, 64, 128, 256, 512, 1024)
 
 
 def bench_sweep(S, torch, sos, x, y, n, steps, ref_dev, full):
     """PH and CR at every N of the paper's sweep (8 .. 1024 blocks per lane
-    run, L = 16) and at L = 32 and 64 for N <= 64, on the headline signal
+    run, and the narrowest width, 4; L = 16) and at L = 32 and 64 for
+    8 <= N <= 64, on the headline signal
     with FP64 arithmetic.  Each point: time per launch, GS/s, its fraction
     of HBM and of the FP64 vector roofline, and (when the oracle's output is
     given) its relative RMS error against the oracle over the whole signal.
@@ -708,7 +709,7 @@ def main():
                     help="widen the N sweep with FP32 arithmetic, the deferred PH and the scalar and block "
                          "variants")
     ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the sweep of PH and CR over N = 8 .. 1024 (and L = 32, 64)")
+                    help="skip the sweep of PH and CR over N = 4 .. 1024 (and L = 32, 64)")
     ap.add_argument("--batch", action="store_true",
                     help="also time the batched ragged workload (4096 channels), autotuned, graph-replayed")
     ap.add_argument("--grad", action="store_true",

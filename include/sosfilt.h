@@ -115,8 +115,9 @@ typedef struct {
     int32_t compute_dtype;  /* sos_dtype of the in-kernel arithmetic (default SOS_F64); SOS_F16
                                and SOS_BF16 only with SOS_BLOCK */
     int32_t solver;         /* sos_solver (default SOS_AUTO) */
-    int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32); also 128, 256, 512
-                               and 1024 for single signals with SOS_AUTO, SOS_PH or SOS_CR, FP64
+    int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32); also 4 for single
+                               signals with SOS_AUTO, SOS_PH or SOS_CR and L = 16; and 128, 256,
+                               512 and 1024 for single signals with SOS_AUTO, SOS_PH or SOS_CR, FP64
                                arithmetic and L = 16.  At N = 128 with FP32 I/O a lane's run
                                (128 doubles) stays in registers, one wavefront per SIMD; the
                                other wide runs do not fit on chip and live in the workspace

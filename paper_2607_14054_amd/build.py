@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsosfilt.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("plan.cpp", "sosfilt_api.hip", "sosfilt_batch.hip",
                                           "sosfilt_backward.hip", "sosfilt_block.hip", "sosfilt_carry.hip",
-                                          "sosfilt_static.hip", "sosfilt_wide.hip")]
+                                          "sosfilt_static.hip", "sosfilt_wide.hip", "sosfilt_narrow.hip")]
 OBJDIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -101,4 +101,9 @@ inline int64_t model_tile_groups(int64_t groups, int64_t warm_groups, const Resi
 // residency of a wide plan's kernel (sosfilt_wide.hip)
 Residency wide_residency(const sos_plan_s &p);
 
+// a narrow plan's residency and launch (sosfilt_narrow.hip)
+struct FiltArgs;
+Residency narrow_residency(const sos_plan_s &p);
+sos_status launch_narrow(const sos_plan_s &p, const void *x, void *y, const FiltArgs &a, hipStream_t s);
+
 }  // namespace sosf

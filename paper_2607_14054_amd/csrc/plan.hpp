@@ -116,6 +116,8 @@ bool wide_plan(const sos_plan_s &p);
 int64_t wide_tile(const sos_plan_s &p, int64_t n);
 size_t wide_workspace(const sos_plan_s &p, int64_t n);
 sos_status launch_wide(const sos_plan_s &p, const void *x, void *y, int64_t n, void *ws, hipStream_t s);
+// narrow groups, N = 4 (sosfilt_narrow.hip): single signals on 16-lane rows
+bool narrow_plan(const sos_plan_s &p);
 }
 sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
                        sos_plan_t *out);

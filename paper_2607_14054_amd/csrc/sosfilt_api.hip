@@ -278,7 +278,10 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   if (low && o.solver != SOS_BLOCK) return SOS_E_UNSUPPORTED;
   if (o.solver == SOS_BLOCK && o.compute_dtype == SOS_F32) return SOS_E_UNSUPPORTED;
   if (o.tile_groups < 0) return SOS_E_ARG;
-  if (!pow2_in(o.N, 8, kWideMaxN) || !pow2_in(o.L, 16, 64)) return SOS_E_UNSUPPORTED;
+  if (!pow2_in(o.N, 4, kWideMaxN) || !pow2_in(o.L, 16, 64)) return SOS_E_UNSUPPORTED;
+  // N = 4: single signals, PH and CR on 16-lane rows (sosfilt_narrow.hip)
+  if (o.N == 4 && (o.L != kL || !(o.solver == SOS_AUTO || o.solver == SOS_PH || o.solver == SOS_CR)))
+    return SOS_E_UNSUPPORTED;
   // N = 128 .. 1024: the lane runs live in the workspace (kernels_wide.hpp),
   // for PH and CR with FP64 arithmetic and 16-lane rows
   if (o.N > 64 && (o.L != kL || o.compute_dtype != SOS_F64 ||
@@ -345,6 +348,8 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
       r.waves_per_simd = p->waves_per_simd;
     } else if (st == SOS_OK && wide_plan(*p)) {
       r = wide_residency(*p);
+    } else if (st == SOS_OK && narrow_plan(*p)) {
+      r = narrow_residency(*p);
     } else if (st == SOS_OK)
       dispatch_rows_l<ResidencyRows>(p->N, p->L, p->io_dtype, p->compute_dtype, p->b0_factored, solver_mix(*p),
                                      p->K, &r);
@@ -489,6 +494,7 @@ sos_status sos_filt(sos_plan_t p, const void *x, void *y, int64_t n, void *works
     if (workspace && ((uintptr_t)workspace & 15) == 0) return launch_carry(*p, cl, x, y, n, workspace, s);
     if (p->flags & SOS_FLAG_CARRY_SCAN) return SOS_E_ARG;   // asked for, but no workspace
   }
+  if (narrow_plan(*p)) return launch_narrow(*p, x, y, a, s);
   // one solver for every section lets the kernel drop the per-section branch
   return dispatch_rows_l<LaunchRows>(p->N, p->L, p->io_dtype, p->compute_dtype, b0one, solver_mix(*p), q, a, s);
 }

@@ -111,7 +111,7 @@ sos_status validate(const sos_plan_t *plans, int32_t C, const int64_t *n, bool h
     if (!p || n[c] < 0) return SOS_E_ARG;
     if (!host_only && !p->d_table) return SOS_E_ARG;   // a host-only plan cannot filter
     if (p->solver_opt == SOS_PH_DEFERRED || p->solver_opt == SOS_SCALAR) return SOS_E_UNSUPPORTED;
-    if (p->N > 64) return SOS_E_UNSUPPORTED;   // wide groups run single signals only
+    if (p->N > 64 || p->N < 8) return SOS_E_UNSUPPORTED;   // wide and narrow groups run single signals only
     // block filtering batches only with block filtering (its own kernel)
     if ((p->solver_opt == SOS_BLOCK) != (plans[0]->solver_opt == SOS_BLOCK)) return SOS_E_UNSUPPORTED;
     if (!host_only && p->solver_opt == SOS_BLOCK && (!p->d_block || !p->d_aop)) return SOS_E_ARG;

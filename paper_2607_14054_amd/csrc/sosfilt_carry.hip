@@ -53,7 +53,7 @@ namespace sosf {
 constexpr int64_t kCarryMinSaving = 8192;   // section-samples of run-in per row
 
 bool carry_supported(const sos_plan_s &p) {
-  return p.compute_dtype == SOS_F64 && p.L == kL && p.N <= 64 &&
+  return p.compute_dtype == SOS_F64 && p.L == kL && p.N >= 8 && p.N <= 64 &&
          (p.solver_opt == SOS_AUTO || p.solver_opt == SOS_PH || p.solver_opt == SOS_CR) &&
          2 * p.K <= kCarryDMax;
 }

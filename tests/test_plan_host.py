@@ -64,7 +64,10 @@ def test_coefficient_validation(bad, code):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(N=4), S.SOS_E_UNSUPPORTED), (dict(N=24), S.SOS_E_UNSUPPORTED),
+    (dict(N=2), S.SOS_E_UNSUPPORTED), (dict(N=24), S.SOS_E_UNSUPPORTED),
+    # narrow groups (N = 4): 16-lane rows, PH or CR only
+    (dict(N=4, L=32), S.SOS_E_UNSUPPORTED), (dict(N=4, solver="scalar"), S.SOS_E_UNSUPPORTED),
+    (dict(N=4, solver="phd"), S.SOS_E_UNSUPPORTED),
     (dict(N=2048), S.SOS_E_UNSUPPORTED), (dict(io_dtype="f64", compute_dtype="f32"), S.SOS_E_UNSUPPORTED),
     # wide groups (N > 64): FP64 arithmetic, 16-lane rows, PH or CR only
     (dict(N=128, compute_dtype="f32"), S.SOS_E_UNSUPPORTED), (dict(N=256, L=32), S.SOS_E_UNSUPPORTED),
@@ -101,7 +104,7 @@ def test_b0_zero_keeps_unfactored_rows():
     assert np.allclose(p.table(S.SOS_TABLE_ROWS, 1), [0.0, 1.0, 0.5, sos[1, 4], sos[1, 5]])
 
 
-@pytest.mark.parametrize("N", [8, 16, 32, 64])
+@pytest.mark.parametrize("N", [4, 8, 16, 32, 64])
 def test_ph_tables_match_model(N):
     sos = W.make_sos(3, 0.6, 0.97, 4)
     p = plan(sos, N=N, solver="ph")
@@ -119,7 +122,7 @@ def test_ph_tables_match_model(N):
     assert p.info().solver == ["ph"] * 3
 
 
-@pytest.mark.parametrize("N", [8, 16, 64])
+@pytest.mark.parametrize("N", [4, 8, 16, 64])
 def test_cr_tables_match_closed_form(N):
     r, theta = 0.93, 0.7
     sec = np.array([[1.0, 0.1, 0.2, 1.0, -2 * r * math.cos(theta), r * r]])
