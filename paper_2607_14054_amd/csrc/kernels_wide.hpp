@@ -201,6 +201,130 @@ __device__ __forceinline__ void wide_cr_section(double *__restrict__ S, int N, i
   xs1 = ys1;
 }
 
+// One group of a row through an all-PH cascade with the run in the
+// workspace (Section VI-B, the steps of ph_section), in one pass over the
+// run per section: the input is read chunk by chunk from HBM into section
+// 0's pass, every later pass applies the previous section's homogeneous
+// correction (step 3) to its input as it reads it, and the store applies
+// the last section's.  Each pass forms the non-recursive stage and the
+// particular recurrence (step 1) and ends with the terminal scan (step 2).
+// That is one read and one write of the run per section, where separate
+// FIR-and-recurrence and correction passes take two of each.
+// st: the row's boundary values (raw input pair, then each section's output
+// pair); live: store the group.
+template <typename TI, bool B0ONE>
+__device__ __forceinline__ void wide_ph_group(double *__restrict__ S, const TI *__restrict__ x,
+                                              TI *__restrict__ y, int64_t g, int N, int64_t n, int K,
+                                              int stride, ctab<double> ct, double gain, double *st,
+                                              TI *__restrict__ buf, bool full, bool live) {
+  const int rl = row_lane();
+  const double m0 = lane0_mask<double>();
+  // the raw input's extended blocks: the two samples before the lane's run
+  // (for lane 0 the previous group's last two, kept in st)
+  double p1, p2;
+  {
+    const int64_t i1 = g + (int64_t)rl * N - 1, i2 = i1 - 1;
+    const double v1 = (rl > 0 && i1 >= 0 && i1 < n) ? (double)x[i1] : 0.0;
+    const double v2 = (rl > 0 && i2 >= 0 && i2 < n) ? (double)x[i2] : 0.0;
+    p1 = rl == 0 ? st[1] : v1;
+    p2 = rl == 0 ? st[0] : v2;
+    // this group's last two raw inputs, for the next group's lane 0
+    const int64_t e = g + (int64_t)kL * N;
+    st[0] = (e - 2 >= 0 && e - 2 < n) ? (double)x[e - 2] : 0.0;
+    st[1] = (e - 1 >= 0 && e - 1 < n) ? (double)x[e - 1] : 0.0;
+  }
+  double pr = 0.0, qr = 0.0, xs2 = 0.0, xs1 = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const ctab<double> c = ct + (int64_t)k * stride;
+    const double b0 = c[OFF_B0], b1 = c[OFF_B1], b2 = c[OFF_B2], a1 = c[OFF_A1], a2 = c[OFF_A2];
+    double *ys = st + 2 + 2 * k;
+    const double ys2 = ys[0], ys1 = ys[1];
+    double w1 = m0 * ys1, w2 = m0 * ys2;
+    if (k == 0) {
+      // section 0 reads the raw input, staged 64 blocks at a time
+      for (int cc = 0; cc < N / kWideChunk; ++cc) {
+        double X[kWideChunk];
+        wide_load_chunk<TI>(X, x, g, N, cc, n, full, buf);
+#pragma unroll
+        for (int j = 0; j < kWideChunk; ++j) {
+          const double xin = X[j];
+          double v = B0ONE ? xin : b0 * xin;
+          v = fma_(b1, p1, v);
+          v = fma_(b2, p2, v);
+          v = fma_(-a2, w2, v);
+          v = fma_(-a1, w1, v);
+          S[64 * (cc * kWideChunk + j)] = v;
+          p2 = p1;
+          p1 = xin;
+          w2 = w1;
+          w1 = v;
+        }
+      }
+    } else {
+      // the previous section's output: its particular solution plus the
+      // homogeneous correction from (pr, qr), true in the last two blocks
+      const ctab<double> u1 = c - stride + OFF_U1;
+      const ctab<double> u2 = c - stride + OFF_U1 + N;
+#pragma unroll 8
+      for (int m = 0; m < N - 2; ++m) {
+        const double xin = fma_(-u2[m], pr, fma_(-u1[m], qr, S[64 * m]));
+        double v = B0ONE ? xin : b0 * xin;
+        v = fma_(b1, p1, v);
+        v = fma_(b2, p2, v);
+        v = fma_(-a2, w2, v);
+        v = fma_(-a1, w1, v);
+        S[64 * m] = v;
+        p2 = p1;
+        p1 = xin;
+        w2 = w1;
+        w1 = v;
+      }
+#pragma unroll
+      for (int m = N - 2; m < N; ++m) {
+        const double xin = S[64 * m];
+        double v = B0ONE ? xin : b0 * xin;
+        v = fma_(b1, p1, v);
+        v = fma_(b2, p2, v);
+        v = fma_(-a2, w2, v);
+        v = fma_(-a1, w1, v);
+        S[64 * m] = v;
+        p2 = p1;
+        p1 = xin;
+        w2 = w1;
+        w1 = v;
+      }
+    }
+    // step 2: the true last two blocks along the row
+    double p = w2, q = w1;
+    row_scan_2x2(p, q, c + OFF_PH_POW);
+    S[64 * (N - 2)] = p;
+    S[64 * (N - 1)] = q;
+    pr = shr<1>(p);
+    qr = shr<1>(q);
+    ys[0] = last_of_row(p);
+    ys[1] = last_of_row(q);
+    // the next section's extended blocks: this section's true output at the
+    // end of the previous lane (lane 0: of the previous group)
+    xs2 = ys2;
+    xs1 = ys1;
+    p1 = shift_r(q, xs1);
+    p2 = shift_r(p, xs2);
+  }
+  if (!live) return;
+  const ctab<double> cl = ct + (int64_t)(K - 1) * stride;
+  const ctab<double> u1 = cl + OFF_U1;
+  const ctab<double> u2 = cl + OFF_U1 + N;
+  for (int cc = 0; cc < N / kWideChunk; ++cc) {
+    double X[kWideChunk];
+#pragma unroll
+    for (int j = 0; j < kWideChunk; ++j) {
+      const int m = cc * kWideChunk + j;
+      X[j] = m < N - 2 ? fma_(-u2[m], pr, fma_(-u1[m], qr, S[64 * m])) : S[64 * m];
+    }
+    wide_store_chunk<TI>(X, y, g, N, cc, n, full, gain, buf);
+  }
+}
+
 // One wavefront filters four tiles, one per row, as sos_rows_kernel (run-in,
 // then the tile, groups chained through the sections' boundary values).
 template <typename TI, bool B0ONE, int SOLVER>
@@ -227,6 +351,10 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_wide_kernel(
   for (int64_t it = 0; it < steps; ++it) {
     const int64_t g = t0 - a.warm + it * G;
     const bool full = __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= a.n)) == 0;
+    if constexpr (SOLVER == SOS_PH) {
+      wide_ph_group<TI, B0ONE>(S, x, y, g, N, a.n, a.K, a.stride, ct, a.gain, st, buf, full, it >= warm_groups);
+      continue;
+    }
     for (int c = 0; c < N / kWideChunk; ++c) {
       wide_load_chunk<TI>(X, x, g, N, c, a.n, full, buf);
 #pragma unroll

@@ -1,7 +1,8 @@
 """GPU parity of wide groups, N = 128 .. 1024 blocks per lane run (the upper
 half of the paper's N sweep), against the FP64 oracle through the C ABI.
 N = 128 with FP32 I/O keeps a lane's run in registers (a wavefront alone
-on its SIMD); the other wide plans keep the runs in the caller's workspace.  PH and cyclic
+on its SIMD); the other wide plans keep the runs in the caller's workspace,
+all-PH plans with one pass over it per section.  PH and cyclic
 reduction (log2 N = 7 .. 10 levels).  Bars as for N <= 64: FP64 in/out
 within 1e-12 relative RMS (or four times the FP64 oracle's own error
 against its extended-precision twin where that is larger), FP32 in/out
@@ -114,8 +115,26 @@ def test_wide_needs_its_workspace():
     assert bool((y == 3.0).all())
 
 
+@pytest.mark.parametrize("n", [1, 17, 16 * 256 - 1, 16 * 256 + 1, 5 * 16 * 256 + 3, 70001])
+def test_wide_ph_one_pass_ragged(n):
+    """The all-PH wide kernel (one pass over the run per section; AUTO is
+    all PH here) at N = 256, FP32 I/O: lengths below one group and around
+    group boundaries, K = 3 and a b0 = 0 section (b0 kept in the
+    numerator)."""
+    sos = W.make_sos(3, 0.5, 0.95, 937)
+    for b0zero in (False, True):
+        s_ = sos.copy()
+        if b0zero:
+            s_[1, 0:3] = [0.0, 0.5, -0.25]
+        x = W.make_signal(n, 938, np.float32)
+        for solver in ("ph", "auto"):
+            p = S.Plan(s_, io_dtype="f32", compute_dtype="f64", solver=solver, N=256, tile_groups=2)
+            assert p.workspace_size(n) > 0 and p.info().b0_factored == (not b0zero)
+            check(filt(p, x), x, s_, "f32", "%s n=%d b0zero=%s" % (solver, n, b0zero))
+
+
 @pytest.mark.parametrize("solver", ["ph", "cr"])
-@pytest.mark.parametrize("N", [128, 1024])
+@pytest.mark.parametrize("N", [128, 256, 1024])
 def test_wide_headline_full_size_sampled(N, solver):
     """The full headline workload (2^28 float32 samples, K = 8, r in
     [0.8, 0.98], seed 0) at N = 128 and 1024 in the launch shape the bench
