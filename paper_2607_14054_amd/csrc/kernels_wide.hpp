@@ -23,6 +23,7 @@ namespace sosf {
 
 constexpr int kWideChunk = 64;     // blocks staged per pass through LDS
 constexpr int kWideMaxN = 1024;
+constexpr int kWideBatch = 8;      // independent CR updates whose reads are issued together
 
 struct WideArgs {
   int64_t n;
@@ -162,18 +163,33 @@ __device__ __forceinline__ void wide_cr_section(double *__restrict__ S, int N, i
   const double m0 = lane0_mask<double>(), z1 = m0 * ys1, z2 = m0 * ys2;
   S[0] = fma_(-a1, z1, fma_(-a2, z2, S[0]));
   S[64] = fma_(-a2, z1, S[64]);
-  // reduction, eq. cr_coeff_update coefficients per level
+  // reduction, eq. cr_coeff_update coefficients per level.  The updates of
+  // one parity at one level are independent (each reads blocks of the other
+  // parity), so they go kWideBatch at a time with every read issued before
+  // the first write: the compiler cannot tell that the runtime offsets do
+  // not overlap, and would otherwise wait on each read in turn.
   for (int i = 0; i < LG; ++i) {
     const int s = 1 << i, ni = N >> i;
     const double fe = c[OFF_CR_LVL + 4 * i], e = c[OFF_CR_LVL + 4 * i + 1];
     const double wrap = shr<1>(S[64 * (N - 1)]);
-    for (int j = 0; j < ni; j += 2) {
-      const int m = s * (j + 1) - 1;
-      S[64 * m] = fma_(-fe, j == 0 ? wrap : S[64 * (m - s)], S[64 * m]);
-    }
-    for (int j = 1; j < ni; j += 2) {
-      const int m = s * (j + 1) - 1;
-      S[64 * m] = fma_(-e, S[64 * (m - s)], S[64 * m]);
+    for (int par = 0; par < 2; ++par) {
+      const double f = par == 0 ? fe : e;
+      for (int j0 = par; j0 < ni; j0 += 2 * kWideBatch) {
+        double a[kWideBatch], b[kWideBatch];
+#pragma unroll
+        for (int t = 0; t < kWideBatch; ++t) {
+          const int j = j0 + 2 * t, m = s * (j + 1) - 1;
+          if (j < ni) {
+            a[t] = S[64 * m];
+            b[t] = j == 0 ? wrap : S[64 * (m - s)];
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < kWideBatch; ++t) {
+          const int j = j0 + 2 * t, m = s * (j + 1) - 1;
+          if (j < ni) S[64 * m] = fma_(-f, b[t], a[t]);
+        }
+      }
     }
   }
   // terminal block, eq. cr_terminal_block, by the row scan
@@ -188,11 +204,23 @@ __device__ __forceinline__ void wide_cr_section(double *__restrict__ S, int N, i
     const int s = 1 << i, ni = N >> i;
     const double cc = c[OFF_CR_LVL + 4 * i + 2], dd = c[OFF_CR_LVL + 4 * i + 3];
     const double w3 = ni == 2 ? shr<1>(r1) : shr<1>(S[64 * (N - 2 * s - 1)]);
-    for (int j = 0; j < ni; j += 2) {
-      const int m = s * (j + 1) - 1;
-      const double y1 = (j >= 1) ? S[64 * (m - s)] : r1;
-      const double y3 = (j >= 3) ? S[64 * (m - 3 * s)] : (j == 0 ? w3 : r1);
-      S[64 * m] = fma_(-cc, y1, fma_(-dd, y3, S[64 * m]));
+    // the even blocks of the level read only odd ones: independent, batched
+    for (int j0 = 0; j0 < ni; j0 += 2 * kWideBatch) {
+      double a[kWideBatch], y1[kWideBatch], y3[kWideBatch];
+#pragma unroll
+      for (int t = 0; t < kWideBatch; ++t) {
+        const int j = j0 + 2 * t, m = s * (j + 1) - 1;
+        if (j < ni) {
+          a[t] = S[64 * m];
+          y1[t] = (j >= 1) ? S[64 * (m - s)] : r1;
+          y3[t] = (j >= 3) ? S[64 * (m - 3 * s)] : (j == 0 ? w3 : r1);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kWideBatch; ++t) {
+        const int j = j0 + 2 * t, m = s * (j + 1) - 1;
+        if (j < ni) S[64 * m] = fma_(-cc, y1[t], fma_(-dd, y3[t], a[t]));
+      }
     }
   }
   ys[0] = last_of_row(S[64 * (N - 2)]);
