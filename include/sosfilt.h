@@ -255,8 +255,8 @@ sos_status sos_filt(sos_plan_t plan, const void *x, void *y, int64_t n,
  * x, y, n, stream  as sos_filt (device x and y on the current device, which
  *                  must be the plan's).
  * Returns SOS_E_SCRATCH, enqueuing nothing, when sos_workspace_size(plan, n)
- * exceeds SOS_STATIC_SCRATCH_BYTES (only the exact carry uses a workspace;
- * calls that carry by the run-in need none).  The first call on a device
+ * exceeds SOS_STATIC_SCRATCH_BYTES (only the exact carry and the lane runs
+ * of wide groups use a workspace; other calls need none).  The first call on a device
  * looks up the buffer's address there (SOS_E_DEVICE if that fails).  No
  * allocation, no synchronisation.  Every call on one GPU uses the same
  * buffer, whatever the plan or stream: calls whose launches can overlap on

@@ -1,11 +1,11 @@
 // sos_filt_static: sos_filt for callers that cannot allocate device memory.
 //
-// sos_filt's exact inter-tile carry needs a caller workspace (the tiles' end
-// states, the scan's second buffer and the powers of the transition).  This
-// entry point takes that workspace from a fixed buffer in the library's own
-// device image instead, so the caller passes only x and y.  Everything else
-// (argument checks, the choice between run-in and scan, the kernels) is
-// sos_filt's.
+// sos_filt needs a caller workspace for its exact inter-tile carry (the
+// tiles' end states, the scan's second buffer and the powers of the
+// transition) and for the lane runs of wide groups.  This entry point takes
+// that workspace from a fixed buffer in the library's own device image
+// instead, so the caller passes only x and y.  Everything else (argument
+// checks, the choice between run-in and scan, the kernels) is sos_filt's.
 #include <hip/hip_runtime.h>
 
 #include <mutex>

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dispatch.hpp"
 #include "kernels_wide.hpp"
@@ -29,13 +30,19 @@ bool in_registers(const sos_plan_s &p) {
 
 template <typename TI>
 const void *wide_kernel_t(bool regs, bool b0one, int mix) {
-#define SOSF_W(B, S)                                                                               \
-  (regs ? reinterpret_cast<const void *>(&sos_rows_kernel<kRegN, TI, double, B, S, kL>)            \
-        : reinterpret_cast<const void *>(&sos_rows_wide_kernel<TI, B, S>))
-  if (mix == SOS_PH) return b0one ? SOSF_W(true, SOS_PH) : SOSF_W(false, SOS_PH);
-  if (mix == SOS_CR) return b0one ? SOSF_W(true, SOS_CR) : SOSF_W(false, SOS_CR);
-  return b0one ? SOSF_W(true, SOS_AUTO) : SOSF_W(false, SOS_AUTO);
-#undef SOSF_W
+#define SOSF_PICK(K)                                                            \
+  if (mix == SOS_PH) return b0one ? K(true, SOS_PH) : K(false, SOS_PH);         \
+  if (mix == SOS_CR) return b0one ? K(true, SOS_CR) : K(false, SOS_CR);         \
+  return b0one ? K(true, SOS_AUTO) : K(false, SOS_AUTO);
+#define SOSF_REG(B, S) reinterpret_cast<const void *>(&sos_rows_kernel<kRegN, float, double, B, S, kL>)
+#define SOSF_WS(B, S) reinterpret_cast<const void *>(&sos_rows_wide_kernel<TI, B, S>)
+  if constexpr (std::is_same<TI, float>::value) {
+    if (regs) { SOSF_PICK(SOSF_REG) }
+  }
+  SOSF_PICK(SOSF_WS)
+#undef SOSF_WS
+#undef SOSF_REG
+#undef SOSF_PICK
 }
 
 int mix_of(const sos_plan_s &p) {
@@ -51,9 +58,7 @@ const void *wide_kernel(const sos_plan_s &p) {
 }
 
 size_t wide_lds(const sos_plan_s &p) {
-  if (in_registers(p))
-    return p.io_dtype == SOS_F32 ? (size_t)lds_bytes<kRegN, float, double>(p.K)
-                                 : (size_t)lds_bytes<kRegN, double, double>(p.K);
+  if (in_registers(p)) return (size_t)lds_bytes<kRegN, float, double>(p.K);   // FP32 I/O only
   return p.io_dtype == SOS_F32 ? (size_t)lds_bytes<kWideChunk, float, double>(p.K)
                                : (size_t)lds_bytes<kWideChunk, double, double>(p.K);
 }
