@@ -549,8 +549,10 @@ def bench_tiny(S, W, torch, dev, args):
         import oracle
         ref = oracle.sosfilt(x_np, sos)
     out = {"n": c.n, "rows": []}
-    for solver, N in (("ph", 8), ("cr", 8), ("ph", 16), ("ph", 32), ("cr", 32)):
-        plan = S.Plan(sos, io_dtype="f64", compute_dtype="f64", solver=solver, N=N)
+    # the specified shape (N = 8, L = 64) first, then 16-lane rows
+    for solver, N, L in (("ph", 8, 64), ("cr", 8, 64), ("ph", 8, 16), ("cr", 8, 16), ("ph", 16, 16),
+                         ("ph", 32, 16), ("cr", 32, 16)):
+        plan = S.Plan(sos, io_dtype="f64", compute_dtype="f64", solver=solver, N=N, L=L)
         S.filt(plan, xt, y)
         torch.cuda.synchronize()
         lat = []
@@ -563,14 +565,14 @@ def bench_tiny(S, W, torch, dev, args):
             torch.cuda.synchronize()
             lat.append(e0.elapsed_time(e1) * 1e3)
         sec = timed(torch, lambda: S.filt(plan, xt, y), 50)
-        row = {"solver": solver, "N": N, "latency_us_median": float(np.median(lat)),
+        row = {"solver": solver, "N": N, "L": L, "latency_us_median": float(np.median(lat)),
                "back_to_back_us": sec * 1e6, "GSps": c.n / sec / 1e9}
         if ref is not None:
             import oracle
             row["rel_rms"] = oracle.rel_rms(y.cpu().numpy(), ref)
         out["rows"].append(row)
-        log("tiny %s N=%2d: latency median %.1f us, back-to-back %.1f us (%.1f GS/s)%s"
-            % (solver, N, row["latency_us_median"], row["back_to_back_us"], row["GSps"],
+        log("tiny %s N=%2d L=%2d: latency median %.1f us, back-to-back %.1f us (%.1f GS/s)%s"
+            % (solver, N, L, row["latency_us_median"], row["back_to_back_us"], row["GSps"],
                ", rel_rms %.2e" % row["rel_rms"] if "rel_rms" in row else ""))
     return out
 
