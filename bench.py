@@ -739,7 +739,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the cascade is filtered on a single "
-              "MI355X; multi-GPU sharding is not part of this build", file=sys.stderr)
+              "MI355X; sharding across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
