@@ -216,7 +216,7 @@ sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
  * at N = 1024), required.  N = 128 with FP32 I/O needs none.  Otherwise
  * 0 when it carries the state between tiles by the run-in, else the size
  * of the exact carry's buffers.  The exact carry (FP64 arithmetic, solvers AUTO, PH or CR,
- * K <= 16) runs every tile twice, once from zero section states to get its
+ * K <= 16, L = 16, N = 8 .. 64) runs every tile twice, once from zero section states to get its
  * end state c_t and once from the scanned true state, with a log-depth scan
  * S_t = c_t + Phi^T S_{t-1} in between (Phi the cascade's one-step state
  * transition).  sos_filt takes it when the run-in would be longer than 1.2
