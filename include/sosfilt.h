@@ -279,7 +279,8 @@ sos_status sos_filt_static(sos_plan_t plan, const void *x, void *y, int64_t n, s
  * sos_batch_plan -- fix the channel set and lengths once (allocates).
  *
  * plans    host [C]: channel c is filtered with plans[c] (the same plan may
- *          serve several channels).  All plans must share N, io_dtype and
+ *          serve several channels).  All plans must share N (8 .. 64; the
+ *          narrow and wide widths are single-signal only), L, io_dtype and
  *          compute_dtype (else SOS_E_UNSUPPORTED), and either all use
  *          SOS_AUTO, SOS_PH or SOS_CR, or all use SOS_BLOCK (block filtering,
  *          one workgroup per four tiles of a channel, with that channel's
