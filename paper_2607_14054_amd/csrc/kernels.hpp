@@ -242,6 +242,67 @@ __device__ __forceinline__ void ph_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
   xs1 = ys1;
 }
 
+// PH over the cascade with each section's homogeneous correction (step 3)
+// applied inside the next section's pass: one ascending pass per section
+// corrects the section's input (the previous section's particular
+// solution, from that section's terminal values pr, qr and tables cp),
+// forms the non-recursive stage and runs the particular recurrence (step 1);
+// then the terminal scan (step 2).  The values and the order of operations
+// on each are those of ph_section; fewer values are live at once, which is
+// what a run too long for the architectural registers (N = 128) needs.
+// FIRST: the input is the raw signal (nothing to correct).  On exit X holds
+// the section's particular solution with its true last two blocks, and
+// (pr, qr) the correction's inputs for the next pass (or for
+// ph_last_correction).  Boundary values as for ph_section.
+template <int N, typename T, bool B0ONE, bool FIRST, int L = kL>
+__device__ __forceinline__ void ph_fused_section(T (&X)[N], ctab<T> c, ctab<T> cp, T &pr, T &qr, T &xs2,
+                                                 T &xs1, T *ys) {
+  const T b0 = c[OFF_B0], b1 = c[OFF_B1], b2 = c[OFF_B2], a1 = c[OFF_A1], a2 = c[OFF_A2];
+  const T ys2 = ys[0], ys1 = ys[1];
+  // the extended blocks: the input's last two blocks in the previous lane
+  // (true values: the raw input, or the previous section's scanned ones)
+  T p1 = shift_r<L>(X[N - 1], xs1), p2 = shift_r<L>(X[N - 2], xs2);
+  const T m0 = lane0_mask<T, L>();
+  T w1 = m0 * ys1, w2 = m0 * ys2;
+  const ctab<T> u1 = cp + OFF_U1;
+  const ctab<T> u2 = cp + OFF_U1 + N;
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    T xin = X[m];
+    if (!FIRST && m < N - 2) xin = fma_(-u2[m], pr, fma_(-u1[m], qr, xin));
+    T v = B0ONE ? xin : b0 * xin;
+    v = fma_(b1, p1, v);
+    v = fma_(b2, p2, v);
+    v = fma_(-a2, w2, v);
+    v = fma_(-a1, w1, v);
+    X[m] = v;
+    p2 = p1;
+    p1 = xin;
+    w2 = w1;
+    w1 = v;
+    if ((m & (kSchedChunk - 1)) == kSchedChunk - 1) __builtin_amdgcn_sched_barrier(0);
+  }
+  T p = X[N - 2], q = X[N - 1];
+  row_scan_2x2<T, L>(p, q, c + OFF_PH_POW);
+  X[N - 2] = p;
+  X[N - 1] = q;
+  pr = shr<1, T, L>(p);
+  qr = shr<1, T, L>(q);
+  ys[0] = last_of_row<L>(p);
+  ys[1] = last_of_row<L>(q);
+  xs2 = ys2;
+  xs1 = ys1;
+}
+
+// The last section's homogeneous correction (step 3, eq. PH_forward).
+template <int N, typename T>
+__device__ __forceinline__ void ph_last_correction(T (&X)[N], ctab<T> cp, T pr, T qr) {
+  const ctab<T> u1 = cp + OFF_U1;
+  const ctab<T> u2 = cp + OFF_U1 + N;
+#pragma unroll
+  for (int m = 0; m < N - 2; ++m) X[m] = fma_(-u2[m], pr, fma_(-u1[m], qr, X[m]));
+}
+
 // Cyclic reduction (Section VI-C) of one section on one group per row.
 // Level i works on the blocks m = s(j+1)-1 (s = 2^i, j = 0..N/s-1); even j
 // are eliminated, odd j retained.  A reference below j = 0 wraps to the last
@@ -471,12 +532,23 @@ __device__ __forceinline__ void filter_rows(const TI *__restrict__ x, TI *__rest
     T xs2 = st[0], xs1 = st[1];
     st[0] = last_of_row<L>(X[N - 2]);
     st[1] = last_of_row<L>(X[N - 1]);
-    for (int k = 0; k < K; ++k) {
-      const ctab<T> c = tab + (int64_t)k * stride;
-      if (SOLVER == SOS_CR || (SOLVER == SOS_AUTO && solver[k] == SOS_CR))
-        cr_section<N, T, B0ONE, L>(X, c, xs2, xs1, st + 2 + 2 * k);
-      else
-        ph_section<N, T, B0ONE, L>(X, c, xs2, xs1, st + 2 + 2 * k);
+    if constexpr (SOLVER == SOS_PH && N >= 128) {
+      // a run that needs the accumulation registers: one pass per section
+      T pr = T(0), qr = T(0);
+      ph_fused_section<N, T, B0ONE, true, L>(X, tab, tab, pr, qr, xs2, xs1, st + 2);
+      for (int k = 1; k < K; ++k) {
+        const ctab<T> c = tab + (int64_t)k * stride;
+        ph_fused_section<N, T, B0ONE, false, L>(X, c, c - stride, pr, qr, xs2, xs1, st + 2 + 2 * k);
+      }
+      if (it >= warm_groups) ph_last_correction<N, T>(X, tab + (int64_t)(K - 1) * stride, pr, qr);
+    } else {
+      for (int k = 0; k < K; ++k) {
+        const ctab<T> c = tab + (int64_t)k * stride;
+        if (SOLVER == SOS_CR || (SOLVER == SOS_AUTO && solver[k] == SOS_CR))
+          cr_section<N, T, B0ONE, L>(X, c, xs2, xs1, st + 2 + 2 * k);
+        else
+          ph_section<N, T, B0ONE, L>(X, c, xs2, xs1, st + 2 + 2 * k);
+      }
     }
     if (it >= warm_groups) store_group<N, TI, T, L>(X, y, g, n, full, gain, buf);
   }
