@@ -1,4 +1,5 @@
-// Wide groups: N = 128 .. 1024 blocks per lane run, L = 16, FP64 arithmetic.
+// Wide groups with the lane runs in memory: N = 256 .. 1024 blocks per lane
+// run (and N = 128 with FP64 I/O), L = 16, FP64 arithmetic.
 //
 // The method is the one of kernels.hpp (Sections V to VII): lane l of a
 // 16-lane row holds the run x[g + l N + m], m = 0..N-1, and each section is
@@ -7,8 +8,8 @@
 // doubles; 8 KB at N = 1024), nor the LDS of a compute unit's resident
 // lanes, so it lives in a device workspace: element (m, lane) of wavefront
 // w at ws[(w N + m) 64 + lane], so that the 64 lanes of a wavefront touch
-// 512 consecutive bytes for each m.  Every pass of a section streams over
-// m through that buffer.
+// 512 consecutive bytes for each m.  An all-PH cascade makes one pass over
+// that buffer per section (wide_ph_group); CR makes one per level.
 //
 // Input and output move between HBM and the workspace 64 blocks at a time,
 // staged through the same per-row LDS buffer as N = 64 (the stride-N
