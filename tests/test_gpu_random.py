@@ -63,3 +63,48 @@ def test_random_config(case):
     yb = yb.cpu().numpy()
     check(yb[b.offsets[1]:b.offsets[1] + n], x, sos, io, "batched")
     check(yb[b.offsets[0]:b.offsets[0] + 37], x2, W.make_sos(2, 0.5, 0.9, 7000 + i), io, "neighbour")
+
+
+# The widths and block sizes outside the sweep above: N = 4 and N = 128 ..
+# 1024 (single signals; FP64 arithmetic), and L = 32, 64 at N = 8 .. 64
+# (also batched).  A separate seed keeps the cases above as they are.
+RNG2 = np.random.default_rng(2025)
+CASES2 = []
+for i in range(24):
+    wide = i % 2 == 0
+    K = int(RNG2.integers(1, 17))
+    if wide:
+        N, L = int(RNG2.choice([4, 128, 256, 512, 1024])), 16
+    else:
+        N, L = int(RNG2.choice([8, 16, 32, 64])), int(RNG2.choice([32, 64]))
+    io = str(RNG2.choice(["f32", "f64"]))
+    solver = str(RNG2.choice(["auto", "ph", "cr"]))
+    n = int(np.floor(2.0 ** RNG2.uniform(0, 19 if wide else 17)))
+    r_hi = float(RNG2.choice([0.9, 0.98, 0.995]))
+    CASES2.append((i, K, N, L, io, solver, n, r_hi))
+
+
+@pytest.mark.parametrize("case", CASES2, ids=lambda c: "w%02d-K%d-N%d-L%d-%s-%s-n%d-r%g" % c)
+def test_random_width_and_block_size(case):
+    i, K, N, L, io, solver, n, r_hi = case
+    sos = W.make_sos(K, 0.5, r_hi, 8000 + i)
+    dt = np.float64 if io == "f64" else np.float32
+    x = W.make_signal(n, 8100 + i, dt)
+    p = S.Plan(sos, io_dtype=io, compute_dtype="f64", solver=solver, N=N, L=L)
+    assert p.info().N == N and p.info().L == L
+    y = S.filt(p, torch.from_numpy(x).to(DEV))
+    torch.cuda.synchronize()
+    check(y.cpu().numpy(), x, sos, io, "single")
+    if 8 <= N <= 64:
+        # one batch with a short neighbour at an odd offset, same N and L
+        q = S.Plan(W.make_sos(2, 0.5, 0.9, 8200 + i), io_dtype=io, compute_dtype="f64", solver=solver, N=N, L=L)
+        x2 = W.make_signal(37, 8300 + i, dt)
+        b = S.Batch([q, p], [37, n])
+        xb = np.zeros(b.total, dt)
+        xb[b.offsets[0]:b.offsets[0] + 37] = x2
+        xb[b.offsets[1]:b.offsets[1] + n] = x
+        yb = S.filt_batched(b, torch.from_numpy(xb).to(DEV))
+        torch.cuda.synchronize()
+        yb = yb.cpu().numpy()
+        check(yb[b.offsets[1]:b.offsets[1] + n], x, sos, io, "batched")
+        check(yb[b.offsets[0]:b.offsets[0] + 37], x2, W.make_sos(2, 0.5, 0.9, 8200 + i), io, "neighbour")
