@@ -126,12 +126,16 @@ def test_backward_f32_adjoint_config_channel():
     assert es < 1e-9
 
 
-@pytest.mark.parametrize("solver,N", [("cr", 64), ("ph", 8), ("phd", 32)])
-def test_backward_independent_of_forward_solver(solver, N):
+@pytest.mark.parametrize("solver,N,L", [("cr", 64, 16), ("ph", 8, 16), ("phd", 32, 16), ("ph", 4, 16),
+                                         ("cr", 4, 16), ("auto", 128, 16), ("ph", 1024, 16), ("ph", 16, 64)])
+def test_backward_independent_of_forward_solver(solver, N, L):
+    """The adjoint runs on its own 16-block sub-plan: the same gradients
+    whatever the forward plan's solver, width (N = 4 .. 1024) or block
+    size."""
     sos = W.make_sos(4, 0.5, 0.95, 44)
     x = W.make_signal(30001, 45, np.float64)
     g = W.grad_seed_signal(30001, 45, np.float64)
-    gx, gs = run_backward(sos, x, g, compute_dtype="f64", solver=solver, N=N)
+    gx, gs = run_backward(sos, x, g, compute_dtype="f64", solver=solver, N=N, L=L)
     check_f64(x, sos, g, gx, gs, solver)
 
 
