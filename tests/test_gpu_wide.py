@@ -175,3 +175,40 @@ def test_wide_headline_full_size_sampled(N, solver):
         ref = oracle.sosfilt(x_np[lo:hi], sos)[start - lo:]
         err = oracle.rel_rms(y[start:hi].cpu().numpy(), ref)
         assert err < 1e-6, (N, solver, start, err)
+
+
+@pytest.mark.parametrize("N,solver", [(4, "cr"), (128, "auto"), (256, "ph"), (512, "cr")])
+def test_wide_and_narrow_graph_replays(N, solver):
+    """sos_filt captured in a HIP graph (workspace allocated beforehand)
+    replays equal to the eager launch, three times with new inputs in
+    between."""
+    sos = W.make_sos(6, 0.8, 0.98, 941)
+    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=solver, N=N)
+    n = 7 * 16 * N + 333
+    ws = p.workspace_size(n)
+    wsb = torch.empty(max(ws, 16), dtype=torch.uint8, device=DEV)
+    x = torch.from_numpy(W.make_signal(n, 942, np.float32)).to(DEV)
+    y = torch.empty_like(x)
+    vp = ctypes.c_void_p
+
+    def launch(stream_ptr):
+        rc = S.lib().sos_filt(p.handle, vp(x.data_ptr()), vp(y.data_ptr()), n,
+                              vp(wsb.data_ptr()) if ws else None, stream_ptr)
+        assert rc == S.SOS_OK, rc
+
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    launch(S._stream_ptr(None))
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        launch(S._stream_ptr(s))
+    for rep in range(3):
+        x.copy_(torch.from_numpy(W.make_signal(n, 943 + rep, np.float32)).to(DEV))
+        y.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        got = y.clone()
+        launch(S._stream_ptr(None))
+        torch.cuda.synchronize()
+        assert torch.equal(got, y), (N, rep)
+        check(y.cpu().numpy(), x.cpu().numpy(), sos, "f32", "N=%d rep %d" % (N, rep))
