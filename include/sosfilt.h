@@ -65,10 +65,8 @@ typedef enum {
 } sos_dtype;
 
 typedef enum {
-    SOS_AUTO = 0,        /* the faster of PH and CR on MI355X for the plan's width: PH
-                            for every section at N = 4 .. 64 (free of the CR guard)
-                            and with wide runs in the workspace; CR where the guard
-                            allows it (else PH) at N = 128 with FP32 I/O */
+    SOS_AUTO = 0,        /* PH for every section: the faster of the two on MI355X at
+                            every N, and free of the CR guard */
     SOS_PH = 1,          /* PH factorisation (Section VI-B) for every section */
     SOS_CR = 2,          /* cyclic reduction (Section VI-C), guard still applies */
     SOS_PH_DEFERRED = 3, /* PH with the homogeneous correction (eq. PH_forward) of all

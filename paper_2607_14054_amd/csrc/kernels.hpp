@@ -245,11 +245,12 @@ __device__ __forceinline__ void ph_section(T (&X)[N], ctab<T> c, T &xs2, T &xs1,
 // PH over the cascade with each section's homogeneous correction (step 3)
 // applied inside the next section's pass: one ascending pass per section
 // corrects the section's input (the previous section's particular
-// solution, from that section's terminal values pr, qr and tables cp),
-// forms the non-recursive stage and runs the particular recurrence (step 1);
-// then the terminal scan (step 2).  The values and the order of operations
-// on each are those of ph_section; fewer values are live at once, which is
-// what a run too long for the architectural registers (N = 128) needs.
+// solution, from that section's terminal values pr, qr and coefficients
+// cp), forms the non-recursive stage and runs the particular recurrence
+// (step 1); then the terminal scan (step 2).  The arithmetic is
+// ph_section's except that the correction comes from its own recurrence
+// rather than the u tables; fewer values are live at once, which is what a
+// run too long for the architectural registers (N = 128) needs.
 // FIRST: the input is the raw signal (nothing to correct).  On exit X holds
 // the section's particular solution with its true last two blocks, and
 // (pr, qr) the correction's inputs for the next pass (or for
@@ -264,12 +265,21 @@ __device__ __forceinline__ void ph_fused_section(T (&X)[N], ctab<T> c, ctab<T> c
   T p1 = shift_r<L>(X[N - 1], xs1), p2 = shift_r<L>(X[N - 2], xs2);
   const T m0 = lane0_mask<T, L>();
   T w1 = m0 * ys1, w2 = m0 * ys2;
-  const ctab<T> u1 = cp + OFF_U1;
-  const ctab<T> u2 = cp + OFF_U1 + N;
+  // the correction e_m = -(u1_m qr + u2_m pr) is the previous section's
+  // homogeneous response to (e_-1, e_-2) = (qr, pr): generated by its own
+  // recurrence instead of read from the u tables, whose scalar loads a lone
+  // wavefront per SIMD would wait on
+  const T pa1 = cp[OFF_A1], pa2 = cp[OFF_A2];
+  T e1 = qr, e2 = pr;
 #pragma unroll
   for (int m = 0; m < N; ++m) {
     T xin = X[m];
-    if (!FIRST && m < N - 2) xin = fma_(-u2[m], pr, fma_(-u1[m], qr, xin));
+    if (!FIRST && m < N - 2) {
+      const T e = fma_(-pa1, e1, -pa2 * e2);
+      e2 = e1;
+      e1 = e;
+      xin += e;
+    }
     T v = B0ONE ? xin : b0 * xin;
     v = fma_(b1, p1, v);
     v = fma_(b2, p2, v);
@@ -294,13 +304,19 @@ __device__ __forceinline__ void ph_fused_section(T (&X)[N], ctab<T> c, ctab<T> c
   xs1 = ys1;
 }
 
-// The last section's homogeneous correction (step 3, eq. PH_forward).
+// The last section's homogeneous correction (step 3, eq. PH_forward), by
+// the same recurrence as in ph_fused_section.
 template <int N, typename T>
 __device__ __forceinline__ void ph_last_correction(T (&X)[N], ctab<T> cp, T pr, T qr) {
-  const ctab<T> u1 = cp + OFF_U1;
-  const ctab<T> u2 = cp + OFF_U1 + N;
+  const T pa1 = cp[OFF_A1], pa2 = cp[OFF_A2];
+  T e1 = qr, e2 = pr;
 #pragma unroll
-  for (int m = 0; m < N - 2; ++m) X[m] = fma_(-u2[m], pr, fma_(-u1[m], qr, X[m]));
+  for (int m = 0; m < N - 2; ++m) {
+    const T e = fma_(-pa1, e1, -pa2 * e2);
+    e2 = e1;
+    e1 = e;
+    X[m] += e;
+  }
 }
 
 // Cyclic reduction (Section VI-C) of one section on one group per row.

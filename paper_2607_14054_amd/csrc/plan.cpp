@@ -156,13 +156,11 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
       q[0] = T.a; q[1] = T.b; q[2] = T.c; q[3] = T.d;
       T = mul(T, T);
     }
-    // AUTO takes the faster solver for the plan's width on MI355X: PH at
-    // N = 4 .. 64 (1-8% ahead, and free of the guard) and with the runs in
-    // the workspace; CR, where the guard allows it, at N = 128 with FP32
-    // I/O, whose runs sit in the accumulation registers (about 24% ahead).
-    // CR is used where asked for and the guard allows it.
-    const bool auto_cr = p.solver_opt == SOS_AUTO && p.N == 128 && p.io_dtype == SOS_F32;
-    p.solver[k] = ((p.solver_opt == SOS_CR || auto_cr) && cr_ok) ? SOS_CR : SOS_PH;
+    // AUTO takes PH: on MI355X it is the faster of the two at every N (1-8%
+    // ahead at N = 4 .. 64, 17% at N = 128, several times with the runs in
+    // the workspace), and it needs no guard.  CR is used where asked for
+    // and the guard allows it.
+    p.solver[k] = (p.solver_opt == SOS_CR && cr_ok) ? SOS_CR : SOS_PH;
   }
   // 4. cascade state s = (y_1[n-2], y_1[n-1], ..., y_K[n-2], y_K[n-1]) in the
   //    scaled domain the kernels use; one step with zero raw input.

@@ -48,7 +48,7 @@ def check(y, x, sos, io, what=""):
 @pytest.mark.parametrize("solver", ["ph", "cr", "auto"])
 def test_wide_groups(solver, N, io):
     """K = 8, r in [0.8, 0.98], several groups per tile plus a ragged tail
-    (AUTO: CR at N = 128 with FP32 I/O, PH otherwise)."""
+    (AUTO is PH)."""
     sos = W.make_sos(8, 0.8, 0.98, 930 + N)
     dt = np.float64 if io == "f64" else np.float32
     n = 9 * 16 * N + 4321
@@ -56,7 +56,7 @@ def test_wide_groups(solver, N, io):
     p = S.Plan(sos, io_dtype=io, compute_dtype="f64", solver=solver, N=N, tile_groups=2)
     info = p.info()
     if solver == "auto":
-        assert info.solver == ["cr" if (N == 128 and io == "f32") else "ph"] * 8
+        assert info.solver == ["ph"] * 8
     # N = 128 with FP32 I/O keeps its lane runs in registers, the other wide
     # plans keep them in the workspace
     assert info.N == N and (p.workspace_size(n) > 0) == (N > 128 or io == "f64")

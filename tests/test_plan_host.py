@@ -159,22 +159,10 @@ def test_cr_guard_falls_back_to_ph(theta, N):
 
 def test_auto_takes_ph():
     sos = W.make_sos(8, 0.8, 0.98, 0)
-    for N in (4, 8, 16, 32, 64, 256, 1024):
-        assert plan(sos, N=N).info().solver == ["ph"] * 8
+    for N in (4, 8, 16, 32, 64, 128, 256, 1024):
+        for io in ("f32", "f64"):
+            assert plan(sos, N=N, io_dtype=io).info().solver == ["ph"] * 8
         assert plan(sos, N=N, solver="cr").info().solver == ["cr"] * 8
-
-
-def test_auto_takes_cr_where_it_is_faster():
-    """N = 128 with FP32 I/O (runs in the accumulation registers): AUTO takes
-    CR where the guard allows it, PH for the guarded sections; with FP64
-    I/O (runs in the workspace) PH."""
-    sos = W.make_sos(8, 0.8, 0.98, 0)
-    assert plan(sos, N=128, io_dtype="f32").info().solver == ["cr"] * 8
-    assert plan(sos, N=128, io_dtype="f64").info().solver == ["ph"] * 8
-    r = 0.9
-    sec = np.array([[1.0, 0.0, 0.0, 1.0, -2 * r * math.cos(math.pi / 2), r * r],
-                    [1.0, 0.0, 0.0, 1.0, -2 * r * math.cos(1.0), r * r]])
-    assert plan(sec, N=128, io_dtype="f32").info().solver == ["ph", "cr"]
 
 
 def test_cr_flush_of_negligible_levels():
