@@ -291,12 +291,20 @@ __device__ __forceinline__ void wide_ph_group(double *__restrict__ S, const TI *
       }
     } else {
       // the previous section's output: its particular solution plus the
-      // homogeneous correction from (pr, qr), true in the last two blocks
-      const ctab<double> u1 = c - stride + OFF_U1;
-      const ctab<double> u2 = c - stride + OFF_U1 + N;
+      // homogeneous correction from (pr, qr), true in the last two blocks.
+      // The correction e_m = -(u1_m qr + u2_m pr) is the previous section's
+      // homogeneous response to (e_-1, e_-2) = (qr, pr), generated by its
+      // own recurrence rather than read from the u tables (scalar loads a
+      // lone wavefront per SIMD would wait on)
+      const ctab<double> cp = c - stride;   // the previous section's table
+      const double pa1 = cp[OFF_A1], pa2 = cp[OFF_A2];
+      double e1 = qr, e2 = pr;
 #pragma unroll 8
       for (int m = 0; m < N - 2; ++m) {
-        const double xin = fma_(-u2[m], pr, fma_(-u1[m], qr, S[64 * m]));
+        const double e = fma_(-pa1, e1, -pa2 * e2);
+        e2 = e1;
+        e1 = e;
+        const double xin = S[64 * m] + e;
         double v = B0ONE ? xin : b0 * xin;
         v = fma_(b1, p1, v);
         v = fma_(b2, p2, v);
@@ -340,15 +348,23 @@ __device__ __forceinline__ void wide_ph_group(double *__restrict__ S, const TI *
     p2 = shift_r(p, xs2);
   }
   if (!live) return;
+  // the last section's correction by the same recurrence
   const ctab<double> cl = ct + (int64_t)(K - 1) * stride;
-  const ctab<double> u1 = cl + OFF_U1;
-  const ctab<double> u2 = cl + OFF_U1 + N;
+  const double pa1 = cl[OFF_A1], pa2 = cl[OFF_A2];
+  double e1 = qr, e2 = pr;
   for (int cc = 0; cc < N / kWideChunk; ++cc) {
     double X[kWideChunk];
 #pragma unroll
     for (int j = 0; j < kWideChunk; ++j) {
       const int m = cc * kWideChunk + j;
-      X[j] = m < N - 2 ? fma_(-u2[m], pr, fma_(-u1[m], qr, S[64 * m])) : S[64 * m];
+      if (m < N - 2) {
+        const double e = fma_(-pa1, e1, -pa2 * e2);
+        e2 = e1;
+        e1 = e;
+        X[j] = S[64 * m] + e;
+      } else {
+        X[j] = S[64 * m];
+      }
     }
     wide_store_chunk<TI>(X, y, g, N, cc, n, full, gain, buf);
   }
