@@ -401,23 +401,25 @@ sos_status sos_filt_batched(sos_batch_t batch, const void *x, void *y, void *wor
  *  - saved outputs: the forward pass stores every section's output (FP64,
  *    K n samples) and the adjoint reads them back;
  *  - recompute: the forward pass stores the cascade state (2K + 2 values)
- *    at every group of 256 samples, and the adjoint recomputes section k's
- *    input from the group's state (K(K-1)/2 + 1 forward section passes per
- *    group).  It also keeps one or two section inputs per group and
- *    recomputes later inputs from them: section K/2's in LDS (FP32 I/O,
- *    4 <= K <= 17) and section K/4's in registers, or section K/2's in
- *    registers otherwise (K >= 4).  At K = 8 that is 13 passes instead of
- *    29.
- * Measured costs per sample on MI355X, in ps: 4.95 + 3.827 K for saved
- * outputs, plus 6.59 - 0.438 K with FP64 I/O; 4.43 + 1.642 K + 0.321 P for
- * recompute with P passes per group, plus 3.92 with FP64 I/O.  So without
- * a flag a plan recomputes for K <= 27 with FP32 I/O and K <= 23 with FP64
- * I/O.
+ *    at every group of 256 samples and, for K >= 8, section K/2's input
+ *    (FP64, n samples); the adjoint recomputes section k's input in each
+ *    group from the nearest kept one below it: the group's input, section
+ *    K/2's, and in each half two more kept on that half's first pass, one
+ *    in LDS (FP32 I/O, 4 <= K <= 17) and one in registers.  At K = 8 that
+ *    is 7 forward section passes per group, where recomputing every input
+ *    from the group's state would take K(K-1)/2 + 1 = 29.
+ * Measured costs per sample on MI355X, in ps, P the passes per group:
+ * saved outputs 4.23 + 3.38 K (FP32 I/O), 7.92 + 3.36 K (FP64 I/O);
+ * recompute 2.34 + 1.75 K + 0.331 P (FP32 I/O), 5.38 + 1.57 K + 0.381 P
+ * (FP64 I/O), times 1.34 or 1.28 where the adjoint's LDS leaves one
+ * wavefront per SIMD.  So without a flag a plan recomputes for K <= 40
+ * with FP32 I/O and K <= 31 with FP64 I/O.
  *
  * sos_backward_workspace_size -- device bytes sos_filt_backward needs for n
  * samples: the saved outputs (K n doubles, padded) or the group states
- * ((2K + 2) doubles per 256 samples), and the per-tile partial sums.  0 for
- * a host-only plan.
+ * ((2K + 2) doubles per 256 samples, and for K >= 8 one double per sample
+ * for the kept section input), and the per-tile partial sums.  0 for a
+ * host-only plan.
  */
 size_t sos_backward_workspace_size(sos_plan_t plan, int64_t n);
 

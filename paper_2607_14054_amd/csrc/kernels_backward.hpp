@@ -17,13 +17,13 @@
 //    (true scale, FP64) to the workspace, and the reversed-time adjoint pass
 //    reads them back one section at a time (about 16K bytes per sample
 //    written and read back);
-//  * recompute: the forward pass writes only the cascade state at every
-//    group boundary (2K + 2 values per group, aligned with the adjoint's
-//    reversed-time groups), and the adjoint pass recomputes the section
-//    inputs of each group from its checkpoint, in registers: section k's
-//    input takes k forward sections, so a group costs K(K-1)/2 + 1 forward
-//    section passes on top of the adjoint's own work, and no per-section
-//    traffic.
+//  * recompute: the forward pass writes the cascade state at every group
+//    boundary (2K + 2 values per group, aligned with the adjoint's
+//    reversed-time groups) and, for K >= 8, one section input u_{K/2}
+//    (8 bytes per sample), and the adjoint pass recomputes the other section inputs of
+//    each group from the nearest kept one, in registers (adj_slots: 7
+//    forward section passes per group at K = 8, where every input from its
+//    checkpoint would take K(K-1)/2 + 1 = 29).
 #pragma once
 
 #include <type_traits>
@@ -153,7 +153,8 @@ struct BwdArgs {
   int64_t sstride;          // elements between saved section outputs
   int64_t shift;            // forward tiles cover [-shift, n)
   int64_t nck;              // recompute mode: group checkpoints
-  int64_t stash;            // recompute mode: stashed section input (0: none)
+  int64_t stash;            // recompute mode: > 0 when the row has an LDS stash
+  int64_t mid_off;          // recompute mode: doubles from the checkpoints to the kept u_H
   int32_t K, stride;
 };
 
@@ -162,7 +163,9 @@ struct BwdArgs {
 // (RC): writes, before each of its groups, the row's boundary values (the
 // state the cascade enters the group with) as checkpoint j = (np - g)/G - 1,
 // the reversed-time group that covers the same samples; the tiles start
-// where the groups line up with the reversed-time ones (shift = -np mod G).
+// where the groups line up with the reversed-time ones (shift = -np mod G);
+// for K >= 8 it also writes the group's input u_H of section H = K/2 to
+// saved + mid_off + j G, element (m, lane) at m L + lane (adj_slots).
 // PH, FP64 arithmetic, tiles as in filter_rows.  STORE_Y: also store the
 // cascade's output y (the forward pass of a training step, which then
 // needs no second pass for the adjoint).  st: 2 + 2K boundary values;
@@ -184,21 +187,27 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
   const int64_t t0 = tile_index * v.tile - v.shift;
   if (!RC) saved += v.shift;
   const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
+  const int H = RC && adj_mid(v.K) > 0 ? adj_mid(v.K) : -1;   // RC: section whose input is kept (adj_slots)
   T X[N];
   for (int64_t it = 0; it < steps; ++it) {
     const int64_t g = t0 - v.warm + it * G;
     const bool full = aligned && __builtin_amdgcn_ballot_w64(!(g >= 0 && g + G <= v.n)) == 0;
     const bool live = it >= warm_groups;
-    if (RC && live) {
-      const int64_t j = (v.np - g) / G - 1;   // g = np mod G: exact
-      if (j >= 0 && j < v.nck)
-        for (int i = row_lane(); i < SE; i += kL) saved[j * SE + i] = st[i];
-    }
+    const int64_t j = (v.np - g) / G - 1;   // g = np mod G: exact
+    const bool keep = RC && live && j >= 0 && j < v.nck;
+    if (keep)
+      for (int i = row_lane(); i < SE; i += kL) saved[j * SE + i] = st[i];
     load_group<N, TI, T>(X, x, g, v.n, full, buf);
     T xs2 = st[0], xs1 = st[1];
     st[0] = last_of_row(X[N - 2]);
     st[1] = last_of_row(X[N - 1]);
     for (int k = 0; k < v.K; ++k) {
+      if (keep && k == H) {
+        // the group's u_H for the adjoint, element (m, lane) at m * L + lane
+        double *mp = saved + v.mid_off + j * G + row_lane();
+#pragma unroll
+        for (int m = 0; m < N; ++m) mp[m * kL] = X[m];
+      }
       ph_section<N, T, B0ONE>(X, ct + (int64_t)k * v.stride, xs2, xs1, st + 2 + 2 * k);
       if (!RC && live)
         store_group<N, double, T>(X, saved + (int64_t)k * v.sstride, g, v.n, full, cb[kBwdRow * k + BW_SCALE],
@@ -224,11 +233,11 @@ __device__ __forceinline__ void save_rows(const TI *__restrict__ x, double *__re
 // in turn (no copies between steps).
 // st: 7K values (2K all-pole output states, then 5K running sums); RC adds
 // the group's checkpoint and a working copy of it (2 + 2K each).
-// RC keeps section inputs from the first pass of each group and
-// recomputes later ones from the nearest kept one below: with v.stash =
-// S > 0, u_S in the row's LDS stash (one FP64 group, forward layout) and
-// u_{S/2} in registers; with no LDS stash, u_{K/2} in registers (K >= 4).
-// u_k then takes k - s passes, s the kept index at or below k.  rowbuf:
+// RC recomputes u_k from the nearest kept input at or below it, in k - s
+// passes (adj_slots): u_H from the forward pass (K >= 8), the group's input
+// u_0, and in each phase two inputs kept on the phase's first pass, one
+// in the row's LDS stash (v.stash > 0: one FP64 group, forward layout) and
+// one in registers.  rowbuf:
 // the row's stage, FP64 in the saved-output mode (which reads FP64
 // groups), else of the I/O type.
 template <int N, typename TI, bool B0ONE, bool RC>
@@ -240,11 +249,10 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   typedef double T;
   TI *buf = reinterpret_cast<TI *>(rowbuf);
   double *dbuf = reinterpret_cast<double *>(rowbuf);
-  const int S = RC ? (int)v.stash : 0;
-  // a stash kept in registers: u_S1 with S1 = S / 2 under the LDS stash
-  // (S >= 4), or S1 = K / 2 where there is no LDS stash (K >= 4); u_k for
-  // S1 < k (< S) then takes k - S1 passes
-  const int S1 = !RC ? 0 : (S >= 4 ? S / 2 : (S == 0 && v.K >= 4 ? v.K / 2 : 0));
+  // RC: the inputs kept per group (adj_slots): u_H in the workspace, and
+  // per phase one input in the LDS stash and one in registers
+  const int H = RC ? adj_mid(v.K) : 0;
+  const bool lds_stash = RC && v.stash > 0;
   constexpr int SRUN = Stage<N, double>::RUN;   // stash doubles per lane (padded)
   double *my_stash = stash + row_lane() * SRUN;
   T *acc = st + 2 * v.K;
@@ -257,64 +265,60 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
   const int64_t pad = v.np - v.n;
   const int64_t warm_groups = v.warm / G, steps = warm_groups + v.tile / G;
   T X[N], A[N], B[N], F[N], R1[N];
-  int64_t g = 0;
+  int64_t g = 0, j = 0;
   bool full = false, live = false;
 
-  // RC: F = the group's forward-time input through sections 0 .. upto-1
-  // (from the checkpoint; capture: leave u_S in the stash on the way); the
-  // chain's input state is left in xs2, xs1
+  // RC: F = u_from (the group's input from the stage, u_H from the
+  // workspace, or a kept input), then through sections from .. upto-1
+  // (capture: keep the phase's inputs on the way); the chain's input state
+  // is left in xs2, xs1
   T xs2 = T(0), xs1 = T(0);
-  auto forward = [&](int upto, bool capture) {
-    stage_to_regs<N, TI, T>(F, buf);
+  auto forward = [&](int from, int upto, const AdjSlots &sl, bool capture) {
+    if (from == 0) {
+      stage_to_regs<N, TI, T>(F, buf);
+    } else if (from == H) {   // (kept indices lie strictly inside a phase, never at H)
+      // u_H of this group (zero past the checkpointed range)
+      const bool in = j < v.nck;
+      const double *mp = saved + v.mid_off + j * G + row_lane();
+#pragma unroll
+      for (int m = 0; m < N; ++m) F[m] = in ? mp[m * kL] : T(0);
+    } else if (from == sl.lds) {
+#pragma unroll
+      for (int m = 0; m < N; m += 2) {
+        const vd2 p = *reinterpret_cast<const vd2 *>(my_stash + m);
+        F[m] = p[0];
+        F[m + 1] = p[1];
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < N; ++m) F[m] = R1[m];
+    }
     for (int i = row_lane(); i < SE; i += kL) cw[i] = ck[i];
     __builtin_amdgcn_wave_barrier();
-    xs2 = cw[0];
-    xs1 = cw[1];
-    for (int q = 0; q < upto; ++q) {
+    xs2 = cw[2 * from];   // section from-1's last two outputs before the group
+    xs1 = cw[2 * from + 1];
+    for (int q = from; q < upto; ++q) {
       ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
-      if (capture && q + 1 == S) {
+      if (capture && q + 1 == sl.lds) {
 #pragma unroll
         for (int m = 0; m < N; m += 2) *reinterpret_cast<vd2 *>(my_stash + m) = vd2{F[m], F[m + 1]};
       }
-      if (capture && q + 1 == S1) {
+      if (capture && q + 1 == sl.regs) {
 #pragma unroll
         for (int m = 0; m < N; ++m) R1[m] = F[m];
       }
     }
   };
-  // RC: F = u_S from the stash through sections S .. upto-1
-  auto forward_from_stash = [&](int upto) {
-#pragma unroll
-    for (int m = 0; m < N; m += 2) {
-      const vd2 p = *reinterpret_cast<const vd2 *>(my_stash + m);
-      F[m] = p[0];
-      F[m + 1] = p[1];
-    }
-    for (int i = row_lane(); i < SE; i += kL) cw[i] = ck[i];
-    __builtin_amdgcn_wave_barrier();
-    xs2 = cw[2 * S];       // section S-1's last two outputs before the group
-    xs1 = cw[2 * S + 1];
-    for (int q = S; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
-  };
-  // RC: F = u_S1 from the registers through sections S1 .. upto-1
-  auto forward_from_regs = [&](int upto) {
-#pragma unroll
-    for (int m = 0; m < N; ++m) F[m] = R1[m];
-    for (int i = row_lane(); i < SE; i += kL) cw[i] = ck[i];
-    __builtin_amdgcn_wave_barrier();
-    xs2 = cw[2 * S1];
-    xs1 = cw[2 * S1 + 1];
-    for (int q = S1; q < upto; ++q) ph_section<N, T, B0ONE>(F, ct + (int64_t)q * v.stride, xs2, xs1, cw + 2 + 2 * q);
-  };
   // U = u_k in reversed time
   auto input_of = [&](int k, T (&U)[N]) {
     if constexpr (RC) {
-      if (S > 0 && k >= S)
-        forward_from_stash(k);
-      else if (S1 > 0 && k >= S1)
-        forward_from_regs(k);
-      else
-        forward(k, false);
+      const AdjSlots sl = adj_slots(v.K, lds_stash, H > 0 && k >= H ? 1 : 0);
+      int from = sl.base;
+      if (k != sl.top) {   // the phase's top keeps the others on its way
+        if (sl.lds && sl.lds <= k && sl.lds > from) from = sl.lds;
+        if (sl.regs && sl.regs <= k && sl.regs > from) from = sl.regs;
+      }
+      forward(from, k, sl, k == sl.top);
       to_reversed<N>(U, F);
       __builtin_amdgcn_wave_barrier();
     } else {
@@ -388,10 +392,11 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
         // forward order (kept in the row's stage until the group's gx is
         // stored) and the state the cascade enters it with
         load_group<N, TI, T>(F, x, v.np - g - G, v.n, full, buf);
-        const int64_t j = g / G;
+        j = g / G;
         for (int i = row_lane(); i < SE; i += kL) ck[i] = j < v.nck ? saved[j * SE + i] : T(0);
         __builtin_amdgcn_wave_barrier();
-        forward(v.K - 1, S > 0 || S1 > 0);
+        const AdjSlots top = adj_slots(v.K, lds_stash, H > 0 ? 1 : 0);
+        forward(top.base, v.K - 1, top, true);
         to_reversed<N>(A, F);
         ph_section<N, T, B0ONE>(F, ct + (int64_t)(v.K - 1) * v.stride, xs2, xs1, cw + 2 + 2 * (v.K - 1));
         to_reversed<N>(B, F);
@@ -456,6 +461,7 @@ __device__ __forceinline__ AdjView adj_view(const BwdArgs &a) {
   v.shift = a.shift;
   v.nck = a.nck;
   v.stash = a.stash;
+  v.mid_off = a.mid_off;
   v.K = a.K;
   v.stride = a.stride;
   return v;
@@ -509,6 +515,7 @@ __device__ __forceinline__ AdjView adj_view(const AdjChan &c) {
   v.shift = c.shift;
   v.nck = c.nck;
   v.stash = c.stash;
+  v.mid_off = c.mid_off;
   v.K = c.K;
   v.stride = c.stride;
   return v;

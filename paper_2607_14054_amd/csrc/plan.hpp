@@ -88,7 +88,6 @@ sos_status attach_adjoint(sos_plan_s &p, const double *sos);
 bool adjoint_recompute(const sos_plan_s &p);
 double adjoint_cost_saved(int K, int io_dtype);
 double adjoint_cost_recompute(int K, int io_dtype, bool stash);
-int adjoint_passes(int K, int S);
 bool adjoint_stash(bool rc, int io_dtype, int kmax);
 // block filtering plans (sosfilt_block.hip)
 sos_status build_block_plan(sos_plan_s &p);

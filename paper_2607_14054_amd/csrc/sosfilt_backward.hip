@@ -43,39 +43,35 @@ sos_status attach_adjoint(sos_plan_s &p, const double *sos) {
   return SOS_OK;
 }
 
-// The recompute mode's stash of u_S, S = K/2: with FP32 I/O (whose stage
-// leaves room for it) and K >= 4, where it fits two workgroups per CU.
-// Without it, u_k takes k passes; with it, k - S for k > S.
+// The recompute mode's LDS stash (one FP64 group per row, adj_slots): with
+// FP32 I/O (whose stage leaves room for it) and K >= 4, where it fits two
+// workgroups per CU.
 bool adjoint_stash(bool rc, int io_dtype, int kmax) {
   return rc && io_dtype == SOS_F32 && kmax >= 4 && AdjLds<kBwdN, float, true>::bytes(kmax, true) <= 80 * 1024;
 }
 
-// The recompute mode's stash indices, as the adjoint kernel derives them:
-// S (LDS, 0 if none) and S1 (registers): S1 = S / 2 under an LDS stash of
-// S >= 4, else K / 2 where there is no LDS stash.  Forward section passes
-// per group: K for u_{K-1} and w_{K-1}, then for k = K-2 .. 1, k minus the
-// largest stash index at or below k.
-int adjoint_passes(int K, int S) {
-  const int S1 = S >= 4 ? S / 2 : (S == 0 && K >= 4 ? K / 2 : 0);
-  int passes = K;
-  for (int k = 1; k <= K - 2; ++k) passes += k - (k >= S && S > 0 ? S : (k >= S1 && S1 > 0 ? S1 : 0));
-  return passes;
-}
-
-// Recompute (group checkpoints) or saved outputs, by measured costs per
-// sample (MI355X, 2^24 samples, ps, fitted over K = 1 .. 32 with relative
-// weights):
-//   saved outputs (about 16K bytes per sample): 4.95 + 3.827 K, plus
-//     6.59 - 0.438 K with FP64 I/O;
-//   recompute: 4.43 + 1.642 K + 0.321 P, plus 3.92 with FP64 I/O, P the
-//     passes above.
-// Recompute is the cheaper up to K = 27 (FP32 I/O) and K = 23 (FP64 I/O).
+// Recompute (group checkpoints) or saved outputs, by measured costs of one
+// sos_filt_backward call per sample (MI355X, 2^24 samples, ps, fitted over
+// K = 1 .. 48 with relative weights; within 11% (FP32 I/O) and 18% (FP64
+// I/O) of every measured point):
+//   saved outputs (about 16K bytes per sample): 4.23 + 3.38 K (FP32 I/O),
+//     7.92 + 3.36 K (FP64 I/O);
+//   recompute, P the forward section passes per group (adj_passes):
+//     2.34 + 1.75 K + 0.331 P (FP32 I/O), 5.38 + 1.57 K + 0.381 P (FP64
+//     I/O), times 1.34 (FP32) or 1.28 (FP64) where the adjoint pass's LDS
+//     leaves one wavefront per SIMD instead of two (K > 43 with FP32 I/O,
+//     K > 31 with FP64 I/O).
+// Recompute is the cheaper up to K = 40 (FP32 I/O) and K = 31 (FP64 I/O).
 double adjoint_cost_saved(int K, int io_dtype) {
-  return 4.95 + 3.827 * K + (io_dtype == SOS_F64 ? 6.59 - 0.438 * K : 0.0);
+  return io_dtype == SOS_F64 ? 7.92 + 3.36 * K : 4.23 + 3.38 * K;
 }
 double adjoint_cost_recompute(int K, int io_dtype, bool stash) {
-  const int S = stash && K >= 4 ? K / 2 : 0;
-  return 4.43 + 1.642 * K + 0.321 * adjoint_passes(K, S) + (io_dtype == SOS_F64 ? 3.92 : 0.0);
+  const bool lds = stash && K >= 4;
+  const double P = adj_passes(K, lds);
+  const bool f64 = io_dtype == SOS_F64;
+  const size_t bytes = f64 ? AdjLds<kBwdN, double, true>::bytes(K, lds) : AdjLds<kBwdN, float, true>::bytes(K, lds);
+  const double c = f64 ? 5.38 + 1.57 * K + 0.381 * P : 2.34 + 1.75 * K + 0.331 * P;
+  return bytes <= 80 * 1024 ? c : c * (f64 ? 1.28 : 1.34);
 }
 
 bool adjoint_recompute(const sos_plan_s &p) {
@@ -137,7 +133,8 @@ Residency adjoint_residency(int io_dtype, bool rc, int K, bool stash) {
 
 struct BwdLayout {
   bool rc;                  // recompute mode
-  int64_t stash;            // recompute mode: S (0: no stash)
+  int64_t stash;            // recompute mode: 1 with the LDS stash, else 0
+  int64_t mid_off;          // recompute mode: doubles from the checkpoints to the kept inputs u_H
   int64_t np, tile, ntiles, sstride;
   int64_t shift, nck;       // forward tiles over [-shift, n); checkpoints (recompute mode)
   int64_t ftile, fntiles;   // the forward pass's tiles
@@ -149,7 +146,7 @@ BwdLayout layout(const sos_plan_s &p, int64_t n) {
   const int64_t V = 16 / (int64_t)esz, G = (int64_t)kBwdN * kL;
   BwdLayout l;
   l.rc = adjoint_recompute(p);
-  l.stash = adjoint_stash(l.rc, p.io_dtype, p.K) ? p.K / 2 : 0;
+  l.stash = adjoint_stash(l.rc, p.io_dtype, p.K) ? 1 : 0;
   l.np = (n + V - 1) / V * V;
   if (p.bwd->tile_groups > 0) {
     l.tile = sos_plan_tile(p.bwd, std::max<int64_t>(l.np, 1));
@@ -163,10 +160,13 @@ BwdLayout layout(const sos_plan_s &p, int64_t n) {
     // forward groups start where the reversed-time groups of [0, np) do
     l.shift = (G - l.np % G) % G;
     l.nck = (l.np + l.shift) / G;
-    l.saved_bytes = (size_t)l.nck * state_elems(p.K) * sizeof(double);
+    // the checkpoints, then (K >= 8) each group's u_H
+    l.mid_off = (l.nck * state_elems(p.K) + 31) / 32 * 32;
+    l.saved_bytes = (size_t)(l.mid_off + (adj_mid(p.K) > 0 ? l.nck * G : 0)) * sizeof(double);
   } else {
     l.shift = 0;
     l.nck = 0;
+    l.mid_off = 0;
     l.saved_bytes = (size_t)p.K * (size_t)l.sstride * sizeof(double);
   }
   l.ftile = sos_plan_tile(p.bwd, std::max<int64_t>(n + l.shift, 1));
@@ -193,6 +193,7 @@ sos_status launch_adjoint(int steps, const sos_plan_s &p, const void *x, void *y
   a.shift = l.shift;
   a.nck = l.nck;
   a.stash = l.stash;
+  a.mid_off = l.mid_off;
   const double *tab = static_cast<const double *>(b.d_table);
   const double *rows = static_cast<const double *>(p.d_bwd_rows);
   if (n > 0) {
@@ -374,9 +375,11 @@ sos_status schedule_batch_adjoint(sos_batch_s &b, const sos_plan_t *plans, int32
     a.first_item = items;
     a.sstride = (b.n[c] + shift[c] + 63) / 64 * 64;
     a.nck = b.adj_rc && b.n[c] ? (np[c] + shift[c]) / G : 0;
-    a.stash = b.adj_stash && plans[c]->K >= 4 ? plans[c]->K / 2 : 0;
+    a.stash = b.adj_stash && plans[c]->K >= 4 ? 1 : 0;
     a.saved_off = ws;
-    ws += b.adj_rc ? (a.nck * state_elems(plans[c]->K) + 31) / 32 * 32 : (int64_t)plans[c]->K * a.sstride;
+    // recompute mode: the checkpoints, then (K >= 8) each group's u_H
+    a.mid_off = b.adj_rc ? (a.nck * state_elems(plans[c]->K) + 31) / 32 * 32 : 0;
+    ws += b.adj_rc ? a.mid_off + (adj_mid(plans[c]->K) > 0 ? a.nck * G : 0) : (int64_t)plans[c]->K * a.sstride;
     a.partial_off = ws;
     ws += (a.ntiles * 5 * plans[c]->K + 31) / 32 * 32;
     a.K = plans[c]->K;

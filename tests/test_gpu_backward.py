@@ -89,19 +89,23 @@ def test_backward_recompute_equals_saved_outputs(io, K):
 
 def test_backward_mode_choice_and_workspace():
     """Automatic mode by the measured cost model: recompute (checkpoints:
-    2K + 2 doubles per 256-sample group) up to K = 27 with FP32 I/O and
-    K = 23 with FP64 I/O, saved outputs above (K doubles per sample); both
-    flags together are rejected."""
+    2K + 2 doubles per 256-sample group, and for K >= 8 one kept section
+    input, a double per sample) up to K = 40 with FP32 I/O and K = 31 with
+    FP64 I/O, saved outputs above (K doubles per sample); both flags
+    together are rejected."""
     n = 2 ** 20
-    for io, cases in (("f32", ((1, True), (8, True), (17, True), (18, True), (27, True), (28, False), (40, False))),
-                      ("f64", ((1, True), (8, True), (23, True), (24, False), (40, False)))):
+    for io, cases in (("f32", ((1, True), (4, True), (8, True), (17, True), (18, True), (40, True), (41, False),
+                               (48, False))),
+                      ("f64", ((1, True), (8, True), (23, True), (31, True), (32, False), (40, False)))):
         for K, rc in cases:
             sos = W.make_sos(K, 0.5, 0.95, 150 + K)
             auto = S.Plan(sos, io_dtype=io).backward_workspace_size(n)
             save = S.Plan(sos, io_dtype=io, adjoint="save").backward_workspace_size(n)
             rec = S.Plan(sos, io_dtype=io, adjoint="recompute").backward_workspace_size(n)
             assert save >= K * n * 8
-            assert rec < (2 * K + 2) * 8 * (n // 256 + 2) + save - K * n * 8
+            kept = 8 * (n + 512) if K >= 8 else 0
+            assert rec < (2 * K + 2) * 8 * (n // 256 + 2) + kept + save - K * n * 8
+            assert (rec >= 8 * n) == (K >= 8)
             assert auto == (rec if rc else save), (io, K)
     import ctypes
     s2 = np.ascontiguousarray(W.make_sos(2, 0.5, 0.9, 1))
@@ -255,20 +259,21 @@ def test_backward_bad_arguments():
 def test_batched_adjoint_mode_choice():
     """One adjoint mode per batch: saved outputs if any plan asks for them,
     else recompute if any asks for it, else the cheaper one over the batch's
-    samples (K = 2 and 4 channels recompute; a batch dominated by K = 32
+    samples (K = 2 and 4 channels recompute; a batch dominated by K = 48
     keeps the outputs, one dominated by K = 4 recomputes).  The workspace
-    shows the mode."""
+    shows the mode: K doubles per sample for saved outputs, group
+    checkpoints and one kept section input (K >= 4) for recompute."""
     def ws(Ks, modes, lengths=(5000, 70001)):
         plans = [S.Plan(W.make_sos(k, 0.5, 0.95, 190 + i), io_dtype="f32", adjoint=m)
                  for i, (k, m) in enumerate(zip(Ks, modes))]
         return S.Batch(plans, list(lengths)).backward_workspace_size()
     saved_bytes = 8 * (2 * 5000 + 4 * 70001)
-    assert ws([2, 4], ["auto", "auto"]) < saved_bytes / 4
+    assert ws([2, 4], ["auto", "auto"]) < saved_bytes / 3
     assert ws([2, 4], ["auto", "save"]) >= saved_bytes
-    assert ws([2, 4], ["recompute", "auto"]) < saved_bytes / 4
+    assert ws([2, 4], ["recompute", "auto"]) < saved_bytes / 3
     assert ws([2, 4], ["recompute", "save"]) >= saved_bytes
-    assert ws([2, 32], ["auto", "auto"]) >= 8 * (2 * 5000 + 32 * 70001)
-    assert ws([32, 4], ["auto", "auto"], (1000, 200000)) < 8 * (32 * 1000 + 4 * 200000) / 4
+    assert ws([2, 48], ["auto", "auto"]) >= 8 * (2 * 5000 + 48 * 70001)
+    assert ws([48, 4], ["auto", "auto"], (1000, 200000)) < 8 * (48 * 1000 + 4 * 200000) / 3
 
 
 @pytest.mark.parametrize("adjoint", ["save", "recompute"])
@@ -414,17 +419,22 @@ def test_adjoint_graph_replays_match_eager(adjoint):
         assert torch.equal(got_x, gx) and torch.equal(got_s, gs), rep
 
 
-@pytest.mark.parametrize("K", [4, 5, 8, 17, 18, 21])
-def test_backward_stash_edges(K):
-    """FP32 I/O recompute with its stashes of section inputs: the LDS stash
-    alone (K = 4, 5), LDS and register stashes (8, and 17, the largest
-    whose LDS stash fits two workgroups per CU), and the register stash
-    alone (18, 21).  Equal to the saved-output mode to rounding and to the
-    oracle adjoint."""
+@pytest.mark.parametrize("io", ["f32", "f64"])
+@pytest.mark.parametrize("K", [4, 5, 6, 7, 8, 9, 12, 16, 17, 18, 21, 32])
+def test_backward_stash_edges(K, io):
+    """Recompute with its kept section inputs: below K = 8 the group's
+    input and two stashes (LDS and registers with FP32 I/O, registers
+    alone with FP64 I/O); from K = 8 also section K/2's input from the
+    forward pass, which splits the sections into two halves with stashes
+    each (odd K: halves of unequal length); the LDS stash up to K = 17 (the
+    largest that fits two workgroups per CU), registers alone above.
+    Equal to the saved-output mode to rounding and to the oracle
+    adjoint."""
     n = 2 ** 17 + 333
+    dt = np.float32 if io == "f32" else np.float64
     sos = W.make_sos(K, 0.5, 0.97, 160 + K)
-    x = W.make_signal(n, 161, np.float32)
-    g = W.grad_seed_signal(n, 161, np.float32)
+    x = W.make_signal(n, 161, dt)
+    g = W.grad_seed_signal(n, 161, dt)
     rx, rs = run_backward(sos, x, g, adjoint="recompute")
     sx, ss = run_backward(sos, x, g, adjoint="save")
     assert oracle.rel_rms(rx, sx) < 1e-6
