@@ -366,8 +366,8 @@ def test_batched_adjoint_shifted_starts_keep_neighbours(io, adjoint):
 def test_batched_adjoint_equals_single_channel_adjoint():
     """Each channel of the batched adjoint equals sos_filt_backward on that
     channel alone to rounding (the tiles differ)."""
-    lengths = [3000, 40000]
-    sos = [W.make_sos(4, 0.5, 0.95, 80), W.make_sos(6, 0.5, 0.95, 81)]
+    lengths = [3000, 40000, 9000]
+    sos = [W.make_sos(4, 0.5, 0.95, 80), W.make_sos(6, 0.5, 0.95, 81), W.make_sos(9, 0.5, 0.95, 83)]
     plans = [S.Plan(s_, io_dtype="f64", compute_dtype="f64", N=32) for s_ in sos]
     b = S.Batch(plans, lengths)
     xs = [W.make_signal(n, 82 + c, np.float64) for c, n in enumerate(lengths)]
@@ -375,26 +375,28 @@ def test_batched_adjoint_equals_single_channel_adjoint():
     xb = torch.from_numpy(np.concatenate(xs)).to(DEV)
     gb = torch.from_numpy(np.concatenate(gs)).to(DEV)
     gx, gsos, first = S.filt_backward_batched(b, xb, gb)
-    for c in range(2):
+    for c in range(3):
         sx, ss = S.filt_backward(plans[c], torch.from_numpy(xs[c]).to(DEV), torch.from_numpy(gs[c]).to(DEV))
         o = b.offsets[c]
         assert oracle.rel_rms(gx[o:o + lengths[c]].cpu().numpy(), sx.cpu().numpy()) < 1e-13
         assert row_err(gsos[first[c]:first[c] + plans[c].K].cpu().numpy(), ss.cpu().numpy()) < 1e-12
 
 
+@pytest.mark.parametrize("K", [6, 10])
 @pytest.mark.parametrize("adjoint", ["save", "recompute"])
-def test_adjoint_graph_replays_match_eager(adjoint):
+def test_adjoint_graph_replays_match_eager(adjoint, K):
     """sos_filt_backward (three kernels, caller workspace) captured in a HIP
-    graph: every replay equals the eager call bit for bit."""
+    graph: every replay equals the eager call bit for bit (K = 10: the
+    recompute forward also keeps section 5's input)."""
     import ctypes
     lib = S.lib()
-    sos = W.make_sos(6, 0.5, 0.95, 92)
+    sos = W.make_sos(K, 0.5, 0.95, 92)
     n = 200003
     p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", N=32, adjoint=adjoint)
     x = torch.from_numpy(W.make_signal(n, 93, np.float32)).to(DEV)
     g = torch.from_numpy(W.grad_seed_signal(n, 93, np.float32)).to(DEV)
     gx = torch.empty_like(x)
-    gs = torch.empty((6, 6), dtype=torch.float64, device=DEV)
+    gs = torch.empty((K, 6), dtype=torch.float64, device=DEV)
     ws = torch.empty(lib.sos_backward_workspace_size(p.handle, n), dtype=torch.uint8, device=DEV)
     vp = ctypes.c_void_p
 
