@@ -212,8 +212,9 @@ sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
 /*
  * Device workspace bytes sos_filt uses for n samples.  For N = 256 .. 1024,
  * and N = 128 with FP64 I/O: the lane runs of every wavefront of the launch
- * (N x 64 doubles per wavefront, one wavefront per SIMD; 512 MB on MI355X
- * at N = 1024), required.  N = 128 with FP32 I/O needs none.  Otherwise
+ * (N x 64 doubles per wavefront, at most one wavefront per SIMD and at
+ * most 256 MB in all, the last-level cache of MI355X: 512 wavefronts at
+ * N = 1024), required.  N = 128 with FP32 I/O needs none.  Otherwise
  * 0 when it carries the state between tiles by the run-in, else the size
  * of the exact carry's buffers.  The exact carry (FP64 arithmetic, solvers AUTO, PH or CR,
  * K <= 16, L = 16, N = 8 .. 64) runs every tile twice, once from zero section states to get its

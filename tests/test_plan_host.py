@@ -412,3 +412,16 @@ def test_wide_plan_tables(N):
     assert p.info().N == N
     assert p.table(S.SOS_TABLE_U1, 0).shape == (N,)
     assert p.table(S.SOS_TABLE_CR_LEVELS, 0).shape == (4 * int(np.log2(N)),)
+
+
+def test_wide_launch_keeps_runs_in_cache():
+    """Wide plans on 2^28 samples: one wavefront per SIMD (1024), capped so
+    that the runs of all wavefronts (N x 64 doubles each) fit the 256 MB
+    last-level cache: 512 wavefronts at N = 1024."""
+    n = 2 ** 28
+    for N, waves in ((256, 1024), (512, 1024), (1024, 512)):
+        p = plan(W.make_sos(8, 0.8, 0.98, 0), N=N)
+        tiles = -(-n // p.tile(n))
+        got = -(-tiles // 4)
+        assert got == waves, (N, got)
+        assert got * N * 64 * 8 <= 256 << 20
