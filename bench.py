@@ -275,14 +275,16 @@ SWEEP_NS = (4, 8, 16, 32, 64, 128, 256, 512, 1024)
 def bench_sweep(S, torch, sos, x, y, n, steps, ref_dev, full):
     """PH and CR at every N of the paper's sweep (8 .. 1024 blocks per lane
     run, and the narrowest width, 4; L = 16) and at L = 32 and 64 for
-    8 <= N <= 64, on the headline signal
+    8 <= N <= 64, and the deferred-correction PH at N = 128 .. 1024 (AUTO's
+    choice where the runs live in the workspace), on the headline signal
     with FP64 arithmetic.  Each point: time per launch, GS/s, its fraction
     of HBM and of the FP64 vector roofline, and (when the oracle's output is
     given) its relative RMS error against the oracle over the whole signal.
-    With `full`, also FP32 arithmetic, the deferred-correction PH and the
-    scalar and block-filtering variants."""
+    With `full`, also FP32 arithmetic, the deferred-correction PH at
+    N = 16 .. 64 and the scalar and block-filtering variants."""
     cases = [(s_, NN, 16, "f64") for s_ in ("ph", "cr") for NN in SWEEP_NS]
     cases += [(s_, NN, L, "f64") for s_ in ("ph", "cr") for L in (32, 64) for NN in (8, 16, 32, 64)]
+    cases += [("phd", NN, 16, "f64") for NN in SWEEP_NS if NN >= 128]
     if full:
         cases += [(s_, NN, 16, "f32") for s_ in ("ph", "cr") for NN in (8, 16, 32, 64)]
         cases += [("phd", NN, 16, "f64") for NN in (16, 32, 64)]

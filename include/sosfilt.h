@@ -65,14 +65,17 @@ typedef enum {
 } sos_dtype;
 
 typedef enum {
-    SOS_AUTO = 0,        /* PH for every section: the faster of the two on MI355X at
-                            every N, and free of the CR guard */
+    SOS_AUTO = 0,        /* PH for every section (the faster of PH and CR on MI355X at
+                            every N, and free of the CR guard); where the lane runs
+                            live in the workspace (N = 256 .. 1024, and N = 128 with
+                            FP64 I/O) and K <= 16, SOS_PH_DEFERRED, which passes
+                            the runs once for all sections (4-5 times faster there) */
     SOS_PH = 1,          /* PH factorisation (Section VI-B) for every section */
     SOS_CR = 2,          /* cyclic reduction (Section VI-C), guard still applies */
     SOS_PH_DEFERRED = 3, /* PH with the homogeneous correction (eq. PH_forward) of all
                             sections deferred to the end of the cascade and applied as
-                            one FP64 matrix-core product; FP64 arithmetic, N >= 16,
-                            K <= 16 */
+                            one FP64 matrix-core product; FP64 arithmetic, N >= 16
+                            (up to 1024, L = 16), K <= 16 */
     SOS_SCALAR = 4,      /* comparison point: scalar filtering (the plain recurrence of
                             Section II, one lane per segment, run-in carry); K <= 16,
                             N ignored */
@@ -117,11 +120,11 @@ typedef struct {
     int32_t solver;         /* sos_solver (default SOS_AUTO) */
     int32_t N;              /* blocks per group: 8, 16, 32 or 64 (0 = 32); also 4 for single
                                signals with SOS_AUTO, SOS_PH or SOS_CR and L = 16; and 128, 256,
-                               512 and 1024 for single signals with SOS_AUTO, SOS_PH or SOS_CR, FP64
-                               arithmetic and L = 16.  At N = 128 with FP32 I/O a lane's run
-                               (128 doubles) stays in registers, one wavefront per SIMD; the
-                               other wide runs do not fit on chip and live in the workspace
-                               (sos_workspace_size) */
+                               512 and 1024 for single signals with SOS_AUTO, SOS_PH, SOS_CR or
+                               SOS_PH_DEFERRED, FP64 arithmetic and L = 16.  At N = 128 with
+                               FP32 I/O a lane's run (128 doubles) stays in registers for PH
+                               and CR, one wavefront per SIMD; the other wide runs do not fit
+                               on chip and live in the workspace (sos_workspace_size) */
     int32_t L;              /* samples per block = lanes per group: 16 (a DPP row), 32 or 64
                                (the whole wavefront); 32 and 64 with SOS_AUTO, SOS_PH and
                                SOS_CR only (0 = 16) */
@@ -211,10 +214,12 @@ sos_status sos_plan_table(sos_plan_t plan, int32_t table, int32_t section,
 
 /*
  * Device workspace bytes sos_filt uses for n samples.  For N = 256 .. 1024,
- * and N = 128 with FP64 I/O: the lane runs of every wavefront of the launch
- * (N x 64 doubles per wavefront, at most one wavefront per SIMD and at
- * most 256 MB in all, the last-level cache of MI355X: 512 wavefronts at
- * N = 1024), required.  N = 128 with FP32 I/O needs none.  Otherwise
+ * and N = 128 with FP64 I/O or SOS_PH_DEFERRED: the lane runs of every
+ * wavefront of the launch (N x 64 doubles per wavefront, at most one
+ * wavefront per SIMD; PH and CR, which pass the runs once per section, also
+ * at most 256 MB in all, the last-level cache of MI355X: 512 wavefronts at
+ * N = 1024), required.  N = 128 with FP32 I/O and PH or CR needs none.
+ * Otherwise
  * 0 when it carries the state between tiles by the run-in, else the size
  * of the exact carry's buffers.  The exact carry (FP64 arithmetic, solvers AUTO, PH or CR,
  * K <= 16, L = 16, N = 8 .. 64) runs every tile twice, once from zero section states to get its

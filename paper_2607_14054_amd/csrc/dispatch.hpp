@@ -98,8 +98,10 @@ inline int64_t model_tile_groups(int64_t groups, int64_t warm_groups, const Resi
   return std::max<int64_t>((groups + rows - 1) / rows, 1);
 }
 
-// residency of a wide plan's kernel (sosfilt_wide.hip)
+// residency of a wide plan's kernel (sosfilt_wide.hip), and whether AUTO
+// takes the deferred PH there
 Residency wide_residency(const sos_plan_s &p);
+bool wide_auto_deferred(int N, int io_dtype, int K);
 
 // a narrow plan's residency and launch (sosfilt_narrow.hip)
 struct FiltArgs;

@@ -159,7 +159,9 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
     // AUTO takes PH: on MI355X it is the faster of the two at every N (1-8%
     // ahead at N = 4 .. 64, 17% at N = 128, several times with the runs in
     // the workspace), and it needs no guard.  CR is used where asked for
-    // and the guard allows it.
+    // and the guard allows it.  (Where the runs live in the workspace, AUTO
+    // plans take the deferred-correction PH instead, chosen at plan
+    // creation.)
     p.solver[k] = (p.solver_opt == SOS_CR && cr_ok) ? SOS_CR : SOS_PH;
   }
   // 4. cascade state s = (y_1[n-2], y_1[n-1], ..., y_K[n-2], y_K[n-1]) in the

@@ -283,9 +283,11 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   if (o.N == 4 && (o.L != kL || !(o.solver == SOS_AUTO || o.solver == SOS_PH || o.solver == SOS_CR)))
     return SOS_E_UNSUPPORTED;
   // N = 128 .. 1024: the lane runs live in the workspace (kernels_wide.hpp),
-  // for PH and CR with FP64 arithmetic and 16-lane rows
+  // for PH, CR and the deferred-correction PH with FP64 arithmetic and
+  // 16-lane rows
   if (o.N > 64 && (o.L != kL || o.compute_dtype != SOS_F64 ||
-                   !(o.solver == SOS_AUTO || o.solver == SOS_PH || o.solver == SOS_CR)))
+                   !(o.solver == SOS_AUTO || o.solver == SOS_PH || o.solver == SOS_CR ||
+                     o.solver == SOS_PH_DEFERRED)))
     return SOS_E_UNSUPPORTED;
   // the block sizes L = 32, 64 exist for PH and CR (the other solvers work
   // on 16-lane rows or single lanes)
@@ -306,7 +308,10 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   p->lgN = __builtin_ctz((unsigned)o.N);
   p->io_dtype = o.io_dtype;
   p->compute_dtype = o.compute_dtype;
-  p->solver_opt = o.solver;
+  p->solver_opt = (o.solver == SOS_AUTO && o.compute_dtype == SOS_F64 && o.L == kL &&
+                   wide_auto_deferred(o.N, o.io_dtype, K))
+                      ? SOS_PH_DEFERRED
+                      : o.solver;
   p->tile_groups = o.tile_groups;
   p->flags = o.flags;
   p->block_slices = !low ? 1 : (slices ? slices : (o.compute_dtype == SOS_F16 ? 3 : 4));
@@ -337,7 +342,7 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
       }
     }
     Residency r;
-    if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED)
+    if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED && !wide_plan(*p))
       r = p->io_dtype == SOS_F32 ? deferred_residency<float>(p->N, p->K, p->b0_factored)
                                  : deferred_residency<double>(p->N, p->K, p->b0_factored);
     else if (st == SOS_OK && p->solver_opt == SOS_SCALAR)

@@ -12,6 +12,7 @@
 
 #include "dispatch.hpp"
 #include "kernels_wide.hpp"
+#include "kernels_wide_deferred.hpp"
 #include "plan.hpp"
 
 using namespace sosf;
@@ -25,7 +26,21 @@ constexpr size_t kLdsPerCu = 160 * 1024;
 // FP32 I/O only: the four wavefronts' staging of a 128-block group in FP64
 // would take 266 KB of LDS
 bool in_registers(const sos_plan_s &p) {
-  return p.N == kRegN && p.io_dtype == SOS_F32 && (size_t)lds_bytes<kRegN, float, double>(p.K) <= kLdsPerCu;
+  return p.N == kRegN && p.io_dtype == SOS_F32 && p.solver_opt != SOS_PH_DEFERRED &&
+         (size_t)lds_bytes<kRegN, float, double>(p.K) <= kLdsPerCu;
+}
+
+bool deferred(const sos_plan_s &p) { return p.solver_opt == SOS_PH_DEFERRED; }
+
+// the deferred kernel's instance: Theta's 4-wide state blocks (as the plan
+// built them, 2, 4 or 8) and b0 factoring
+template <typename TI>
+const void *wide_deferred_kernel_t(const sos_plan_s &p) {
+#define SOSF_DK(B, KB) reinterpret_cast<const void *>(&sos_rows_wide_deferred_kernel<TI, B, KB>)
+  if (p.K <= 4) return p.b0_factored ? SOSF_DK(true, 2) : SOSF_DK(false, 2);
+  if (p.K <= 8) return p.b0_factored ? SOSF_DK(true, 4) : SOSF_DK(false, 4);
+  return p.b0_factored ? SOSF_DK(true, 8) : SOSF_DK(false, 8);
+#undef SOSF_DK
 }
 
 template <typename TI>
@@ -53,11 +68,16 @@ int mix_of(const sos_plan_s &p) {
 }
 
 const void *wide_kernel(const sos_plan_s &p) {
+  if (deferred(p))
+    return p.io_dtype == SOS_F32 ? wide_deferred_kernel_t<float>(p) : wide_deferred_kernel_t<double>(p);
   return p.io_dtype == SOS_F32 ? wide_kernel_t<float>(in_registers(p), p.b0_factored, mix_of(p))
                                : wide_kernel_t<double>(in_registers(p), p.b0_factored, mix_of(p));
 }
 
 size_t wide_lds(const sos_plan_s &p) {
+  if (deferred(p))
+    return p.io_dtype == SOS_F32 ? (size_t)wide_deferred_lds_bytes<float>(p.K)
+                                 : (size_t)wide_deferred_lds_bytes<double>(p.K);
   if (in_registers(p)) return (size_t)lds_bytes<kRegN, float, double>(p.K);   // FP32 I/O only
   return p.io_dtype == SOS_F32 ? (size_t)lds_bytes<kWideChunk, float, double>(p.K)
                                : (size_t)lds_bytes<kWideChunk, double, double>(p.K);
@@ -75,21 +95,36 @@ Residency wide_residency(const sos_plan_s &p) {
 
 // Tiles of a wide plan: every SIMD gets one wavefront (four row tiles).  The
 // workspace holds N x 64 doubles per wavefront of the launch, so the launch
-// keeps to one wavefront per SIMD, and to as many wavefronts as keep the
-// whole workspace within the 256 MB last-level cache that MI355X puts in
-// front of HBM: every section pass reads and writes the runs, and from the
-// cache they move faster than the idle SIMDs cost.  At N = 1024 that is 512
-// wavefronts of 512 KB (measured on 2^28 samples, PH: 29.6 GS/s, against
-// 27.0 with 1024 wavefronts and 512 MB).
+// keeps to one wavefront per SIMD.  PH and CR also keep to as many
+// wavefronts as keep the whole workspace within the 256 MB last-level cache
+// that MI355X puts in front of HBM: every section pass reads and writes the
+// runs, and from the cache they move faster than the idle SIMDs cost.  At
+// N = 1024 that is 512 wavefronts of 512 KB (measured on 2^28 samples, PH:
+// 29.6 GS/s, against 27.0 with 1024 wavefronts and 512 MB).  The deferred
+// PH moves each run once and uses every SIMD (150 GS/s at N = 1024 with
+// 1024 wavefronts, 125 with 512).
 constexpr int64_t kWideCacheBytes = (int64_t)256 << 20;
 
 int64_t wide_tile(const sos_plan_s &p, int64_t n) {
   const int64_t G = (int64_t)p.N * kL;
   if (p.tile_groups > 0) return (int64_t)p.tile_groups * G;
   Residency r;
-  r.simds = (int)std::max<int64_t>(std::min<int64_t>(p.simds, kWideCacheBytes / ((int64_t)p.N * 64 * 8)), 1);
+  r.simds = deferred(p) ? p.simds
+                        : (int)std::max<int64_t>(
+                              std::min<int64_t>(p.simds, kWideCacheBytes / ((int64_t)p.N * 64 * 8)), 1);
   r.waves_per_simd = 1;
   return model_tile_groups((n + G - 1) / G, p.warm / G, r) * G;
+}
+
+// AUTO on a wide plan whose runs live in the workspace takes the deferred
+// PH (K <= 16): one pass over the run for every section against one per
+// section, 4-5 times faster at N = 256 .. 1024 (2^28 samples, K = 8:
+// 242 / 204 / 150 against 48 / 43 / 30 GS/s) and at N = 128 with FP64 I/O
+// (169 against 43 on 2^26).  N = 128 with FP32 I/O keeps PH in registers
+// (321 against 198 on 2^26).
+bool wide_auto_deferred(int N, int io_dtype, int K) {
+  if (N <= 64 || K > 16) return false;
+  return !(N == kRegN && io_dtype == SOS_F32 && (size_t)lds_bytes<kRegN, float, double>(K) <= kLdsPerCu);
 }
 
 size_t wide_workspace(const sos_plan_s &p, int64_t n) {
@@ -132,6 +167,14 @@ sos_status launch_wide(const sos_plan_s &p, const void *x, void *y, int64_t n, v
   a.gain = p.gain;
   a.ws = static_cast<double *>(ws);
   const int64_t blocks = (a.ntiles + per_block - 1) / per_block;
+  if (deferred(p)) {
+    const void *ca = p.d_coupling, *tha = p.d_theta;
+    void *dargs[] = {&xa, &ya, &ta, &ca, &tha, &a};   // addresses of the kernel's six arguments
+    if (hipLaunchKernel(wide_kernel(p), dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), dargs, wide_lds(p),
+                        s) != hipSuccess)
+      return SOS_E_DEVICE;
+    return hipGetLastError() == hipSuccess ? SOS_OK : SOS_E_DEVICE;
+  }
   void *args[] = {&xa, &ya, &ta, &sa, &a};   // addresses of the kernel's five arguments
   if (hipLaunchKernel(wide_kernel(p), dim3((unsigned)blocks), dim3(kWavesPerBlock * 64), args, wide_lds(p), s) !=
       hipSuccess)

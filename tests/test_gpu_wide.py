@@ -2,9 +2,10 @@
 half of the paper's N sweep), against the FP64 oracle through the C ABI.
 N = 128 with FP32 I/O keeps a lane's run in registers (a wavefront alone
 on its SIMD); the other wide plans keep the runs in the caller's workspace,
-all-PH plans with one pass over it per section.  PH and cyclic
-reduction (log2 N = 7 .. 10 levels).  Bars as for N <= 64: FP64 in/out
-within 1e-12 relative RMS (or four times the FP64 oracle's own error
+all-PH plans with one pass over it per section, the deferred-correction PH
+(AUTO's choice there) with one pass for all sections.  PH, cyclic reduction
+(log2 N = 7 .. 10 levels) and the deferred PH.  Bars as for N <= 64: FP64
+in/out within 1e-12 relative RMS (or four times the FP64 oracle's own error
 against its extended-precision twin where that is larger), FP32 in/out
 within 1e-6.
 """
@@ -48,7 +49,8 @@ def check(y, x, sos, io, what=""):
 @pytest.mark.parametrize("solver", ["ph", "cr", "auto"])
 def test_wide_groups(solver, N, io):
     """K = 8, r in [0.8, 0.98], several groups per tile plus a ragged tail
-    (AUTO is PH)."""
+    (AUTO is the deferred PH where the runs live in the workspace, PH in
+    registers)."""
     sos = W.make_sos(8, 0.8, 0.98, 930 + N)
     dt = np.float64 if io == "f64" else np.float32
     n = 9 * 16 * N + 4321
@@ -56,7 +58,7 @@ def test_wide_groups(solver, N, io):
     p = S.Plan(sos, io_dtype=io, compute_dtype="f64", solver=solver, N=N, tile_groups=2)
     info = p.info()
     if solver == "auto":
-        assert info.solver == ["ph"] * 8
+        assert info.solver == ["phd" if (N > 128 or io == "f64") else "ph"] * 8
     # N = 128 with FP32 I/O keeps its lane runs in registers, the other wide
     # plans keep them in the workspace
     assert info.N == N and (p.workspace_size(n) > 0) == (N > 128 or io == "f64")
@@ -137,10 +139,10 @@ def test_wide_static_scratch_matches(N):
 
 @pytest.mark.parametrize("n", [1, 17, 16 * 256 - 1, 16 * 256 + 1, 5 * 16 * 256 + 3, 70001])
 def test_wide_ph_one_pass_ragged(n):
-    """The all-PH wide kernel (one pass over the run per section; AUTO is
-    all PH here) at N = 256, FP32 I/O: lengths below one group and around
-    group boundaries, K = 3 and a b0 = 0 section (b0 kept in the
-    numerator)."""
+    """The all-PH wide kernel (one pass over the run per section) and AUTO's
+    deferred PH (one pass for all sections) at N = 256, FP32 I/O: lengths
+    below one group and around group boundaries, K = 3 and a b0 = 0 section
+    (b0 kept in the numerator)."""
     sos = W.make_sos(3, 0.5, 0.95, 937)
     for b0zero in (False, True):
         s_ = sos.copy()
@@ -212,3 +214,58 @@ def test_wide_and_narrow_graph_replays(N, solver):
         torch.cuda.synchronize()
         assert torch.equal(got, y), (N, rep)
         check(y.cpu().numpy(), x.cpu().numpy(), sos, "f32", "N=%d rep %d" % (N, rep))
+
+
+@pytest.mark.parametrize("io", ["f64", "f32"])
+@pytest.mark.parametrize("K", [1, 3, 8, 13, 16])
+@pytest.mark.parametrize("N", WIDE_N)
+def test_wide_deferred(N, K, io):
+    """The deferred-correction PH on wide groups (all sections zero-state in
+    one pass over the run, the corrections of every section at the end on
+    MFMA): K = 1 .. 16 (the three register classes of its zero-state
+    histories), several groups per tile and a ragged tail."""
+    sos = W.make_sos(K, 0.8, 0.98, 950 + K)
+    dt = np.float64 if io == "f64" else np.float32
+    n = 9 * 16 * N + 4321
+    x = W.make_signal(n, 951, dt)
+    p = S.Plan(sos, io_dtype=io, compute_dtype="f64", solver="phd", N=N, tile_groups=2)
+    assert p.info().N == N and set(p.info().solver) == {"phd"}
+    assert p.workspace_size(n) > 0
+    check(filt(p, x), x, sos, io, "phd N=%d K=%d %s" % (N, K, io))
+
+
+@pytest.mark.parametrize("N", [128, 1024])
+def test_wide_deferred_tiny_ragged_and_impulses(N):
+    """Lengths below one group and around group and tile boundaries, and
+    impulses just before and at them (K = 5)."""
+    sos = W.make_sos(5, 0.9, 0.98, 952)
+    p = S.Plan(sos, io_dtype="f64", compute_dtype="f64", solver="phd", N=N, tile_groups=1)
+    for n in (1, 17, 16 * N - 1, 16 * N + 1, 3 * 16 * N + 5):
+        x = W.make_signal(n, 953, np.float64)
+        check(filt(p, x), x, sos, "f64", "N=%d n=%d" % (N, n))
+    n = 6 * 16 * N + 7
+    x = np.zeros(n)
+    for pos in (N - 1, N, 16 * N - 1, 16 * N, 2 * 16 * N - 2):
+        x[pos] = 1.0
+    check(filt(p, x), x, sos, "f64", "impulses N=%d" % N)
+
+
+def test_wide_deferred_full_size_sampled():
+    """The full headline workload (2^28 float32 samples, K = 8) by the
+    deferred PH at N = 512 in the launch shape the bench sweep times, on
+    windows at the start, across a tile boundary, in the middle and at the
+    end."""
+    c = W.CONFIGS["scale"]
+    sos = W.make_sos(c.K, c.r_lo, c.r_hi, c.seed)
+    x_np = W.make_signal(c.n, c.seed, np.float32)
+    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="phd", N=512)
+    tile, W_run = p.tile(c.n), p.info().warm_samples
+    x = torch.from_numpy(x_np).to(DEV)
+    y = S.filt(p, x)
+    torch.cuda.synchronize()
+    for start in (0, tile - 7, c.n // 2 + 123, c.n - 3000):
+        lo = max(0, start - 4 * W_run)
+        hi = min(start + 3000, c.n)
+        ref = oracle.sosfilt(x_np[lo:hi], sos)[start - lo:]
+        err = oracle.rel_rms(y[start:hi].cpu().numpy(), ref)
+        assert err < 1e-6, (start, err)

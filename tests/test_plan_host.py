@@ -69,9 +69,10 @@ def test_coefficient_validation(bad, code):
     (dict(N=4, L=32), S.SOS_E_UNSUPPORTED), (dict(N=4, solver="scalar"), S.SOS_E_UNSUPPORTED),
     (dict(N=4, solver="phd"), S.SOS_E_UNSUPPORTED),
     (dict(N=2048), S.SOS_E_UNSUPPORTED), (dict(io_dtype="f64", compute_dtype="f32"), S.SOS_E_UNSUPPORTED),
-    # wide groups (N > 64): FP64 arithmetic, 16-lane rows, PH or CR only
+    # wide groups (N > 64): FP64 arithmetic, 16-lane rows, PH, CR or the
+    # deferred-correction PH only
     (dict(N=128, compute_dtype="f32"), S.SOS_E_UNSUPPORTED), (dict(N=256, L=32), S.SOS_E_UNSUPPORTED),
-    (dict(N=512, solver="scalar"), S.SOS_E_UNSUPPORTED),
+    (dict(N=512, solver="scalar"), S.SOS_E_UNSUPPORTED), (dict(N=1024, solver="block"), S.SOS_E_UNSUPPORTED),
 ])
 def test_option_validation(kw, code):
     with pytest.raises(S.SosError) as e:
@@ -158,11 +159,20 @@ def test_cr_guard_falls_back_to_ph(theta, N):
 
 
 def test_auto_takes_ph():
+    """AUTO is PH where the runs stay on chip (N <= 64, and N = 128 with
+    FP32 I/O in registers) and the deferred-correction PH where they live in
+    the workspace (N = 256 .. 1024, N = 128 with FP64 I/O) up to K = 16;
+    PH above K = 16."""
     sos = W.make_sos(8, 0.8, 0.98, 0)
     for N in (4, 8, 16, 32, 64, 128, 256, 1024):
         for io in ("f32", "f64"):
-            assert plan(sos, N=N, io_dtype=io).info().solver == ["ph"] * 8
+            wide_ws = N > 128 or (N == 128 and io == "f64")
+            want = "phd" if wide_ws else "ph"
+            assert plan(sos, N=N, io_dtype=io).info().solver == [want] * 8, (N, io)
         assert plan(sos, N=N, solver="cr").info().solver == ["cr"] * 8
+        assert plan(sos, N=N, solver="ph").info().solver == ["ph"] * 8
+    big = W.make_sos(17, 0.8, 0.98, 0)
+    assert plan(big, N=512).info().solver == ["ph"] * 17
 
 
 def test_cr_flush_of_negligible_levels():
@@ -222,7 +232,7 @@ def test_run_in_truncation_is_negligible_in_the_oracle():
     assert oracle.rel_rms(late, full) < 1e-12
 
 
-@pytest.mark.parametrize("N", [16, 32])
+@pytest.mark.parametrize("N", [16, 32, 256])
 def test_deferred_tables_match_oracle_responses(N):
     """Theta and the coupling blocks of the deferred correction are the
     cascade's responses to unit entry states, computed here by the oracle
@@ -267,6 +277,10 @@ def test_deferred_solver_limits():
         assert e.value.code == S.SOS_E_UNSUPPORTED
     with pytest.raises(S.SosError):
         plan(W.make_sos(17, 0.5, 0.9, 1), solver="phd", N=16)
+    # wide groups: up to K = 16 too
+    assert plan(W.make_sos(16, 0.5, 0.9, 1), solver="phd", N=1024).info().solver == ["phd"] * 16
+    with pytest.raises(S.SosError):
+        plan(W.make_sos(17, 0.5, 0.9, 1), solver="phd", N=256)
     # auto takes cyclic reduction with the guard's PH fallback
     assert set(plan(sos, N=32).info().solver) <= {"cr", "ph"}
     assert set(plan(W.make_sos(17, 0.5, 0.9, 1), N=16).info().solver) <= {"cr", "ph"}
@@ -415,13 +429,19 @@ def test_wide_plan_tables(N):
 
 
 def test_wide_launch_keeps_runs_in_cache():
-    """Wide plans on 2^28 samples: one wavefront per SIMD (1024), capped so
-    that the runs of all wavefronts (N x 64 doubles each) fit the 256 MB
-    last-level cache: 512 wavefronts at N = 1024."""
+    """Wide plans on 2^28 samples: one wavefront per SIMD (1024); PH and CR,
+    which pass the runs once per section, are capped so that the runs of
+    all wavefronts (N x 64 doubles each) fit the 256 MB last-level cache
+    (512 wavefronts at N = 1024); the deferred PH is not."""
     n = 2 ** 28
-    for N, waves in ((256, 1024), (512, 1024), (1024, 512)):
-        p = plan(W.make_sos(8, 0.8, 0.98, 0), N=N)
-        tiles = -(-n // p.tile(n))
-        got = -(-tiles // 4)
-        assert got == waves, (N, got)
-        assert got * N * 64 * 8 <= 256 << 20
+    sos = W.make_sos(8, 0.8, 0.98, 0)
+
+    def waves(p):
+        return -(-(-(-n // p.tile(n))) // 4)
+
+    for N, want in ((256, 1024), (512, 1024), (1024, 512)):
+        for solver in ("ph", "cr"):
+            got = waves(plan(sos, N=N, solver=solver))
+            assert got == want, (N, solver, got)
+            assert got * N * 64 * 8 <= 256 << 20
+        assert waves(plan(sos, N=N, solver="phd")) == 1024
