@@ -120,13 +120,14 @@ def test_wide_needs_its_workspace():
     assert bool((y == 3.0).all())
 
 
+@pytest.mark.parametrize("solver", ["ph", "phd"])
 @pytest.mark.parametrize("N", [256, 1024])
-def test_wide_static_scratch_matches(N):
+def test_wide_static_scratch_matches(N, solver):
     """sos_filt_static on a wide plan whose workspace fits the static
     buffer gives sos_filt's output bit for bit, twice in a row (the second
     call shorter)."""
     sos = W.make_sos(8, 0.8, 0.98, 939)
-    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="ph", N=N)
+    p = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver=solver, N=N)
     for n in (9 * 16 * N + 77, 3 * 16 * N + 5):
         assert 0 < p.workspace_size(n) <= S.SOS_STATIC_SCRATCH_BYTES
         x = torch.from_numpy(W.make_signal(n, 940 + n % 7, np.float32)).to(DEV)
