@@ -82,11 +82,11 @@ __device__ __forceinline__ void load_group_rev(T (&X)[N], const TI *__restrict__
 template <int N, typename TI, typename T>
 __device__ __forceinline__ void store_group_rev(const T (&X)[N], TI *__restrict__ y, int64_t g,
                                                 int64_t n, int64_t np, bool full,
-                                                TI *__restrict__ buf) {
+                                                TI *__restrict__ buf, T gain = T(1)) {
   typedef typename Vec16<TI>::type VT;
   constexpr int V = Stage<N, TI>::V, RUN = Stage<N, TI>::RUN, G = N * kL;
   const int rl = row_lane();
-  regs_to_stage<N, TI, T>(X, T(1), buf);
+  regs_to_stage<N, TI, T>(X, gain, buf);
   __builtin_amdgcn_wave_barrier();
   if (full) {
     VT *dst = reinterpret_cast<VT *>(y + (np - g - G));
@@ -328,15 +328,23 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
         load_group_rev<N, double, T>(U, saved + (int64_t)(k - 1) * v.sstride, g, v.n, v.np, full, dbuf);
     }
   };
-  // the adjoint of section k on X, with U = u_k, W = w_k
+  // the adjoint of section k on X, with U = u_k, W = w_k.  B0ONE: the
+  // transposed FIR runs with b0 factored out (the sub-plan's b1 / b0,
+  // b2 / b0), so X carries lambda and mu divided by pk = the product of b0
+  // over the sections after k; the sums take pk back, and gx the product
+  // over all sections.  (The plan factors b0 only where every product of
+  // the first sections' b0 lies within 2^-400 .. 2^400, so pk, a ratio of
+  // two of them, lies within 2^-800 .. 2^800.)
+  T pk = T(1);
   auto step = [&](int k, const T (&U)[N], const T (&W)[N]) {
     const ctab<T> c = ct + (int64_t)k * v.stride;
     const ctab<T> b = cb + kBwdRow * k;
     T *ys = st + 2 * k;
     const T old2 = ys[0], old1 = ys[1];
-    allpole_ph<N>(X, c, ys);                                 // X = mu_k
+    allpole_ph<N>(X, c, ys);                                 // X = mu_k (/ pk)
     const T m1 = shift_r(X[N - 1], old1), m2 = shift_r(X[N - 2], old2);
-    const T b0 = b[BW_B0], b1 = b[BW_B1], b2 = b[BW_B2];
+    const T b0 = b[BW_B0];
+    const T b1 = B0ONE ? c[OFF_B1] : b[BW_B1], b2 = B0ONE ? c[OFF_B2] : b[BW_B2];
     if (live) {
       T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0), s4 = T(0);
 #pragma unroll
@@ -348,16 +356,22 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
         s2 = fma_(p2, U[m], s2);
         s3 = fma_(p1, W[m], s3);
         s4 = fma_(p2, W[m], s4);
-        X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
+        X[m] = fma_(b2, p2, fma_(b1, p1, B0ONE ? X[m] : b0 * X[m]));
       }
       s0 = row_sum(s0);
       s1 = row_sum(s1);
       s2 = row_sum(s2);
       s3 = row_sum(s3);
       s4 = row_sum(s4);
-      if (RC) {
-        // u_k and w_k in the scaled domain: w_k = scale_k * W, u_k = scale_{k-1} * U
-        const T su = k > 0 ? cb[kBwdRow * (k - 1) + BW_SCALE] : T(1), sw = b[BW_SCALE];
+      if (RC || B0ONE) {
+        // u_k and w_k in the scaled domain (RC): w_k = scale_k * W,
+        // u_k = scale_{k-1} * U; mu_k = pk * X (B0ONE)
+        T su = RC ? (k > 0 ? cb[kBwdRow * (k - 1) + BW_SCALE] : T(1)) : T(1);
+        T sw = RC ? b[BW_SCALE] : T(1);
+        if (B0ONE) {
+          su *= pk;
+          sw *= pk;
+        }
         s0 *= su;
         s1 *= su;
         s2 *= su;
@@ -375,15 +389,17 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
       for (int m = N - 1; m >= 0; --m) {
         const T p1 = m >= 1 ? X[m - 1] : m1;
         const T p2 = m >= 2 ? X[m - 2] : (m == 1 ? m1 : m2);
-        X[m] = fma_(b2, p2, fma_(b1, p1, b0 * X[m]));
+        X[m] = fma_(b2, p2, fma_(b1, p1, B0ONE ? X[m] : b0 * X[m]));
       }
     }
+    if (B0ONE) pk *= b0;
   };
 
   for (int64_t it = 0; it < steps; ++it) {
     g = t0 - v.warm + it * G;
     full = aligned && __builtin_amdgcn_ballot_w64(!(g >= pad && g + G <= v.np)) == 0;
     live = it >= warm_groups;   // uniform per wave
+    pk = T(1);
     load_group_rev<N, TI, T>(X, gy, g, v.n, v.np, full, buf);
     if (live) {
       // A = u_{K-1}, B = w_{K-1}
@@ -414,7 +430,7 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
       if (--k < 0) break;
       if (live) input_of(k, A);
     }
-    if (live) store_group_rev<N, TI, T>(X, gx, g, v.n, v.np, full, buf);
+    if (live) store_group_rev<N, TI, T>(X, gx, g, v.n, v.np, full, buf, pk);
   }
   // one lane per row writes the row's sums (rows past the last tile have none)
   if (row_lane() == 0 && tile_index < v.ntiles)
