@@ -129,9 +129,11 @@ def bench_batch(S, W, torch, dev, args):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=stream):
         S.filt_batched(b, xb, yb, stream=torch.cuda.current_stream())
-    for _ in range(2):
+    # the same clock warm-up as the other legs
+    t_end = time.time() + 0.3
+    while time.time() < t_end:
         g.replay()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
     steps = max(5, args.steps // 2)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -359,17 +361,7 @@ def bench_grad(S, W, torch, dev, args):
             S.filt_batched(b, xb, yb)
             return S.filt_backward_batched(b, xb, gb, gx)
 
-        one_pass()
-        torch.cuda.synchronize()
-        steps = max(3, args.steps // 2)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            one_pass()
-        e1.record()
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / 1e3 / steps
+        sec = timed(torch, one_pass, max(3, args.steps // 2))
         row = {"ms": sec * 1e3, "GSps": total / sec / 1e9}
         label = "%s, %s" % (mode, "two calls" if two_call else "one call")
         log("grad (%s): %d x %d batched forward+backward %.3f ms  %.1f GS/s"
@@ -469,22 +461,9 @@ def bench_grad_long(S, W, torch, dev, args):
     y = torch.empty_like(x)
     out = {"samples": n}
     steps = max(3, args.steps // 4)
-
-    def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / steps
-
     for mode in ("auto", "save"):
         plan = S.Plan(sos, io_dtype="f32", compute_dtype="f64", solver="auto", N=64, adjoint=mode)
-        sec = timed(lambda: S.filt_backward(plan, x, g, gx))
+        sec = timed(torch, lambda: S.filt_backward(plan, x, g, gx), steps)
         log("grad-long (%s): 2^26 backward %.3f ms  %.1f GS/s" % (mode, sec * 1e3, n / sec / 1e9))
         row = {"ms": sec * 1e3, "GSps": n / sec / 1e9}
         if mode == "auto":
@@ -500,7 +479,7 @@ def bench_grad_long(S, W, torch, dev, args):
                 S.filt_backward_stored(plan, x, g, ws, gx)
 
             for name, fn in (("step_one_call", one_call), ("step_two_calls", two_calls)):
-                s2 = timed(fn)
+                s2 = timed(torch, fn, steps)
                 out[name] = {"ms": s2 * 1e3, "GSps": n / s2 / 1e9}
                 log("grad-long (auto): 2^26 training step, %s: %.3f ms  %.1f GS/s"
                     % (name.replace("step_", "").replace("_", " "), s2 * 1e3, n / s2 / 1e9))
@@ -623,12 +602,13 @@ def _check_call(S, plan, x, y, wsb, stream=None):
 
 
 def timed(torch, once, steps):
-    """Seconds per call: a 0.3 s clock warm-up, then `steps` calls between
-    events on the current stream."""
+    """Seconds per call: a 0.3 s clock warm-up (the GPU idles while the host
+    builds plans, and its clock drops), then `steps` calls between events
+    on the current stream."""
     t_end = time.time() + 0.3
     while time.time() < t_end:
         once()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()   # one call in flight: the warm-up ends on time
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -672,16 +652,7 @@ def bench_precision(S, W, torch, dev, args):
 
         def once():
             S.filt_batched(b, xb, yb)
-        once()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(3):
-            once()
-        e1.record()
-        torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / 1e3 / 3
+        sec = timed(torch, once, 3)
         row = {"compute": compute, "solver": solver, "N": N, "GSps": C * n / sec / 1e9}
         if solver == "block" and compute != "f64":
             row["slices"] = plans[0].info().block_slices
