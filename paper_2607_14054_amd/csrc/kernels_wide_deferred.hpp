@@ -17,7 +17,9 @@
 //     response at each block to each entry component), a product with inner
 //     dimension 2K on FP64 16x16x4 MFMA, as for N <= 64, with Theta read
 //     from the plan's device table.
-// The workspace then carries 16 bytes per sample in all, whatever K.
+// The workspace then carries 16 bytes per sample in all, whatever K, less
+// the run's last chunk of 64 blocks, which stays in registers from the
+// first pass to the second (and nothing in the run-in groups).
 #pragma once
 
 #include "kernels_deferred.hpp"
@@ -83,8 +85,10 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_wide_deferred_ke
       st[0] = (e - 2 >= 0 && e - 2 < a.n) ? (T)x[e - 2] : T(0);
       st[1] = (e - 1 >= 0 && e - 1 < a.n) ? (T)x[e - 1] : T(0);
     }
-    for (int cc = 0; cc < N / kWideChunk; ++cc) {
-      T X[kWideChunk];
+    const bool live = it >= warm_groups;   // uniform per wave
+    const int NC = N / kWideChunk;
+    T X[kWideChunk];   // after the pass: the last chunk's zero-state output
+    for (int cc = 0; cc < NC; ++cc) {
       wide_load_chunk<TI>(X, x, g, N, cc, a.n, full, buf);
 #pragma unroll
       for (int k = 0; k < KMAX; ++k) {
@@ -111,8 +115,12 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_wide_deferred_ke
         yh1[k] = w1;
         yh2[k] = w2;
       }
+      // the correction pass reads the zero-state output back, except the
+      // last chunk's, which stays in registers; the run-in needs none
+      if (live && cc + 1 < NC) {
 #pragma unroll
-      for (int j = 0; j < kWideChunk; ++j) S[64 * (cc * kWideChunk + j)] = X[j];
+        for (int j = 0; j < kWideChunk; ++j) S[64 * (cc * kWideChunk + j)] = X[j];
+      }
     }
     // step 2: true terminal values, section by section; RS and the exit
     // state (the next group's entry) from them
@@ -123,7 +131,7 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_wide_deferred_ke
       deferred_terminal(yh2[k], yh1[k], ct + (int64_t)k * a.stride, coup + 2 * k * (k - 1), rs, st, k, D);
     }
     __builtin_amdgcn_wave_barrier();
-    if (it < warm_groups) continue;   // the run-in needs only the exit state
+    if (!live) continue;   // the run-in needs only the exit state
     // step 3: Y = W_K + Theta RS, one 16x16 tile per (row, 16 blocks).  The
     // B operands (RS_r[4b + q][rl]) go to registers before the staging
     // region that holds RS is used for the output again
@@ -136,10 +144,14 @@ __global__ __launch_bounds__(kWavesPerBlock * 64) void sos_rows_wide_deferred_ke
       for (int r = 0; r < kRows; ++r) bv[b][r] = comp < D ? rs[cidx * 64 + 16 * r + rl] : T(0);
     }
     __builtin_amdgcn_wave_barrier();
-    for (int cc = 0; cc < N / kWideChunk; ++cc) {
-      T X[kWideChunk];
+    // the last chunk first, from the registers, then the others from the
+    // workspace
+    for (int ci0 = 0; ci0 < NC; ++ci0) {
+      const int cc = ci0 == 0 ? NC - 1 : ci0 - 1;
+      if (ci0 > 0) {
 #pragma unroll
-      for (int j = 0; j < kWideChunk; ++j) X[j] = S[64 * (cc * kWideChunk + j)];
+        for (int j = 0; j < kWideChunk; ++j) X[j] = S[64 * (cc * kWideChunk + j)];
+      }
 #pragma unroll
       for (int mb = 0; mb < kWideChunk / 16; ++mb) {
         const int64_t mg = (int64_t)cc * (kWideChunk / 16) + mb;   // 16-block of the run
