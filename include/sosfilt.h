@@ -167,8 +167,10 @@ typedef struct {
     int32_t K, N, L;
     int32_t io_dtype, compute_dtype;
     int32_t b0_factored;        /* 1 if the b0 of every section was factored out */
-    int64_t warm_samples;       /* W: samples of run-in that make a tile's carry-in
-                                   state exact to the working precision (a multiple of N*L) */
+    int64_t warm_samples;       /* W: samples of run-in after which the state transition's
+                                   infinity norm is below 2^-64 (FP64 I/O and arithmetic)
+                                   or 2^-40 (otherwise: 2^16 below FP32's unit roundoff);
+                                   a multiple of N*L */
     double gain;                /* product of the b0 applied at the store (1 if not factored) */
     double transition_norm_W;   /* infinity norm of the cascade state transition over W samples */
     int32_t simds;              /* SIMDs of the plan's device (0 for a host-only plan) */

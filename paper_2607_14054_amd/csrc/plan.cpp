@@ -183,8 +183,13 @@ sos_status build_plan_tables(sos_plan_s &p, const double *sos) {
     for (int row = 0; row < D; ++row) p.phi[(size_t)row * D + col] = s2[row];
   }
   // 5. run-in length W: smallest W (to a power-of-two search) with
-  //    ||Phi^W||_inf below eps; rounded up to whole groups.
-  const double eps = (p.compute_dtype == SOS_F64 && p.io_dtype == SOS_F64) ? 0x1p-64 : 0x1p-50;
+  //    ||Phi^W||_inf below eps; rounded up to whole groups.  eps sits 2^16
+  //    below the unit roundoff of what is stored (FP32: 2^-24) and 2^-64
+  //    for FP64 throughout, so a tile's truncated history stays far below
+  //    the rounding of its own outputs.
+  const double eps = p.runin_eps > 0.0                                            ? p.runin_eps
+                     : (p.compute_dtype == SOS_F64 && p.io_dtype == SOS_F64) ? 0x1p-64
+                                                                             : 0x1p-40;
   std::vector<std::vector<double>> pw;   // Phi^(2^j)
   pw.push_back(p.phi);
   int64_t w = 1;

@@ -57,6 +57,7 @@ struct sos_plan_s {
   void *d_theta = nullptr;
   void *d_coupling = nullptr;
   int64_t warm = 0;                // run-in samples, multiple of N*L
+  double runin_eps = 0.0;          // bound on ||Phi^warm||_inf (0: by the I/O type)
   double warm_norm = 0.0;
   int device = -1;
   int simds = 1024, waves_per_simd = 4;   // residency of the plan's kernel (launch-shape model)
@@ -118,5 +119,6 @@ sos_status launch_wide(const sos_plan_s &p, const void *x, void *y, int64_t n, v
 // narrow groups, N = 4 (sosfilt_narrow.hip): single signals on 16-lane rows
 bool narrow_plan(const sos_plan_s &p);
 }
+// runin_eps > 0 replaces the run-in bound that build_plan_tables picks.
 sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
-                       sos_plan_t *out);
+                       sos_plan_t *out, double runin_eps = 0.0);

@@ -265,7 +265,7 @@ sos_status sos_plan(const double *sos, int32_t K, const sos_opts *opts, sos_plan
 // Plan creation; `adjoint` also attaches the adjoint's sub-plan (device
 // plans only).
 sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool adjoint,
-                       sos_plan_t *out) {
+                       sos_plan_t *out, double runin_eps) {
   if (!sos || !out || K < 1 || K > SOS_MAX_SECTIONS) return SOS_E_ARG;
   sos_opts o{SOS_F32, SOS_F64, SOS_AUTO, 0, 0, 0, 0};
   if (opts) o = *opts;
@@ -315,6 +315,7 @@ sos_status create_plan(const double *sos, int32_t K, const sos_opts *opts, bool 
   p->tile_groups = o.tile_groups;
   p->flags = o.flags;
   p->block_slices = !low ? 1 : (slices ? slices : (o.compute_dtype == SOS_F16 ? 3 : 4));
+  p->runin_eps = runin_eps;
   sos_status st = build_plan_tables(*p, sos);
   if (st == SOS_OK && p->solver_opt == SOS_PH_DEFERRED) {
     build_deferred_tables(*p);

@@ -16,11 +16,13 @@ namespace sosf {
 
 // The adjoint kernels run PH with FP64 arithmetic at N = kBwdN on their own
 // tables (same cascade), and read per section the unfactored rows, the
-// forward pass's cumulative b0 scale and the caller's a0.
+// forward pass's cumulative b0 scale and the caller's a0.  The coefficient
+// gradients are sums over the whole signal, so with FP32 I/O their run-ins
+// keep the tighter bound 2^-50 (2^-64 with FP64 I/O, as elsewhere).
 sos_status attach_adjoint(sos_plan_s &p, const double *sos) {
   sos_opts o{p.io_dtype, SOS_F64, SOS_PH, kBwdN, kL, 0, 0};
   sos_plan_t sub = nullptr;
-  sos_status st = create_plan(sos, p.K, &o, false, &sub);
+  sos_status st = create_plan(sos, p.K, &o, false, &sub, p.io_dtype == SOS_F64 ? 0x1p-64 : 0x1p-50);
   if (st != SOS_OK) return st;
   p.bwd = sub;
   std::vector<double> rows((size_t)p.K * kBwdRow, 0.0);

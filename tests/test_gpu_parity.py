@@ -4,7 +4,7 @@ Tolerances (relative RMS against the FP64 oracle, per channel):
 * FP64 in/out, FP64 arithmetic: 1e-12 on the r <= 0.95 draws (the oracle's
   own error against extended precision is ~5e-13 there).
 * FP32 in/out, FP64 arithmetic: 1e-6 (output rounding to FP32 is ~6e-8
-  relative; the run-in truncation is below 2^-50).
+  relative; the run-in truncation is below 2^-40).
 * FP32 in/out, FP32 arithmetic: reported against the plain FP32 sequential
   cascade on the same draw (the FP32 floor), within a factor of 8 of it.
 """

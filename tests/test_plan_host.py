@@ -213,7 +213,8 @@ def test_run_in_length_bounds_transition():
     K = 8
     Phi = p.table(S.SOS_TABLE_TRANSITION).reshape(2 * K, 2 * K)
     P = np.linalg.matrix_power(Phi, info.warm_samples)
-    assert np.max(np.sum(np.abs(P), axis=1)) < 2.0 ** -50
+    # 2^16 below FP32's unit roundoff, the precision of the stored outputs
+    assert np.max(np.sum(np.abs(P), axis=1)) < 2.0 ** -40
     assert info.warm_samples % (32 * 16) == 0
     assert math.isclose(info.transition_norm_W, np.max(np.sum(np.abs(P), axis=1)), rel_tol=1e-6)
     # the run-in is not absurdly long: the slowest pole is 0.98
@@ -221,7 +222,8 @@ def test_run_in_length_bounds_transition():
 
 
 def test_run_in_truncation_is_negligible_in_the_oracle():
-    """Starting a tile from zero state W samples early changes it by < 2^-50."""
+    """Starting a tile from zero state W samples early changes it far below
+    FP32's rounding of the outputs (the truncation is below 2^-40)."""
     sos = W.make_sos(8, 0.8, 0.98, 0)
     info = plan(sos, N=8).info()
     x = W.make_signal(info.warm_samples + 5000, 0)
@@ -229,7 +231,7 @@ def test_run_in_truncation_is_negligible_in_the_oracle():
     # the truncated run starts from zero at sample 0 of a longer signal
     pre = np.concatenate([np.random.default_rng(1).standard_normal(20000), x])
     late = oracle.sosfilt(pre, sos)[20000 + info.warm_samples:]
-    assert oracle.rel_rms(late, full) < 1e-12
+    assert oracle.rel_rms(late, full) < 1e-10
 
 
 @pytest.mark.parametrize("N", [16, 32, 256])
