@@ -33,14 +33,14 @@
 
 namespace sosf {
 
-// Sum over the 16 lanes of a row, in every lane of the row.
+// Sum over the 16 lanes of a row, in the row's last lane.
 template <typename T>
-__device__ __forceinline__ T row_sum(T v) {
+__device__ __forceinline__ T row_total(T v) {
   v += shr<1>(v);
   v += shr<2>(v);
   v += shr<4>(v);
   v += shr<8>(v);
-  return last_of_row(v);
+  return v;
 }
 
 // Reversed-time group I/O.  A signal s of n samples is read as
@@ -117,7 +117,7 @@ __device__ __forceinline__ void store_group_rev(const T (&X)[N], TI *__restrict_
 template <int N>
 __device__ __forceinline__ void to_reversed(double (&R)[N], const double (&F)[N]) {
 #pragma unroll
-  for (int m = 0; m < N; ++m) R[m] = dpp<0x140, false>(F[N - 1 - m]);
+  for (int m = 0; m < N; ++m) R[m] = dpp<0x140, true>(F[N - 1 - m]);
 }
 
 // All-pole part of a section by PH (Section VI-B with b = (1, 0, 0)): X := (1/A) X
@@ -358,32 +358,22 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
         s4 = fma_(p2, W[m], s4);
         X[m] = fma_(b2, p2, fma_(b1, p1, B0ONE ? X[m] : b0 * X[m]));
       }
-      s0 = row_sum(s0);
-      s1 = row_sum(s1);
-      s2 = row_sum(s2);
-      s3 = row_sum(s3);
-      s4 = row_sum(s4);
-      if (RC || B0ONE) {
-        // u_k and w_k in the scaled domain (RC): w_k = scale_k * W,
-        // u_k = scale_{k-1} * U; mu_k = pk * X (B0ONE)
-        T su = RC ? (k > 0 ? cb[kBwdRow * (k - 1) + BW_SCALE] : T(1)) : T(1);
-        T sw = RC ? b[BW_SCALE] : T(1);
-        if (B0ONE) {
-          su *= pk;
-          sw *= pk;
-        }
-        s0 *= su;
-        s1 *= su;
-        s2 *= su;
-        s3 *= sw;
-        s4 *= sw;
+      // the row's totals reach its last lane, which adds them (unscaled:
+      // the scales are the same in every group and are applied once, when
+      // the tile's sums are written)
+      s0 = row_total(s0);
+      s1 = row_total(s1);
+      s2 = row_total(s2);
+      s3 = row_total(s3);
+      s4 = row_total(s4);
+      if (row_lane() == kL - 1) {
+        T *ak = acc + 5 * k;
+        ak[0] += s0;
+        ak[1] += s1;
+        ak[2] += s2;
+        ak[3] += s3;
+        ak[4] += s4;
       }
-      T *ak = acc + 5 * k;
-      ak[0] += s0;
-      ak[1] += s1;
-      ak[2] += s2;
-      ak[3] += s3;
-      ak[4] += s4;
     } else {
 #pragma unroll
       for (int m = N - 1; m >= 0; --m) {
@@ -432,10 +422,25 @@ __device__ __forceinline__ void adjoint_rows(const TI *__restrict__ gy, TI *__re
     }
     if (live) store_group_rev<N, TI, T>(X, gx, g, v.n, v.np, full, buf, pk);
   }
-  // one lane per row writes the row's sums (rows past the last tile have none)
-  if (row_lane() == 0 && tile_index < v.ntiles)
-    for (int k = 0; k < v.K; ++k)
-      for (int j = 0; j < 5; ++j) sums[((int64_t)k * v.ntiles + tile_index) * 5 + j] = acc[5 * k + j];
+  // one lane per row writes the row's sums (rows past the last tile have
+  // none), scaled: in RC u_k and w_k are in the scaled domain (w_k =
+  // scale_k W, u_k = scale_{k-1} U), and with B0ONE mu_k = pk X, pk the
+  // product of b0 over the sections after k
+  __builtin_amdgcn_wave_barrier();
+  if (row_lane() == 0 && tile_index < v.ntiles) {
+    T p = T(1);
+    for (int k = v.K - 1; k >= 0; --k) {
+      T su = RC ? (k > 0 ? cb[kBwdRow * (k - 1) + BW_SCALE] : T(1)) : T(1);
+      T sw = RC ? cb[kBwdRow * k + BW_SCALE] : T(1);
+      if (B0ONE) {
+        su *= p;
+        sw *= p;
+        p *= cb[kBwdRow * k + BW_B0];
+      }
+      double *o = sums + ((int64_t)k * v.ntiles + tile_index) * 5;
+      for (int j = 0; j < 5; ++j) o[j] = acc[5 * k + j] * (j < 3 ? su : sw);
+    }
+  }
 }
 
 // LDS doubles per row of the adjoint pass: all-pole states and sums, and
