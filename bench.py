@@ -361,7 +361,9 @@ def bench_grad(S, W, torch, dev, args):
             S.filt_batched(b, xb, yb)
             return S.filt_backward_batched(b, xb, gb, gx)
 
-        sec = timed(torch, one_pass, max(3, args.steps // 2))
+        # a pass is about 0.3 ms: at least 10 of them, so that the first
+        # launch's start is a small part of the timed region
+        sec = timed(torch, one_pass, max(10, args.steps))
         row = {"ms": sec * 1e3, "GSps": total / sec / 1e9}
         label = "%s, %s" % (mode, "two calls" if two_call else "one call")
         log("grad (%s): %d x %d batched forward+backward %.3f ms  %.1f GS/s"
