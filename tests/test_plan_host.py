@@ -221,6 +221,29 @@ def test_run_in_length_bounds_transition():
     assert info.warm_samples <= 16 * 2048
 
 
+@pytest.mark.parametrize("io,eps", [("f32", 2.0 ** -40), ("f64", 2.0 ** -64)])
+@pytest.mark.parametrize("draw", [(8, 0.8, 0.98, 0), (4, 0.5, 0.95, 7), (2, 0.9, 0.99, 3)])
+def test_run_in_is_the_shortest_whole_group_length_below_its_bound(io, eps, draw):
+    """W is the first multiple of N L at which the transition's infinity
+    norm falls below the bound of the stored type (2^-40 for FP32 output,
+    2^16 below its unit roundoff; 2^-64 for FP64): one group less does not
+    reach it.  The transition is the plan's table, which
+    test_transition_matches_oracle_one_step pins to the oracle."""
+    sos = W.make_sos(*draw)
+    N, L = 32, 16
+    p = plan(sos, N=N, io_dtype=io, compute_dtype="f64")
+    info = p.info()
+    K = sos.shape[0]
+    Phi = p.table(S.SOS_TABLE_TRANSITION).reshape(2 * K, 2 * K)
+    def norm(w):
+        return np.max(np.sum(np.abs(np.linalg.matrix_power(Phi, w)), axis=1))
+    G = N * L
+    W_run = info.warm_samples
+    assert W_run % G == 0 and W_run >= G
+    assert norm(W_run) < eps
+    assert W_run == G or norm(W_run - G) >= eps
+
+
 def test_run_in_truncation_is_negligible_in_the_oracle():
     """Starting a tile from zero state W samples early changes it far below
     FP32's rounding of the outputs (the truncation is below 2^-40)."""
